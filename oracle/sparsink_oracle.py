@@ -1,0 +1,602 @@
+"""CPU FP64 oracle for the Spar-Sink hot path.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import or call this module.  The product (the HIP library and
+its Python binding) never does: it shares no code, headers, tables or constants
+with this file.
+
+Everything here is plain NumPy/SciPy in float64, written from the paper
+(Li, Yu, Li & Meng, "Importance Sparsification for Sinkhorn Algorithm",
+JMLR 2023):
+
+* Sec. 2.1, eq. (rot)/(rot-solu)  -- K = exp(-C/eps), T = diag(u) K diag(v).
+* Alg. 1 (SinkhornOT), Alg. 2 (SinkhornUOT) -- the scaling iterations.
+* Sec. 3.1, eq. (pois)            -- Poisson sparsification, p* = min(1, s p).
+* Sec. 3.1, eq. (pij-ot)          -- p_ij proportional to sqrt(a_i b_j).
+* Sec. 3.2, eq. (pij-uot)         -- p_ij proportional to
+                                     (a_i b_j)^(lam/(2lam+eps)) K_ij^(eps/(2lam+eps)).
+* Alg. 3 / Alg. 4                 -- the Spar-Sink estimates.
+* Sec. 2 notation                 -- KL(x||y) = sum x log(x/y) - x + y, 0 log 0 = 0;
+                                     H(T) = -sum T (log T - 1).
+* Appendix, proof of Thm. 3       -- log-domain form with C~ = C + eps log p*.
+
+Choices where the paper is silent (all restated in the design notes):
+
+* Randomness: the Bernoulli draw for entry (i, j) of problem k is a
+  counter-based hash, Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw,
+  "Parallel random numbers: as easy as 1, 2, 3", SC 2011).  Column j maps to
+  counter word q = (j >> 8) * 64 + (j & 63) and output slot (j >> 6) & 3;
+  the counter is (q, i, k, w) with key (seed lo32, seed hi32).  The slot of
+  the w=0 call gives the high 32 bits, the same slot of the w=1 call the low
+  32 bits; U = (bits >> 11) * 2^-53 and the entry is kept iff U < p*.
+* Sums that decide sampled entries (sum sqrt(a), sum sqrt(b)) are the perfect
+  binary-tree sum over the zero-padded power-of-two vector (adjacent pairs,
+  level by level), so the OT mask is reproducible bit for bit.
+* Cost: c_ij = sum_k (x_ik - y_jk)^2 accumulated in k order, each product
+  and sum separately rounded; with max-normalisation C = c * (1 / max c).
+* UOT sampling weight: q_ij = exp(th*(log a_i + log b_j) - C_ij/(2lam+eps)),
+  th = lam/(2lam+eps) (the identity K^(eps/(2lam+eps)) = exp(-C/(2lam+eps)));
+  Z = sum q; p* = min(1, (s/Z) q).
+* Empty rows/columns (no sampled entry): OT renormalises a and b over the
+  non-empty support ("renormalize"); UOT sets u_i = 0 there ("zero"), the
+  exact optimum of the sparse UOT problem for that row.
+* Stopping: the L1 marginal error of the iterate (u^t, v^t) on the matrix that
+  is iterated; for UOT the fixed-point residual
+  sum |u^(1/th) (K~ v) - a| + sum |v^(1/th) (K~^T u) - b|, th = lam/(lam+eps),
+  summed over rows/columns with at least one entry.  The paper's own rule
+  (change of the scalings) is available as ``stop_rule="delta"``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (Salmon et al., SC 2011), vectorised over counters.
+# --------------------------------------------------------------------------
+_PHILOX_M0 = np.uint64(0xD2511F53)
+_PHILOX_M1 = np.uint64(0xCD9E8D57)
+_PHILOX_W0 = 0x9E3779B9
+_PHILOX_W1 = 0xBB67AE85
+_MASK32 = np.uint64(0xFFFFFFFF)
+_SH32 = np.uint64(32)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32 with 10 rounds.
+
+    ctr: sequence of four uint32 arrays (broadcastable); key: (k0, k1) ints.
+    Returns four uint32 arrays (as uint64 dtype holding 32-bit values).
+    """
+    c0, c1, c2, c3 = (np.asarray(c, dtype=np.uint64) & _MASK32 for c in ctr)
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    for _ in range(10):
+        p0 = _PHILOX_M0 * c0
+        p1 = _PHILOX_M1 * c2
+        hi0, lo0 = p0 >> _SH32, p0 & _MASK32
+        hi1, lo1 = p1 >> _SH32, p1 & _MASK32
+        c0, c1, c2, c3 = hi1 ^ c1 ^ np.uint64(k0), lo1, hi0 ^ c3 ^ np.uint64(k1), lo0
+        k0 = (k0 + _PHILOX_W0) & 0xFFFFFFFF
+        k1 = (k1 + _PHILOX_W1) & 0xFFFFFFFF
+    return c0, c1, c2, c3
+
+
+def uniform_bits(i, j, problem_index: int, seed: int):
+    """64-bit hash word for entries (i, j) (broadcast arrays) of one problem."""
+    i = np.asarray(i, dtype=np.uint64)
+    j = np.asarray(j, dtype=np.uint64)
+    q = (j >> np.uint64(8)) * np.uint64(64) + (j & np.uint64(63))
+    slot = (j >> np.uint64(6)) & np.uint64(3)
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    k = np.uint64(problem_index)
+    hi_words = philox4x32_10((q, i, k, np.uint64(0)), key)
+    lo_words = philox4x32_10((q, i, k, np.uint64(1)), key)
+    hi = np.choose(slot.astype(np.int64), hi_words)
+    lo = np.choose(slot.astype(np.int64), lo_words)
+    return (hi << _SH32) | lo
+
+
+def uniform01(i, j, problem_index: int, seed: int):
+    """U_ij = (bits >> 11) * 2^-53, exactly representable in float64."""
+    bits = uniform_bits(i, j, problem_index, seed)
+    return (bits >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+# --------------------------------------------------------------------------
+# Small helpers with a plain definition.
+# --------------------------------------------------------------------------
+def tree_sum(v) -> float:
+    """Perfect binary-tree sum of v zero-padded to a power of two."""
+    v = np.asarray(v, dtype=np.float64).ravel()
+    if v.size == 0:
+        return 0.0
+    size = 1 << (v.size - 1).bit_length()
+    w = np.zeros(size)
+    w[: v.size] = v
+    while w.size > 1:
+        w = w[0::2] + w[1::2]
+    return float(w[0])
+
+
+def sq_dist(x, y):
+    """c_ij = sum_k (x_ik - y_jk)^2, accumulated in k order (x: (r,d), y: (c,d))."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    diff = x[:, None, 0] - y[None, :, 0]
+    acc = diff * diff
+    for k in range(1, x.shape[1]):
+        diff = x[:, None, k] - y[None, :, k]
+        acc = acc + diff * diff
+    return acc
+
+
+def max_sq_dist(x, y, chunk: int = 512) -> float:
+    out = 0.0
+    for r0 in range(0, x.shape[0], chunk):
+        out = max(out, float(sq_dist(x[r0:r0 + chunk], y).max()))
+    return out
+
+
+def kl_div(x, y) -> float:
+    """KL(x||y) = sum x log(x/y) - x + y with 0 log 0 = 0 (Sec. 2 notation)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    pos = x > 0
+    out = np.zeros_like(x)
+    out[pos] = x[pos] * np.log(x[pos] / y[pos])
+    return float(np.sum(out - x + y))
+
+
+# --------------------------------------------------------------------------
+# Options and the problem's derived scalars.
+# --------------------------------------------------------------------------
+@dataclass
+class Options:
+    eps: float
+    s: float
+    lam: float = math.inf          # inf => balanced OT
+    tol: float = 1e-6
+    max_iter: int = 1000
+    seed: int = 0
+    problem_index: int = 0
+    cost: str = "maxnorm"          # "maxnorm" (C = c / max c) or "plain" (C = c)
+    empty_policy: str = "auto"     # auto | renormalize | zero | fail
+    stop_rule: str = "marginal"    # marginal | delta
+    log_domain: bool = False
+
+
+class EmptySupportError(RuntimeError):
+    pass
+
+
+def is_uot(opt: Options) -> bool:
+    return math.isfinite(opt.lam)
+
+
+def cost_scale(x, y, opt: Options) -> tuple[float, float]:
+    """(cmax, inv_cmax) -- C_ij = c_ij * inv_cmax."""
+    cmax = max_sq_dist(x, y)
+    if opt.cost == "maxnorm":
+        return cmax, (1.0 / cmax if cmax > 0 else 1.0)
+    return cmax, 1.0
+
+
+# --------------------------------------------------------------------------
+# Sampling probabilities: eq. (pij-ot) and eq. (pij-uot), then eq. (pois).
+# --------------------------------------------------------------------------
+@dataclass
+class ProbOT:
+    alpha: np.ndarray   # s * sqrt(a_i) / (S_a S_b)
+    rb: np.ndarray      # sqrt(b_j)
+    s_a: float
+    s_b: float
+
+    def pstar(self, rows, cols):
+        return np.minimum(1.0, self.alpha[rows][:, None] * self.rb[cols][None, :])
+
+
+def ot_probabilities(a, b, s) -> ProbOT:
+    """eq. (pij-ot): p_ij = sqrt(a_i) sqrt(b_j) / (sum_i sqrt(a_i) sum_j sqrt(b_j))."""
+    ra = np.sqrt(np.asarray(a, dtype=np.float64))
+    rb = np.sqrt(np.asarray(b, dtype=np.float64))
+    s_a, s_b = tree_sum(ra), tree_sum(rb)
+    kappa = s / (s_a * s_b)
+    return ProbOT(alpha=kappa * ra, rb=rb, s_a=s_a, s_b=s_b)
+
+
+@dataclass
+class ProbUOT:
+    la: np.ndarray      # th_u * log a_i
+    lb: np.ndarray      # th_u * log b_j
+    inv_tau: float      # 1 / (2 lam + eps)
+    inv_cmax: float
+    z: float            # sum_ij q_ij
+    kappa: float        # s / z
+    x: np.ndarray
+    y: np.ndarray
+
+    def q(self, rows, cols):
+        cij = sq_dist(self.x[rows], self.y[cols]) * self.inv_cmax
+        with np.errstate(invalid="ignore"):
+            e = (self.la[rows][:, None] + self.lb[cols][None, :]) - cij * self.inv_tau
+        return np.exp(e)
+
+    def pstar(self, rows, cols):
+        return np.minimum(1.0, self.kappa * self.q(rows, cols))
+
+
+def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256) -> ProbUOT:
+    """eq. (pij-uot) with K^(eps/(2lam+eps)) written as exp(-C/(2lam+eps))."""
+    tau = 2.0 * lam + eps
+    th = lam / tau
+    with np.errstate(divide="ignore"):
+        la = th * np.log(np.asarray(a, dtype=np.float64))
+        lb = th * np.log(np.asarray(b, dtype=np.float64))
+    pr = ProbUOT(la=la, lb=lb, inv_tau=1.0 / tau, inv_cmax=inv_cmax, z=0.0, kappa=0.0,
+                 x=np.asarray(x, np.float64), y=np.asarray(y, np.float64))
+    cols = np.arange(len(b))
+    rowsums = []
+    for r0 in range(0, len(a), chunk):
+        rows = np.arange(r0, min(len(a), r0 + chunk))
+        rowsums.append(pr.q(rows, cols).sum(axis=1))
+    pr.z = float(np.sum(np.concatenate(rowsums)))
+    pr.kappa = s / pr.z
+    return pr
+
+
+# --------------------------------------------------------------------------
+# eq. (pois): the Poisson mask and the sparse sketch K~ = K / p* (CSR, CSC).
+# --------------------------------------------------------------------------
+@dataclass
+class Sketch:
+    n: int
+    m: int
+    mask: np.ndarray        # (n, ceil(m/64)) uint64, bit j&63 of word j>>6
+    row_ptr: np.ndarray     # (n+1,) int64
+    col_idx: np.ndarray     # (nnz,) int32, ascending within a row
+    val: np.ndarray         # (nnz,) float64, K~_ij = K_ij / p*_ij
+    logval: np.ndarray      # (nnz,) float64, -C_ij/eps - log p*_ij
+    cost: np.ndarray        # (nnz,) float64, C_ij of each kept entry
+    pstar: np.ndarray       # (nnz,) float64
+    col_ptr: np.ndarray     # (m+1,) int64
+    row_idx: np.ndarray     # (nnz,) int32, ascending within a column
+    val_t: np.ndarray       # (nnz,) float64 (CSC order)
+    logval_t: np.ndarray
+    cmax: float
+    inv_cmax: float
+    prob: object
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.size)
+
+    def csr(self):
+        return sp.csr_matrix((self.val, self.col_idx, self.row_ptr), shape=(self.n, self.m))
+
+
+def _pack_mask(keep: np.ndarray) -> np.ndarray:
+    n, m = keep.shape
+    words = (m + 63) // 64
+    padded = np.zeros((n, words * 64), dtype=bool)
+    padded[:, :m] = keep
+    packed = np.packbits(padded, axis=1, bitorder="little")
+    return packed.view("<u8").reshape(n, words).astype(np.uint64)
+
+
+def sample_rows(x, y, a, b, opt: Options, rows, prob=None, inv_cmax=None):
+    """Keep-decisions, p* and U for the given rows over all columns."""
+    m = len(b)
+    cols = np.arange(m)
+    rows = np.asarray(rows)
+    pst = prob.pstar(rows, cols)
+    u01 = uniform01(rows[:, None], cols[None, :], opt.problem_index, opt.seed)
+    keep = u01 < pst
+    return keep, pst, u01
+
+
+def build_sketch(x, y, a, b, opt: Options, chunk: int = 256) -> Sketch:
+    """Alg. 3/4 step 1: construct K~ by eq. (pois) with eq. (pij-ot)/(pij-uot)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    n, m = x.shape[0], y.shape[0]
+    cmax, inv_cmax = cost_scale(x, y, opt)
+    if is_uot(opt):
+        prob = uot_probabilities(a, b, x, y, opt.s, opt.lam, opt.eps, inv_cmax)
+    else:
+        prob = ot_probabilities(a, b, opt.s)
+    masks, ri, ci, pvals = [], [], [], []
+    for r0 in range(0, n, chunk):
+        rows = np.arange(r0, min(n, r0 + chunk))
+        keep, pst, _ = sample_rows(x, y, a, b, opt, rows, prob)
+        masks.append(_pack_mask(keep))
+        rr, cc = np.nonzero(keep)
+        ri.append(rows[rr])
+        ci.append(cc)
+        pvals.append(pst[rr, cc])
+    mask = np.concatenate(masks, axis=0) if masks else np.zeros((0, (m + 63) // 64), np.uint64)
+    ri = np.concatenate(ri).astype(np.int64) if ri else np.zeros(0, np.int64)
+    ci = np.concatenate(ci).astype(np.int64) if ci else np.zeros(0, np.int64)
+    ps = np.concatenate(pvals) if pvals else np.zeros(0)
+    # Entry values: C recomputed from the coordinates, K = exp(-C/eps).
+    cvals = np.array([sq_dist(x[i:i + 1], y[j:j + 1])[0, 0] for i, j in zip(ri, ci)]) \
+        if ri.size < 4096 else _pair_sq_dist(x, y, ri, ci)
+    cost = cvals * inv_cmax
+    kval = np.exp(-(cost / opt.eps))
+    val = kval / ps
+    logval = -(cost / opt.eps) - np.log(ps)
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(ri, minlength=n), out=row_ptr[1:])
+    # CSC: stable order by (column, row).
+    order = np.lexsort((ri, ci))
+    col_ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(ci, minlength=m), out=col_ptr[1:])
+    return Sketch(n=n, m=m, mask=mask, row_ptr=row_ptr, col_idx=ci.astype(np.int32),
+                  val=val, logval=logval, cost=cost, pstar=ps, col_ptr=col_ptr,
+                  row_idx=ri[order].astype(np.int32), val_t=val[order],
+                  logval_t=logval[order], cmax=cmax, inv_cmax=inv_cmax, prob=prob)
+
+
+def _pair_sq_dist(x, y, ri, ci):
+    diff = x[ri, 0] - y[ci, 0]
+    acc = diff * diff
+    for k in range(1, x.shape[1]):
+        diff = x[ri, k] - y[ci, k]
+        acc = acc + diff * diff
+    return acc
+
+
+def expected_nnz_ot(prob: ProbOT) -> tuple[float, float]:
+    """E[nnz] = sum p*, Var[nnz] = sum p*(1-p*) (eq. (pois) and its remark)."""
+    e, v = 0.0, 0.0
+    for i in range(prob.alpha.size):
+        p = np.minimum(1.0, prob.alpha[i] * prob.rb)
+        e += p.sum()
+        v += (p * (1 - p)).sum()
+    return e, v
+
+
+# --------------------------------------------------------------------------
+# Empty rows / columns.
+# --------------------------------------------------------------------------
+def apply_empty_policy(a, b, row_cnt, col_cnt, opt: Options):
+    """Returns (a_eff, b_eff, row_active, col_active, dropped_a, dropped_b)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    ra = row_cnt > 0
+    ca = col_cnt > 0
+    dropped_a = float(a[~ra].sum())
+    dropped_b = float(b[~ca].sum())
+    policy = opt.empty_policy
+    if policy == "auto":
+        policy = "zero" if is_uot(opt) else "renormalize"
+    if policy == "fail" and (np.any(~ra & (a > 0)) or np.any(~ca & (b > 0))):
+        raise EmptySupportError("empty row or column in the sparse sketch")
+    a_eff = np.where(ra, a, 0.0)
+    b_eff = np.where(ca, b, 0.0)
+    if policy == "renormalize":
+        a_eff = a_eff / a_eff.sum()
+        b_eff = b_eff / b_eff.sum()
+    return a_eff, b_eff, ra, ca, dropped_a, dropped_b
+
+
+# --------------------------------------------------------------------------
+# Alg. 1 / Alg. 2 on a given (sparse or dense) kernel.
+# --------------------------------------------------------------------------
+@dataclass
+class SinkhornResult:
+    u: np.ndarray
+    v: np.ndarray
+    iters: int
+    err: float
+    hist: list
+    converged: bool
+
+
+def _quotient(num, den, th):
+    """(num / den)^th on positions with den > 0; 0 elsewhere."""
+    out = np.zeros_like(num)
+    pos = den > 0
+    q = num[pos] / den[pos]
+    out[pos] = q if th == 1.0 else q ** th
+    return out
+
+
+def marginal_error(K, KT, u, v, a, b, th, row_active, col_active) -> float:
+    """Sum |u^(1/th) (K v) - a| + sum |v^(1/th) (K^T u) - b| over active rows/cols."""
+    kv = K @ v
+    ktu = KT @ u
+    up = u if th == 1.0 else u ** (1.0 / th)
+    vp = v if th == 1.0 else v ** (1.0 / th)
+    return float(np.abs(up * kv - a)[row_active].sum() + np.abs(vp * ktu - b)[col_active].sum())
+
+
+def sinkhorn(K, a, b, opt: Options, row_active=None, col_active=None, u0=None, v0=None):
+    """Alg. 1 (th = 1) / Alg. 2 (th = lam/(lam+eps)), linear domain.
+
+    The loop stops at the first t with err(u^t, v^t) <= tol, or at max_iter.
+    """
+    n, m = K.shape
+    th = opt.lam / (opt.lam + opt.eps) if is_uot(opt) else 1.0
+    row_active = np.ones(n, bool) if row_active is None else row_active
+    col_active = np.ones(m, bool) if col_active is None else col_active
+    KT = K.T.tocsr() if sp.issparse(K) else K.T
+    u = np.where(row_active, 1.0, 0.0) if u0 is None else np.array(u0, np.float64)
+    v = np.where(col_active, 1.0, 0.0) if v0 is None else np.array(v0, np.float64)
+    hist = []
+    err = math.inf
+    t = 0
+    for t in range(1, opt.max_iter + 1):
+        u_prev, v_prev = u, v
+        u = _quotient(a, K @ v, th)
+        v = _quotient(b, KT @ u, th)
+        if opt.stop_rule == "delta":
+            err = float(np.abs(u - u_prev).sum() + np.abs(v - v_prev).sum())
+        else:
+            err = marginal_error(K, KT, u, v, a, b, th, row_active, col_active)
+        hist.append(err)
+        if err <= opt.tol:
+            break
+    return SinkhornResult(u=u, v=v, iters=t, err=err, hist=hist, converged=err <= opt.tol)
+
+
+def _segment_logsumexp(z, seg_ptr):
+    """log sum exp over CSR segments; -inf for empty segments."""
+    n = seg_ptr.size - 1
+    out = np.full(n, -np.inf)
+    for i in range(n):
+        lo, hi = seg_ptr[i], seg_ptr[i + 1]
+        if hi > lo:
+            zz = z[lo:hi]
+            mx = zz.max()
+            out[i] = mx + math.log(np.exp(zz - mx).sum())
+    return out
+
+
+def sinkhorn_log(sk: Sketch, a, b, opt: Options, row_active, col_active, f0=None, g0=None):
+    """Log-domain Alg. 1/2 on K~: f = log u, g = log v, with
+    f_i = th (log a_i - log sum_j exp(l_ij + g_j)),  l_ij = log K~_ij
+    (appendix, proof of Thm. 3: the same update with C~ = C + eps log p*)."""
+    th = opt.lam / (opt.lam + opt.eps) if is_uot(opt) else 1.0
+    order_rows = sk.row_idx.astype(np.int64)
+    l_r, c_r = sk.logval, sk.col_idx.astype(np.int64)
+    l_c = sk.logval_t
+    with np.errstate(divide="ignore"):
+        la, lb = np.log(a), np.log(b)
+    f = np.zeros(sk.n) if f0 is None else np.array(f0, np.float64)
+    g = np.zeros(sk.m) if g0 is None else np.array(g0, np.float64)
+    f[~row_active] = -np.inf
+    g[~col_active] = -np.inf
+    hist = []
+    err = math.inf
+    t = 0
+    for t in range(1, opt.max_iter + 1):
+        f_prev, g_prev = f, g
+        lse_r = _segment_logsumexp(l_r + g[c_r], sk.row_ptr)
+        with np.errstate(invalid="ignore"):
+            f = np.where(row_active, th * (la - lse_r), -np.inf)
+        lse_c = _segment_logsumexp(l_c + f[order_rows], sk.col_ptr)
+        with np.errstate(invalid="ignore"):
+            g = np.where(col_active, th * (lb - lse_c), -np.inf)
+        if opt.stop_rule == "delta":
+            err = float(np.abs(np.exp(f) - np.exp(f_prev)).sum()
+                        + np.abs(np.exp(g) - np.exp(g_prev)).sum())
+        else:
+            lse_r2 = _segment_logsumexp(l_r + g[c_r], sk.row_ptr)
+            lse_c2 = _segment_logsumexp(l_c + f[order_rows], sk.col_ptr)
+            r_row = np.abs(np.exp(f / th + lse_r2) - a)[row_active].sum()
+            r_col = np.abs(np.exp(g / th + lse_c2) - b)[col_active].sum()
+            err = float(r_row + r_col)
+        hist.append(err)
+        if err <= opt.tol:
+            break
+    return SinkhornResult(u=np.exp(f), v=np.exp(g), iters=t, err=err, hist=hist,
+                          converged=err <= opt.tol)
+
+
+# --------------------------------------------------------------------------
+# Alg. 3 / Alg. 4 output: <T~, C> - eps H(T~) (+ lam KL terms for UOT).
+# --------------------------------------------------------------------------
+@dataclass
+class Estimate:
+    estimate: float
+    transport: float
+    neg_entropy: float       # sum T (log T - 1) = -H(T)
+    kl_a: float
+    kl_b: float
+    sparse_objective: float  # <T~, C~> - eps H(T~) (+ lam KLs), C~ = -eps log K~
+
+
+def estimate_from_entries(rows, cols, t, cost, u, v, a, b, opt: Options) -> Estimate:
+    pos = t > 0
+    transport = float(np.sum(t * cost))
+    neg_ent = float(np.sum(t[pos] * (np.log(t[pos]) - 1.0)))
+    row_sum = np.bincount(rows, weights=t, minlength=len(a))
+    col_sum = np.bincount(cols, weights=t, minlength=len(b))
+    with np.errstate(divide="ignore"):
+        lu, lv = np.log(u), np.log(v)
+    sparse_obj = opt.eps * float(np.sum(t[pos] * (lu[rows[pos]] + lv[cols[pos]] - 1.0)))
+    est = transport + opt.eps * neg_ent
+    kl_a = kl_b = 0.0
+    if is_uot(opt):
+        kl_a = kl_div(row_sum, a)
+        kl_b = kl_div(col_sum, b)
+        est += opt.lam * (kl_a + kl_b)
+        sparse_obj += opt.lam * (kl_a + kl_b)
+    return Estimate(est, transport, neg_ent, kl_a, kl_b, sparse_obj)
+
+
+# --------------------------------------------------------------------------
+# Entry points mirroring the library's calls.
+# --------------------------------------------------------------------------
+@dataclass
+class SolveResult:
+    estimate: Estimate
+    sinkhorn: SinkhornResult
+    sketch: Sketch | None
+    nnz: int
+    empty_rows: int
+    empty_cols: int
+    dropped_a: float
+    dropped_b: float
+    cmax: float
+
+
+def spar_sink(x, y, a, b, opt: Options) -> SolveResult:
+    """Alg. 3 (OT, lam = inf) and Alg. 4 (UOT)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    sk = build_sketch(x, y, a, b, opt)
+    row_cnt = np.diff(sk.row_ptr)
+    col_cnt = np.diff(sk.col_ptr)
+    a_eff, b_eff, ra, ca, da, db = apply_empty_policy(a, b, row_cnt, col_cnt, opt)
+    rows = np.repeat(np.arange(sk.n), row_cnt)
+    cols = sk.col_idx.astype(np.int64)
+    if opt.log_domain:
+        res = sinkhorn_log(sk, a_eff, b_eff, opt, ra, ca)
+        with np.errstate(divide="ignore"):
+            lu, lv = np.log(res.u), np.log(res.v)
+        t = np.exp(lu[rows] + sk.logval + lv[cols])
+    else:
+        res = sinkhorn(sk.csr(), a_eff, b_eff, opt, ra, ca)
+        t = res.u[rows] * sk.val * res.v[cols]
+    est = estimate_from_entries(rows, cols, t, sk.cost, res.u, res.v, a, b, opt)
+    return SolveResult(est, res, sk, sk.nnz, int(np.sum(~ra & (a > 0))),
+                       int(np.sum(~ca & (b > 0))), da, db, sk.cmax)
+
+
+def dense_sinkhorn(x, y, a, b, opt: Options) -> SolveResult:
+    """Alg. 1 / Alg. 2 on the full kernel K = exp(-C/eps)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    cmax, inv_cmax = cost_scale(x, y, opt)
+    cost = sq_dist(x, y) * inv_cmax
+    K = np.exp(-(cost / opt.eps))
+    n, m = K.shape
+    if opt.log_domain:
+        sk = _dense_as_sketch(cost, opt, cmax, inv_cmax)
+        res = sinkhorn_log(sk, a, b, opt, np.ones(n, bool), np.ones(m, bool))
+        with np.errstate(divide="ignore"):
+            t = np.exp(np.log(res.u)[:, None] - cost / opt.eps + np.log(res.v)[None, :])
+    else:
+        res = sinkhorn(K, a, b, opt)
+        t = res.u[:, None] * K * res.v[None, :]
+    rows = np.repeat(np.arange(n), m)
+    cols = np.tile(np.arange(m), n)
+    est = estimate_from_entries(rows, cols, t.ravel(), cost.ravel(), res.u, res.v, a, b, opt)
+    return SolveResult(est, res, None, n * m, 0, 0, 0.0, 0.0, cmax)
+
+
+def _dense_as_sketch(cost, opt, cmax, inv_cmax) -> Sketch:
+    n, m = cost.shape
+    logval = -(cost / opt.eps)
+    row_ptr = np.arange(0, n * m + 1, m, dtype=np.int64)
+    col_ptr = np.arange(0, n * m + 1, n, dtype=np.int64)
+    return Sketch(n=n, m=m, mask=np.zeros((n, 0), np.uint64), row_ptr=row_ptr,
+                  col_idx=np.tile(np.arange(m), n).astype(np.int32), val=np.exp(logval).ravel(),
+                  logval=logval.ravel(), cost=cost.ravel(), pstar=np.ones(n * m),
+                  col_ptr=col_ptr, row_idx=np.tile(np.arange(n), m).astype(np.int32),
+                  val_t=np.exp(logval.T).ravel(), logval_t=logval.T.ravel(), cmax=cmax,
+                  inv_cmax=inv_cmax, prob=None)
