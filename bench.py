@@ -1,0 +1,188 @@
+"""Benchmark: seconds to a 1e-6 marginal error, Spar-Sink vs dense Sinkhorn, and
+the HBM bandwidth of the sparse iteration kernel, on one MI355X.
+
+Workload (default): UOT between n = m = 65536 points in R^3, x from an equal
+mixture of three isotropic Gaussians, y = x + N(0, 0.1^2 I), masses U(0,1)
+scaled to totals 1.0 and 1.3, lambda = 1, eps = 0.05, normalised squared
+Euclidean cost, s = 8 n ln n, log-domain FP32 iteration with FP64 potentials,
+stop at L1 fixed-point residual <= 1e-6.
+
+A step is one whole Spar-Sink solve (probabilities, hash mask, CSR/CSC,
+Sinkhorn loop to tolerance, estimate) with the inputs already in HBM.  The
+dense baseline (same stop rule and tolerance, K recomputed on the fly) is
+timed on the same GPU.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "s to 1e-6 marginal err, Spar-Sink vs dense Sinkhorn; SpMV HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--eps", type=float, default=0.05)
+    ap.add_argument("--precision", default="f32_log")
+    ap.add_argument("--dense-precision", default="auto")
+    ap.add_argument("--dense-runs", type=int, default=1)
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--timing-iters", type=int, default=64)
+    return ap.parse_args()
+
+
+def iteration_bytes_per_launch(precision: str, nnz: int, n: int, m: int) -> float:
+    """Algorithmic HBM bytes of one iteration-kernel launch, averaged over the
+    u-launch (CSR, n lines) and the v-launch (CSC, m lines).
+
+    Per stored entry: value + int32 index.  Per line: int64 offset, FP64 mass,
+    the previous and the new scaling.  The gathered vector of the other side
+    is counted once (it stays in L2)."""
+    ev = 8 if precision == "f64" else 4          # stored value
+    ys = 4 if precision == "f32" else 8          # stored scaling / potential
+    per_line = 8 + 8 + 2 * ys
+    u = nnz * (ev + 4) + n * per_line + 8 + m * ys
+    v = nnz * (ev + 4) + m * per_line + 8 + n * ys
+    return (u + v) / 2.0
+
+
+def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
+    """The FP64 oracle timed on a bounded sample of the same workload."""
+    import numpy as np
+
+    from oracle import sparsink_oracle as O
+    from paper_2306_06581_amd import workloads as W
+
+    t_all = time.perf_counter()
+    R = 32
+    opt = O.Options(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, log_domain=precision_log)
+    _, inv_cmax = O.cost_scale(p.x[:R], p.y, opt)  # cost scan of R rows, the rest scaled below
+    t0 = time.perf_counter()
+    O.max_sq_dist(p.x[:R], p.y)
+    t_cmax_rows = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if math.isfinite(p.lam):
+        prob = O.uot_probabilities(p.a[:R], p.b, p.x[:R], p.y, p.s, p.lam, p.eps, inv_cmax)
+    else:
+        prob = O.ot_probabilities(p.a, p.b, p.s)
+    O.sample_rows(p.x, p.y, p.a, p.b, opt, np.arange(R), prob)
+    t_sample_rows = time.perf_counter() - t0
+    t_sample = (t_cmax_rows + t_sample_rows) * (p.n / R)
+    # iteration cost measured on the same generator at n_small, scaled by size
+    ns = 4096
+    q = W.uot_mix3(ns, seed=p.seed, eps=p.eps) if math.isfinite(p.lam) else W.ot_t5_d10(ns)
+    it = 10
+    optq = O.Options(eps=q.eps, s=q.s, lam=q.lam, seed=q.seed, tol=0.0, max_iter=it,
+                     log_domain=precision_log)
+    sk = O.build_sketch(q.x, q.y, q.a, q.b, optq)
+    a_eff, b_eff, ra, ca, _, _ = O.apply_empty_policy(q.a, q.b, np.diff(sk.row_ptr),
+                                                      np.diff(sk.col_ptr), optq)
+    t0 = time.perf_counter()
+    if precision_log:
+        O.sinkhorn_log(sk, a_eff, b_eff, optq, ra, ca)
+    else:
+        O.sinkhorn(sk.csr(), a_eff, b_eff, optq, ra, ca)
+    t_it_small = (time.perf_counter() - t0) / it
+    nnz_full = p.s
+    scale = (nnz_full + p.n + p.m) / (sk.nnz + q.n + q.m)
+    t_iter = t_it_small * scale * gpu_iters
+    total = t_sample + t_iter
+    return {"value": total, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle cost scan + p* + hash mask on {R} of {p.n} rows (x{p.n // R}); "
+                       f"{it} oracle iterations at n={ns} scaled by (nnz+n+m) to the full size "
+                       f"x {gpu_iters} iterations; measured {time.perf_counter() - t_all:.1f} s"),
+            "parts_s": {"sample": t_sample, "iterations": t_iter}}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2306_06581_amd import api as A
+    from paper_2306_06581_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    p = W.uot_mix3(args.n, seed=0, eps=args.eps)
+    prob = A.Problem(p.x, p.y, p.a, p.b)
+    kw = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, tol=1e-6, max_iter=5000,
+              precision=args.precision)
+
+    for _ in range(args.warmup):
+        A.spar_sink_uot(prob, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [A.spar_sink_uot(prob, **kw) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    r = results[-1]
+    for rr in results:
+        if rr.status != 0:
+            raise SystemExit(f"Spar-Sink did not converge: status {rr.status}")
+
+    # dominant kernel: the sparse iteration kernel, timed with HIP events
+    ms_launch = A.ss_time_iterations(prob, args.timing_iters, eps=p.eps, s=p.s, lam=p.lam,
+                                     seed=p.seed, precision=args.precision)
+    bytes_launch = iteration_bytes_per_launch(args.precision, r.nnz, p.n, p.m)
+    gbps = bytes_launch / (ms_launch * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC, "value": ms_step / 1e3, "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"uot_mix3 n=m={p.n} d=3 lambda=1 eps={p.eps:g} s=8nlnn "
+                               f"tol=1e-6 {args.precision}",
+                   "n": p.n, "m": p.m, "d": 3, "eps": p.eps, "lambda": p.lam, "s": p.s,
+                   "tol": 1e-6},
+        "iters": r.iters, "nnz": r.nnz, "estimate": r.estimate, "marginal_err": r.marginal_err,
+        "stage_ms": {"prep": r.t_prep_ms, "sample": r.t_sample_ms, "iterate": r.t_iter_ms,
+                     "objective": r.t_obj_ms},
+        "spmv_GBps": gbps,
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_iterate (sparse iteration, log-domain)",
+                     "ms_per_launch": ms_launch, "bytes_per_launch": bytes_launch},
+    }
+    if not args.no_dense:
+        dp = args.dense_precision
+        if dp == "auto":
+            dp = "f32" if p.eps >= 0.03 else "f32_log"
+        dkw = dict(kw, precision=dp)
+        dres = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.dense_runs):
+            dres.append(A.dense_sinkhorn(prob, **dkw))
+        torch.cuda.synchronize()
+        dms = (time.perf_counter() - t0) * 1e3 / args.dense_runs
+        d = dres[-1]
+        out["dense_s"] = dms / 1e3
+        out["dense_iters"] = d.iters
+        out["dense_status"] = d.status
+        out["dense_precision"] = dp
+        out["dense_estimate"] = d.estimate
+        out["speedup_vs_dense"] = dms / ms_step
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, r.iters, args.precision == "f32_log")
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

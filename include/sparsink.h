@@ -1,0 +1,196 @@
+/*
+ * sparsink.h -- C ABI of the MI355X (gfx950) Spar-Sink library.
+ *
+ * Spar-Sink (Li, Yu, Li & Meng, "Importance Sparsification for Sinkhorn
+ * Algorithm", JMLR 24, 2023) approximates entropic OT (eq. (rot)) and entropic
+ * UOT (eq. (ruot)) by running the Sinkhorn scaling loop (Alg. 1 / Alg. 2) on a
+ * Poisson-sparsified kernel K~ (eq. (pois)) drawn with the importance
+ * probabilities of eq. (pij-ot) / eq. (pij-uot), then reporting the estimate of
+ * Alg. 3 / Alg. 4.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers documented "device" must point to memory the current HIP device
+ *   can read (hipMalloc'd or torch CUDA tensors).  Pointers documented "host"
+ *   are ordinary process memory.  The library never allocates or frees caller
+ *   memory: every scratch byte comes from the caller's workspace `ws`, whose
+ *   size is given by ss_workspace_size() for the same problem and options.
+ * - All device work is enqueued on `stream` (a hipStream_t; NULL is the null
+ *   stream).  Calls that fill a host ss_result synchronise that stream before
+ *   returning.  Calls with disjoint workspaces may run concurrently from
+ *   different host threads.
+ * - Return value: 0 = success; > 0 = warning, outputs valid; < 0 = error,
+ *   outputs undefined.  No C++ exception crosses this boundary.
+ *   ss_status_string() names every code; ss_last_error() returns a text
+ *   description of the most recent error on the calling thread.
+ * - Inputs are FP64 in every precision mode, so for a given seed the sampled
+ *   sparsity pattern is the same in every precision.
+ */
+#ifndef SPARSINK_H
+#define SPARSINK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+enum {
+    SS_OK = 0,
+    SS_NOT_CONVERGED = 1,     /* max_iter reached with err > tol; result valid     */
+    SS_E_INVALID_ARG = -1,    /* bad size, parameter, or a null required pointer   */
+    SS_E_HIP = -2,            /* a HIP runtime call failed                         */
+    SS_E_WORKSPACE = -3,      /* ws is NULL, misaligned (256 B) or too small       */
+    SS_E_NONFINITE = -4,      /* NaN/Inf appeared in the scalings                  */
+    SS_E_EMPTY = -5,          /* empty row/column with empty_policy = FAIL         */
+    SS_E_CAPACITY = -6        /* sampled nnz exceeded the workspace capacity       */
+};
+
+enum { SS_F64 = 0, SS_F32 = 1, SS_F32_LOG = 2 };                 /* ss_options.precision */
+enum { SS_COST_SQEUCLID_MAXNORM = 0, SS_COST_SQEUCLID = 1 };      /* ss_options.cost      */
+enum { SS_STOP_MARGINAL_L1 = 0, SS_STOP_SCALING_DELTA_L1 = 1 };   /* ss_options.stop_rule */
+enum { SS_EMPTY_AUTO = 0, SS_EMPTY_RENORMALIZE = 1, SS_EMPTY_ZERO = 2, SS_EMPTY_FAIL = 3 };
+
+/* ---------------------------------------------------------------- types */
+
+/* One transport problem between mu = sum_i a_i delta_{x_i} and
+ * nu = sum_j b_j delta_{y_j} (Sec. 2 notation).  All arrays are device
+ * pointers to FP64 data: x is n*d row-major, y is m*d row-major, a has n and
+ * b has m non-negative finite entries.  problem_index selects an independent
+ * random stream for the Poisson mask (third word of the hash counter). */
+typedef struct ss_problem {
+    int64_t n, m;
+    int32_t d;
+    uint32_t problem_index;
+    const double *x, *y, *a, *b;
+} ss_problem;
+
+/* Solver options.
+ * eps    > 0   entropic regularisation (eq. (rot) / eq. (ruot)).
+ * lambda > 0   KL relaxation weight of eq. (ruot); +INFINITY selects OT.
+ * s      > 0   subsample budget of eq. (pois): p*_ij = min(1, s p_ij).
+ * tol   >= 0   stop at the first iterate t with err(t) <= tol.
+ * seed         64-bit key of the counter-based hash (Philox4x32-10).
+ * max_iter >= 1 cap on Sinkhorn iterations.
+ * precision    SS_F64: FP64 values and scalings.
+ *              SS_F32: FP32 values, FP32 scalings, FP32 accumulation in the
+ *                      sparse products; residual, stop test and estimate FP64.
+ *              SS_F32_LOG: log-domain iteration (appendix, proof of Thm. 3):
+ *                      FP32 log-values log K~_ij, FP64 potentials, stabilised
+ *                      log-sum-exp with FP32 exponentials.
+ * cost         SS_COST_SQEUCLID_MAXNORM: C = |x-y|^2 / max |x-y|^2.
+ *              SS_COST_SQEUCLID:         C = |x-y|^2.
+ * stop_rule    SS_STOP_MARGINAL_L1: err(t) = L1 marginal error of (u^t, v^t) on
+ *              the iterated kernel (for UOT the fixed-point residual
+ *              sum|u^(1/th) K~v - a| + sum|v^(1/th) K~'u - b|, th = lam/(lam+eps)).
+ *              SS_STOP_SCALING_DELTA_L1: |u^t-u^(t-1)|_1 + |v^t-v^(t-1)|_1 (Alg. 1/2).
+ * empty_policy rows/columns of K~ with no entry: AUTO = RENORMALIZE for OT
+ *              (a, b rescaled to mass 1 on the non-empty support), ZERO for UOT
+ *              (u_i = 0, the sparse UOT optimum); FAIL returns SS_E_EMPTY.
+ * lanes_per_row  sparse-product schedule: 0 = automatic, else one of 4..64.
+ * graph_iters  iterations per captured HIP graph; 0 = automatic, < 0 = plain
+ *              launches.
+ * init_log_u, init_log_v  optional device FP64 warm start (log u^0, log v^0).
+ * u_out, v_out optional device FP64 outputs: the returned scalings u^t, v^t.
+ * err_hist     optional device FP64 array of max_iter entries: err(t) for
+ *              t = 1..iters (entries past iters untouched). */
+typedef struct ss_options {
+    double eps, lambda, s, tol;
+    uint64_t seed;
+    int32_t max_iter, precision, cost, stop_rule, empty_policy;
+    int32_t lanes_per_row, graph_iters, reserved0;
+    const double *init_log_u, *init_log_v;
+    double *u_out, *v_out, *err_hist;
+} ss_options;
+
+/* Result of a solve (host struct).
+ * estimate    Alg. 3: <T~,C> - eps H(T~);  Alg. 4 adds lam KL(T~1|a) + lam KL(T~'1|b).
+ * transport   <T~, C>.       neg_entropy  sum T~ (log T~ - 1) = -H(T~).
+ * kl_a, kl_b  KL terms (UOT; 0 for OT).
+ * sparse_objective  the sparse problem's own value <T~, C~> - eps H(T~) (+ KLs),
+ *             C~ = -eps log K~ (appendix, proof of Thm. 3).
+ * marginal_err err(iters) under the chosen stop rule.
+ * cmax        max_ij |x_i - y_j|^2.   z_norm  UOT normaliser sum q_ij (0 for OT).
+ * dropped_mass_a/b  mass of a / b on empty rows / columns.
+ * nnz, empty_rows, empty_cols  size of K~ and its empty lines (with a_i>0 / b_j>0).
+ * iters       t of the returned iterate.   status  same as the return value.
+ * t_*_ms      stage times measured with HIP events on `stream`. */
+typedef struct ss_result {
+    double estimate, transport, neg_entropy, kl_a, kl_b, sparse_objective;
+    double marginal_err, cmax, z_norm, dropped_mass_a, dropped_mass_b;
+    int64_t nnz, empty_rows, empty_cols;
+    int32_t iters, status;
+    float t_prep_ms, t_sample_ms, t_iter_ms, t_obj_ms;
+} ss_result;
+
+/* Caller-allocated device arrays receiving the sparse sketch (ss_sample).
+ * Any pointer may be NULL to skip that output.  `capacity` is the number of
+ * entries available in col_idx/val/row_idx/val_t.  Value arrays hold FP64
+ * (SS_F64), FP32 (SS_F32) or FP32 log K~ (SS_F32_LOG) entries.
+ * mask:   n * ceil(m/64) words, bit (j & 63) of word j >> 6 of row i set iff
+ *         entry (i, j) is kept.
+ * row_ptr (n+1), col_idx (ascending within a row), val        -- CSR of K~.
+ * col_ptr (m+1), row_idx (ascending within a column), val_t   -- CSC of K~.
+ * row_fac (n), col_fac (m): OT: alpha_i = s sqrt(a_i) / (S_a S_b) and sqrt(b_j),
+ *         so p*_ij = min(1, alpha_i * col_fac_j); UOT: th_u log a_i, th_u log b_j.
+ * On return nnz, cmax and z_norm are filled (host fields). */
+typedef struct ss_sparse {
+    uint64_t *mask;
+    int64_t *row_ptr;
+    int32_t *col_idx;
+    void *val;
+    int64_t *col_ptr;
+    int32_t *row_idx;
+    void *val_t;
+    double *row_fac, *col_fac;
+    int64_t capacity;
+    int64_t nnz;
+    double cmax, z_norm;
+} ss_sparse;
+
+/* ---------------------------------------------------------------- calls */
+
+/* Workspace bytes needed by every call below for this problem and options
+ * (the maximum over them).  Host-only; touches no device memory. */
+int ss_workspace_size(const ss_problem *problem, const ss_options *opts, size_t *bytes);
+
+/* Steps 1 of Alg. 3/4: sampling probabilities (eq. (pij-ot) or (pij-uot)),
+ * Poisson mask (eq. (pois)) from the counter hash, CSR and CSC of K~ = K/p*.
+ * Copies the requested pieces into `out` and synchronises `stream`. */
+int ss_sample(const ss_problem *problem, const ss_options *opts, ss_sparse *out,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* Alg. 3 (Spar-Sink for OT).  Requires lambda = +INFINITY. */
+int spar_sink_ot(const ss_problem *problem, const ss_options *opts, void *ws,
+                 size_t ws_bytes, void *stream, ss_result *result);
+
+/* Alg. 4 (Spar-Sink for UOT).  Requires finite lambda > 0. */
+int spar_sink_uot(const ss_problem *problem, const ss_options *opts, void *ws,
+                  size_t ws_bytes, void *stream, ss_result *result);
+
+/* Alg. 1 (lambda = +INFINITY) or Alg. 2 on the full kernel K = exp(-C/eps),
+ * recomputed from the coordinates in every half-step (never stored).  Same
+ * options, stop rules and estimate as the sparse solvers (nnz = n*m). */
+int dense_sinkhorn(const ss_problem *problem, const ss_options *opts, void *ws,
+                   size_t ws_bytes, void *stream, ss_result *result);
+
+/* Measurement hook for the memory-bound iteration kernel.  Samples K~ like
+ * the matching solver (OT if lambda = +INFINITY, else UOT), then runs exactly
+ * `iters` Sinkhorn iterations (even, >= 2; tol ignored, every launch does
+ * work) as one captured HIP graph: one warm-up replay, one replay between two
+ * HIP events on `stream`.  *ms_per_launch (host) receives the mean duration of
+ * one iteration-kernel launch (two launches per iteration: the K~ v product
+ * with the u-update, then the K~' u product with the v-update). */
+int ss_time_iterations(const ss_problem *problem, const ss_options *opts, void *ws,
+                       size_t ws_bytes, void *stream, int32_t iters, double *ms_per_launch);
+
+const char *ss_status_string(int status);
+const char *ss_last_error(void);
+int ss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPARSINK_H */

@@ -1,0 +1,213 @@
+"""Python binding of libsparsink: argument marshalling only.
+
+Every step of the solve runs in the HIP library; this module moves inputs to
+the device as torch tensors, sizes and caches the workspace, passes raw
+pointers and the current torch stream through the C ABI, and returns the host
+result.  Names follow the C calls: ``spar_sink_ot``, ``spar_sink_uot``,
+``dense_sinkhorn``, ``ss_sample``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import native as N
+
+_WS: dict = {}
+
+
+def _dev(t, dtype=torch.float64) -> torch.Tensor:
+    if isinstance(t, torch.Tensor):
+        if t.device.type != "cuda":
+            t = t.to("cuda")
+        return t.to(dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(t), dtype=dtype, device="cuda")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """A cached, 256-byte aligned uint8 device buffer of at least nbytes."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    buf = _WS.get(dev)
+    if buf is None or buf.numel() < nbytes:
+        _WS.pop(dev, None)
+        buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=dev)
+        assert buf.data_ptr() % 256 == 0
+        _WS[dev] = buf
+    return buf
+
+
+@dataclass
+class Result:
+    status: int
+    estimate: float
+    transport: float
+    neg_entropy: float
+    kl_a: float
+    kl_b: float
+    sparse_objective: float
+    marginal_err: float
+    cmax: float
+    z_norm: float
+    dropped_mass_a: float
+    dropped_mass_b: float
+    nnz: int
+    empty_rows: int
+    empty_cols: int
+    iters: int
+    t_prep_ms: float
+    t_sample_ms: float
+    t_iter_ms: float
+    t_obj_ms: float
+    u: Optional[torch.Tensor] = None
+    v: Optional[torch.Tensor] = None
+    err_hist: Optional[torch.Tensor] = None
+    extra: dict = field(default_factory=dict)
+
+
+class Problem:
+    """Device-resident inputs of one problem (FP64, contiguous)."""
+
+    def __init__(self, x, y, a, b, problem_index: int = 0):
+        self.x, self.y, self.a, self.b = _dev(x), _dev(y), _dev(a), _dev(b)
+        if self.x.dim() != 2 or self.y.dim() != 2 or self.x.shape[1] != self.y.shape[1]:
+            raise ValueError("x and y must be (n, d) and (m, d)")
+        if self.a.numel() != self.x.shape[0] or self.b.numel() != self.y.shape[0]:
+            raise ValueError("a must have n entries and b m entries")
+        self.problem_index = int(problem_index)
+        self.c = N.SsProblem(self.x.shape[0], self.y.shape[0], self.x.shape[1],
+                             self.problem_index, _ptr(self.x), _ptr(self.y), _ptr(self.a),
+                             _ptr(self.b))
+
+    @property
+    def n(self):
+        return int(self.x.shape[0])
+
+    @property
+    def m(self):
+        return int(self.y.shape[0])
+
+
+def make_options(eps, s=1.0, lam=math.inf, tol=1e-6, max_iter=1000, seed=0, precision="f64",
+                 cost="maxnorm", stop_rule="marginal", empty_policy="auto", lanes_per_row=0,
+                 graph_iters=0, init_log_u=None, init_log_v=None, u_out=None, v_out=None,
+                 err_hist=None) -> N.SsOptions:
+    return N.SsOptions(float(eps), float(lam), float(s), float(tol), int(seed) & (2 ** 64 - 1),
+                       int(max_iter), N.PRECISION[precision], N.COST[cost], N.STOP[stop_rule],
+                       N.EMPTY[empty_policy], int(lanes_per_row), int(graph_iters), 0,
+                       _ptr(init_log_u), _ptr(init_log_v), _ptr(u_out), _ptr(v_out),
+                       _ptr(err_hist))
+
+
+def workspace_size(prob: Problem, opts: N.SsOptions) -> int:
+    out = ctypes.c_size_t(0)
+    rc = N.lib.ss_workspace_size(ctypes.byref(prob.c), ctypes.byref(opts), ctypes.byref(out))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_workspace_size")
+    return int(out.value)
+
+
+def _solve(fn_name: str, prob: Problem, *, eps, s=1.0, lam=math.inf, tol=1e-6, max_iter=1000,
+           seed=0, precision="f64", cost="maxnorm", stop_rule="marginal", empty_policy="auto",
+           lanes_per_row=0, graph_iters=0, init_log_u=None, init_log_v=None,
+           return_scalings=False, return_hist=False, stream=None, raise_on_error=True) -> Result:
+    u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda") if return_scalings else None
+    v_out = torch.empty(prob.m, dtype=torch.float64, device="cuda") if return_scalings else None
+    hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device="cuda") \
+        if return_hist else None
+    ilu = _dev(init_log_u) if init_log_u is not None else None
+    ilv = _dev(init_log_v) if init_log_v is not None else None
+    opts = make_options(eps, s, lam, tol, max_iter, seed, precision, cost, stop_rule,
+                        empty_policy, lanes_per_row, graph_iters, ilu, ilv, u_out, v_out, hist)
+    nbytes = workspace_size(prob, opts)
+    ws = workspace(nbytes)
+    res = N.SsResult()
+    rc = getattr(N.lib, fn_name)(ctypes.byref(prob.c), ctypes.byref(opts),
+                                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                 _stream(stream), ctypes.byref(res))
+    if rc < 0 and raise_on_error:
+        raise N.SparSinkError(rc, fn_name)
+    out = Result(status=rc, **{k: getattr(res, k) for k, _ in N.SsResult._fields_
+                               if k != "status"})
+    out.u, out.v = u_out, v_out
+    if hist is not None:
+        out.err_hist = hist[: max(res.iters, 0)]
+    return out
+
+
+def spar_sink_ot(prob: Problem, **kw) -> Result:
+    """Alg. 3: Spar-Sink for entropic OT (lam must stay +inf)."""
+    return _solve("spar_sink_ot", prob, **kw)
+
+
+def spar_sink_uot(prob: Problem, **kw) -> Result:
+    """Alg. 4: Spar-Sink for entropic UOT (finite lam > 0)."""
+    return _solve("spar_sink_uot", prob, **kw)
+
+
+def dense_sinkhorn(prob: Problem, **kw) -> Result:
+    """Alg. 1 / Alg. 2 with the full kernel recomputed on the fly."""
+    return _solve("dense_sinkhorn", prob, **kw)
+
+
+def ss_time_iterations(prob: Problem, iters: int = 64, *, eps, s=1.0, lam=math.inf, seed=0,
+                       precision="f64", cost="maxnorm", lanes_per_row=0, stream=None) -> float:
+    """Mean duration (ms) of one iteration-kernel launch over `iters` iterations."""
+    opts = make_options(eps, s, lam, seed=seed, precision=precision, cost=cost,
+                        lanes_per_row=lanes_per_row)
+    ws = workspace(workspace_size(prob, opts))
+    ms = ctypes.c_double(0.0)
+    rc = N.lib.ss_time_iterations(ctypes.byref(prob.c), ctypes.byref(opts),
+                                  ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                  _stream(stream), int(iters), ctypes.byref(ms))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_time_iterations")
+    return float(ms.value)
+
+
+def ss_sample(prob: Problem, *, eps, s, lam=math.inf, seed=0, precision="f64", cost="maxnorm",
+              capacity: Optional[int] = None, want_mask=True, stream=None) -> dict:
+    """Step 1 of Alg. 3/4: returns the mask words, CSR, CSC and p* factors."""
+    opts = make_options(eps, s, lam, seed=seed, precision=precision, cost=cost)
+    nbytes = workspace_size(prob, opts)
+    ws = workspace(nbytes)
+    n, m = prob.n, prob.m
+    cap = capacity if capacity is not None else int(min(n * m, math.floor(s + 8 * math.sqrt(s) + 64)))
+    vdt = torch.float64 if precision == "f64" else torch.float32
+    out = {
+        "mask": torch.empty((n, (m + 63) // 64), dtype=torch.int64, device="cuda") if want_mask else None,
+        "row_ptr": torch.empty(n + 1, dtype=torch.int64, device="cuda"),
+        "col_idx": torch.empty(cap, dtype=torch.int32, device="cuda"),
+        "val": torch.empty(cap, dtype=vdt, device="cuda"),
+        "col_ptr": torch.empty(m + 1, dtype=torch.int64, device="cuda"),
+        "row_idx": torch.empty(cap, dtype=torch.int32, device="cuda"),
+        "val_t": torch.empty(cap, dtype=vdt, device="cuda"),
+        "row_fac": torch.empty(n, dtype=torch.float64, device="cuda"),
+        "col_fac": torch.empty(m, dtype=torch.float64, device="cuda"),
+    }
+    sp = N.SsSparse(*[_ptr(out[k]) for k in ("mask", "row_ptr", "col_idx", "val", "col_ptr",
+                                             "row_idx", "val_t", "row_fac", "col_fac")],
+                    cap, 0, 0.0, 0.0)
+    rc = N.lib.ss_sample(ctypes.byref(prob.c), ctypes.byref(opts), ctypes.byref(sp),
+                         ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                         _stream(stream))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_sample")
+    nnz = int(sp.nnz)
+    for k in ("col_idx", "val", "row_idx", "val_t"):
+        out[k] = out[k][:nnz]
+    out["nnz"], out["cmax"], out["z_norm"] = nnz, sp.cmax, sp.z_norm
+    return out

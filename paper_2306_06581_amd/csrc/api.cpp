@@ -1,0 +1,762 @@
+// Host driver of the C ABI declared in include/sparsink.h: argument checks,
+// workspace carving, stage orchestration on the caller's stream, the
+// graph-captured Sinkhorn loop, and the result assembly.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <functional>
+#include <string>
+
+#include "../../include/sparsink.h"
+#include "internal.hpp"
+
+using namespace ss;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return fail(SS_E_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));      \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Byte offsets of every region of the caller's workspace.
+struct Layout {
+    size_t mask, maskT, row_cnt, col_cnt, row_ptr, col_ptr, scan, col_idx, row_idx, val, val_t;
+    size_t row_fac, col_fac, row_bnd, col_bnd, a_eff, b_eff, tmp, tree, u[2], v[2];
+    size_t partials, state, stats, hstage, dense_part, rowsum, colsum;
+    size_t total;
+    int64_t cap;
+    int64_t partials_len;
+};
+
+int64_t entry_capacity(double s, int64_t n, int64_t m) {
+    const double nm = (double)n * (double)m;
+    double c = floor(s + 8.0 * sqrt(s) + 64.0);
+    if (c > nm) c = nm;
+    return (int64_t)c;
+}
+
+size_t esize(int precision) { return precision == SS_F64 ? 8 : 4; }
+size_t ysize(int precision) { return precision == SS_F32 ? 4 : 8; }
+
+Layout plan(const ss_problem* P, const ss_options* O) {
+    Layout L;
+    const int64_t n = P->n, m = P->m;
+    const int64_t W = (m + 63) / 64, Wn = (n + 63) / 64;
+    const int64_t nm = n > m ? n : m;
+    L.cap = entry_capacity(O->s, n, m);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.mask = take((size_t)n * W * 8);
+    L.maskT = take((size_t)m * Wn * 8);
+    L.row_cnt = take((size_t)n * 4);
+    L.col_cnt = take((size_t)m * 4);
+    L.row_ptr = take((size_t)(n + 1) * 8);
+    L.col_ptr = take((size_t)(m + 1) * 8);
+    L.scan = take((size_t)((nm + 1023) / 1024 + 1) * 8);
+    L.col_idx = take((size_t)L.cap * 4);
+    L.row_idx = take((size_t)L.cap * 4);
+    L.val = take((size_t)L.cap * esize(O->precision));
+    L.val_t = take((size_t)L.cap * esize(O->precision));
+    L.row_fac = take((size_t)n * 8);
+    L.col_fac = take((size_t)m * 8);
+    L.row_bnd = take((size_t)n * 8);
+    L.col_bnd = take((size_t)m * 8);
+    L.a_eff = take((size_t)n * 8);
+    L.b_eff = take((size_t)m * 8);
+    L.tmp = take((size_t)2 * nm * 8);
+    const int64_t cost_blocks = ((n + 255) / 256) * ((m + 2047) / 2048);
+    const int64_t tree_len = (cost_blocks > nm ? cost_blocks : nm);
+    L.tree = take((size_t)(2 * ((tree_len + 1023) / 1024) + 2) * 8);
+    for (int k = 0; k < 2; ++k) {
+        L.u[k] = take((size_t)n * ysize(O->precision));
+        L.v[k] = take((size_t)m * ysize(O->precision));
+    }
+    // block partials: iteration kernels (<= nm lines / 4 per block), objective
+    // (5 per block of 16 lines), UOT normaliser, dense objective.
+    int64_t pl = 5 * ((nm + 15) / 16) + 64;
+    if (cost_blocks > pl) pl = cost_blocks;
+    pl += 8 * ((nm + 255) / 256) + 3 * 4096 + 64;
+    L.partials_len = pl;
+    L.partials = take((size_t)pl * 8);
+    L.state = take(sizeof(IterState));
+    L.stats = take(ST_COUNT * 8);
+    L.hstage = take(64);
+    L.dense_part = take((size_t)64 * nm * 12);  // <= 64 column segments per line
+    L.rowsum = take((size_t)64 * n * 8);
+    L.colsum = take((size_t)64 * m * 8);
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+    return (T*)((char*)ws + off);
+}
+
+int check_args(const ss_problem* P, const ss_options* O, bool dense) {
+    if (!P || !O) return fail(SS_E_INVALID_ARG, "problem and options must not be NULL");
+    if (P->n <= 0 || P->m <= 0) return fail(SS_E_INVALID_ARG, "n and m must be positive");
+    if (P->n >= ((int64_t)1 << 31) || P->m >= ((int64_t)1 << 31))
+        return fail(SS_E_INVALID_ARG, "n and m must be below 2^31");
+    if (P->d <= 0 || P->d > 64) return fail(SS_E_INVALID_ARG, "d must be in [1, 64]");
+    if (dense && P->d > 16) return fail(SS_E_INVALID_ARG, "dense_sinkhorn supports d <= 16");
+    if (!P->x || !P->y || !P->a || !P->b)
+        return fail(SS_E_INVALID_ARG, "x, y, a, b must not be NULL");
+    if (!(O->eps > 0.0) || !isfinite(O->eps)) return fail(SS_E_INVALID_ARG, "eps must be > 0");
+    if (!dense && (!(O->s > 0.0) || !isfinite(O->s)))
+        return fail(SS_E_INVALID_ARG, "s must be a positive finite number");
+    if (!(O->tol >= 0.0)) return fail(SS_E_INVALID_ARG, "tol must be >= 0");
+    if (O->max_iter < 1) return fail(SS_E_INVALID_ARG, "max_iter must be >= 1");
+    if (O->precision < SS_F64 || O->precision > SS_F32_LOG)
+        return fail(SS_E_INVALID_ARG, "unknown precision %d", O->precision);
+    if (O->cost != SS_COST_SQEUCLID_MAXNORM && O->cost != SS_COST_SQEUCLID)
+        return fail(SS_E_INVALID_ARG, "unknown cost %d", O->cost);
+    if (O->stop_rule != SS_STOP_MARGINAL_L1 && O->stop_rule != SS_STOP_SCALING_DELTA_L1)
+        return fail(SS_E_INVALID_ARG, "unknown stop rule %d", O->stop_rule);
+    if (O->empty_policy < SS_EMPTY_AUTO || O->empty_policy > SS_EMPTY_FAIL)
+        return fail(SS_E_INVALID_ARG, "unknown empty policy %d", O->empty_policy);
+    const int l = O->lanes_per_row;
+    if (!(l == 0 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64))
+        return fail(SS_E_INVALID_ARG, "lanes_per_row must be 0, 4, 8, 16, 32 or 64");
+    if (!(O->lambda > 0.0)) return fail(SS_E_INVALID_ARG, "lambda must be > 0 (or +INFINITY)");
+    return SS_OK;
+}
+
+int check_ws(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes, Layout* L) {
+    *L = plan(P, O);
+    if (!ws) return fail(SS_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(SS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L->total)
+        return fail(SS_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L->total);
+    return SS_OK;
+}
+
+struct Timer {
+    hipEvent_t ev[5];
+    bool ok = false;
+    Timer() {
+        ok = true;
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) ok = false;
+    }
+    ~Timer() {
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+    void mark(int k, hipStream_t st) {
+        if (ok) (void)hipEventRecord(ev[k], st);
+    }
+    float ms(int a, int b) {
+        float t = 0.f;
+        if (ok) (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+        return t;
+    }
+};
+
+int auto_lanes(double avg) {
+    if (avg <= 6) return 4;
+    if (avg <= 14) return 8;
+    if (avg <= 40) return 16;
+    if (avg <= 100) return 32;
+    return 64;
+}
+
+// Runs the Sinkhorn loop: `iter(k, stream)` enqueues iteration k (its
+// ping-pong parity is k & 1).  With graph_iters > 0 an even number of
+// iterations is captured once and replayed; the host polls the 8-byte stop
+// state after each replay.
+int run_loop(const std::function<hipError_t(int, hipStream_t)>& iter, int graph_iters,
+             int max_iter, IterState* d_state, IterState* h_state, hipStream_t stream) {
+    const int total = max_iter + 1;  // the last launch only closes the residual
+    if (graph_iters > 0) {
+        int G = graph_iters + (graph_iters & 1);
+        if (G > total + (total & 1)) G = total + (total & 1);
+        hipStream_t cs;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        for (int k = 0; k < G && e == hipSuccess; ++k) e = iter(k, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        int rc = SS_OK;
+        if (e != hipSuccess) rc = fail(SS_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        for (int done = 0; rc == SS_OK && done < total; done += G) {
+            e = hipGraphLaunch(exec, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(h_state, d_state, sizeof(IterState), hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) rc = fail(SS_E_HIP, "loop failed: %s", hipGetErrorString(e));
+            if (h_state->stop_iter != 0 || h_state->nonfinite != 0) break;
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        return rc;
+    }
+    const int poll = 8;
+    for (int t = 1; t <= total; ++t) {
+        HIP_TRY(iter((t - 1) & 1, stream));
+        if (t % poll == 0 || t == total) {
+            HIP_TRY(hipMemcpyAsync(h_state, d_state, sizeof(IterState), hipMemcpyDeviceToHost,
+                                   stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            if (h_state->stop_iter != 0 || h_state->nonfinite != 0) break;
+        }
+    }
+    return SS_OK;
+}
+
+struct Ctx {
+    const ss_problem* P;
+    const ss_options* O;
+    Layout L;
+    void* ws;
+    hipStream_t st;
+    bool uot;
+    double stats[ST_COUNT];
+    int64_t nnz;
+    double inv_cmax;
+};
+
+// Zeroes state and statistics, checks the inputs, computes max c_ij.
+int stage_start(Ctx& c) {
+    const ss_problem* P = c.P;
+    double* stats = at<double>(c.ws, c.L.stats);
+    HIP_TRY(launch_fill_f64(stats, ST_COUNT, 0.0, c.st));
+    HIP_TRY(launch_fill_u32(at<uint32_t>(c.ws, c.L.state), sizeof(IterState) / 4, 0u, c.st));
+    HIP_TRY(launch_validate(P->a, P->n, P->x, P->n * P->d, stats, c.st));
+    HIP_TRY(launch_validate(P->b, P->m, P->y, P->m * P->d, stats, c.st));
+    HIP_TRY(launch_cmax(P->x, P->y, P->n, P->m, P->d, stats, c.st));
+    HIP_TRY(hipMemcpyAsync(c.stats, stats, sizeof(c.stats), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    if (c.stats[ST_BAD_INPUT] != 0.0)
+        return fail(SS_E_INVALID_ARG, "a, b must be finite and >= 0 and x, y finite");
+    const double cmax = c.stats[ST_CMAX];
+    c.inv_cmax = (c.O->cost == SS_COST_SQEUCLID_MAXNORM && cmax > 0.0) ? 1.0 / cmax : 1.0;
+    return SS_OK;
+}
+
+ProbParams make_params(const Ctx& c) {
+    ProbParams pp;
+    const ss_options* O = c.O;
+    pp.uot = c.uot ? 1 : 0;
+    pp.s = O->s;
+    pp.eps = O->eps;
+    pp.inv_cmax = c.inv_cmax;
+    pp.inv_tau = c.uot ? 1.0 / (2.0 * O->lambda + O->eps) : 0.0;
+    pp.kappa = 0.0;
+    pp.row_fac = at<double>(c.ws, c.L.row_fac);
+    pp.col_fac = at<double>(c.ws, c.L.col_fac);
+    pp.row_bnd = at<double>(c.ws, c.L.row_bnd);
+    pp.col_bnd = at<double>(c.ws, c.L.col_bnd);
+    pp.x = c.P->x;
+    pp.y = c.P->y;
+    pp.d = c.P->d;
+    pp.problem_index = c.P->problem_index;
+    pp.k0 = (uint32_t)(O->seed & 0xFFFFFFFFull);
+    pp.k1 = (uint32_t)(O->seed >> 32);
+    return pp;
+}
+
+// Probabilities, mask, CSR and CSC, empty-line policy (step 1 of Alg. 3/4).
+int stage_sample(Ctx& c) {
+    const ss_problem* P = c.P;
+    const ss_options* O = c.O;
+    const int64_t n = P->n, m = P->m;
+    const int64_t W = (m + 63) / 64, Wn = (n + 63) / 64;
+    void* ws = c.ws;
+    hipStream_t st = c.st;
+    double* stats = at<double>(ws, c.L.stats);
+    double* tree = at<double>(ws, c.L.tree);
+    ProbParams pp = make_params(c);
+    if (!c.uot) {
+        HIP_TRY(launch_ot_prep(P->a, P->b, n, m, O->s, (double*)pp.row_fac, (double*)pp.col_fac,
+                               tree, stats, st));
+    } else {
+        HIP_TRY(launch_uot_prep(P->a, P->b, n, m, O->lambda, O->eps, (double*)pp.row_fac,
+                                (double*)pp.col_fac, (double*)pp.row_bnd, st));
+        HIP_TRY(launch_uot_z(pp, n, m, at<double>(ws, c.L.partials), tree, stats, st));
+        HIP_TRY(launch_uot_bounds(pp.col_fac, m, O->s, stats, (double*)pp.col_bnd, st));
+    }
+    int32_t* row_cnt = at<int32_t>(ws, c.L.row_cnt);
+    int32_t* col_cnt = at<int32_t>(ws, c.L.col_cnt);
+    HIP_TRY(launch_fill_i32(row_cnt, n, 0, st));
+    HIP_TRY(launch_fill_i32(col_cnt, m, 0, st));
+    uint64_t* mask = at<uint64_t>(ws, c.L.mask);
+    uint64_t* maskT = at<uint64_t>(ws, c.L.maskT);
+    HIP_TRY(launch_mask(pp, n, m, mask, row_cnt, stats, st));
+    HIP_TRY(launch_transpose(mask, n, m, maskT, col_cnt, st));
+    int64_t* row_ptr = at<int64_t>(ws, c.L.row_ptr);
+    int64_t* col_ptr = at<int64_t>(ws, c.L.col_ptr);
+    HIP_TRY(launch_scan(row_cnt, n, row_ptr, at<int64_t>(ws, c.L.scan), st));
+    HIP_TRY(launch_scan(col_cnt, m, col_ptr, at<int64_t>(ws, c.L.scan), st));
+    int64_t tot[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&tot[0], row_ptr + n, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&tot[1], col_ptr + m, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (tot[0] != tot[1]) return fail(SS_E_HIP, "CSR and CSC sizes differ (%lld vs %lld)",
+                                      (long long)tot[0], (long long)tot[1]);
+    c.nnz = tot[0];
+    if (c.nnz > c.L.cap)
+        return fail(SS_E_CAPACITY, "sampled %lld entries exceed the capacity %lld",
+                    (long long)c.nnz, (long long)c.L.cap);
+    HIP_TRY(launch_fill_entries(0, O->precision, pp, stats, mask, n, W, row_ptr,
+                                at<int32_t>(ws, c.L.col_idx), at<void>(ws, c.L.val), c.L.cap, st));
+    HIP_TRY(launch_fill_entries(1, O->precision, pp, stats, maskT, m, Wn, col_ptr,
+                                at<int32_t>(ws, c.L.row_idx), at<void>(ws, c.L.val_t), c.L.cap,
+                                st));
+    int policy = O->empty_policy;
+    if (policy == SS_EMPTY_AUTO) policy = c.uot ? SS_EMPTY_ZERO : SS_EMPTY_RENORMALIZE;
+    const int renorm = policy == SS_EMPTY_RENORMALIZE;
+    HIP_TRY(launch_empty_policy(P->a, row_cnt, n, renorm, 0, at<double>(ws, c.L.a_eff),
+                                at<double>(ws, c.L.tmp), tree, stats, st));
+    HIP_TRY(launch_empty_policy(P->b, col_cnt, m, renorm, 1, at<double>(ws, c.L.b_eff),
+                                at<double>(ws, c.L.tmp), tree, stats, st));
+    if (policy == SS_EMPTY_FAIL) {
+        HIP_TRY(hipMemcpyAsync(c.stats, stats, sizeof(c.stats), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (c.stats[ST_EMPTY_ROWS] > 0 || c.stats[ST_EMPTY_COLS] > 0)
+            return fail(SS_E_EMPTY, "%.0f empty rows and %.0f empty columns",
+                        c.stats[ST_EMPTY_ROWS], c.stats[ST_EMPTY_COLS]);
+    }
+    return SS_OK;
+}
+
+// Captures `iters` iterations (iters even, every launch active), replays the
+// graph once to warm up, resets the state and scalings, replays it again
+// between two events, and reports the mean time of one kernel launch
+// (2 launches per iteration for the sparse loop, `launches_per_iter` in general).
+int time_graph(const std::function<hipError_t(int, hipStream_t)>& iter, int iters, void* u0,
+               void* v0, int prec, int64_t n, int64_t m, const ss_options* O, IterState* d_state,
+               hipStream_t st, double* ms_out, int launches_per_iter = 2) {
+    if (!ms_out) return fail(SS_E_INVALID_ARG, "ms_out must not be NULL");
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < iters && e == hipSuccess; ++k) e = iter(k, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        e = launch_fill_u32((uint32_t*)d_state, sizeof(IterState) / 4, 0u, st);
+        if (e == hipSuccess) e = launch_init_scaling(prec, u0, O->init_log_u, n, st);
+        if (e == hipSuccess) e = launch_init_scaling(prec, v0, O->init_log_v, m, st);
+        if (e == hipSuccess && rep == 1) e = hipEventRecord(a, st);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, st);
+        if (e == hipSuccess && rep == 1) e = hipEventRecord(b, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(SS_E_HIP, "timing graph failed: %s", hipGetErrorString(e));
+    *ms_out = (double)ms / (double)(iters * launches_per_iter);
+    return SS_OK;
+}
+
+void fill_result(const Ctx& c, const IterState& hs, ss_result* R, int64_t nnz) {
+    const double* s = c.stats;
+    const ss_options* O = c.O;
+    const double kl = c.uot ? O->lambda * (s[ST_KL_A] + s[ST_KL_B]) : 0.0;
+    R->transport = s[ST_TRANSPORT];
+    R->neg_entropy = s[ST_NEGENT];
+    R->kl_a = c.uot ? s[ST_KL_A] : 0.0;
+    R->kl_b = c.uot ? s[ST_KL_B] : 0.0;
+    R->estimate = s[ST_TRANSPORT] + O->eps * s[ST_NEGENT] + kl;
+    R->sparse_objective = O->eps * s[ST_SPARSEOBJ] + kl;
+    R->marginal_err = hs.err_final;
+    R->cmax = s[ST_CMAX];
+    R->z_norm = c.uot ? s[ST_Z] : 0.0;
+    R->dropped_mass_a = s[ST_DROPPED_A];
+    R->dropped_mass_b = s[ST_DROPPED_B];
+    R->nnz = nnz;
+    R->empty_rows = (int64_t)s[ST_EMPTY_ROWS];
+    R->empty_cols = (int64_t)s[ST_EMPTY_COLS];
+    R->iters = hs.stop_iter;
+}
+
+// time_iters > 0: after sampling, run exactly time_iters iterations (tol = 0)
+// as one captured graph, once to warm up and once timed with HIP events, and
+// return the mean duration of one iteration-kernel launch in *ms_out.
+int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes,
+                   void* stream, ss_result* R, bool uot, int time_iters = 0,
+                   double* ms_out = nullptr) {
+    int rc = check_args(P, O, false);
+    if (rc != SS_OK) return rc;
+    if (!R) return fail(SS_E_INVALID_ARG, "result must not be NULL");
+    if (uot && !isfinite(O->lambda)) return fail(SS_E_INVALID_ARG, "spar_sink_uot needs finite lambda");
+    if (!uot && isfinite(O->lambda)) return fail(SS_E_INVALID_ARG, "spar_sink_ot needs lambda = +INFINITY");
+    Ctx c;
+    c.P = P;
+    c.O = O;
+    c.ws = ws;
+    c.st = (hipStream_t)stream;
+    c.uot = uot;
+    rc = check_ws(P, O, ws, ws_bytes, &c.L);
+    if (rc != SS_OK) return rc;
+    memset(R, 0, sizeof *R);
+    Timer tm;
+    tm.mark(0, c.st);
+    rc = stage_start(c);
+    if (rc != SS_OK) return rc;
+    tm.mark(1, c.st);
+    rc = stage_sample(c);
+    if (rc != SS_OK) return rc;
+    tm.mark(2, c.st);
+
+    const int64_t n = P->n, m = P->m;
+    const int prec = O->precision;
+    void* u[2] = {at<void>(ws, c.L.u[0]), at<void>(ws, c.L.u[1])};
+    void* v[2] = {at<void>(ws, c.L.v[0]), at<void>(ws, c.L.v[1])};
+    HIP_TRY(launch_init_scaling(prec, u[0], O->init_log_u, n, c.st));
+    HIP_TRY(launch_init_scaling(prec, v[0], O->init_log_v, m, c.st));
+    IterState* d_state = at<IterState>(ws, c.L.state);
+    const double theta = uot ? O->lambda / (O->lambda + O->eps) : 1.0;
+    const int lanes = O->lanes_per_row ? O->lanes_per_row
+                                       : auto_lanes((double)c.nnz / (double)(n < m ? n : m));
+    IterArgs ua[2], va[2];
+    for (int k = 0; k < 2; ++k) {
+        IterArgs a;
+        a.ptr = at<int64_t>(ws, c.L.row_ptr);
+        a.idx = at<int32_t>(ws, c.L.col_idx);
+        a.val = at<void>(ws, c.L.val);
+        a.nlines = n;
+        a.marg = at<double>(ws, c.L.a_eff);
+        a.xin = v[k];
+        a.yout = u[(k + 1) & 1];
+        a.yprev = u[k];
+        a.theta = theta;
+        a.partials = at<double>(ws, c.L.partials);
+        a.st = d_state;
+        a.err_hist = O->err_hist;
+        a.role = 0;
+        a.stop_rule = O->stop_rule;
+        a.max_iter = O->max_iter;
+        a.tol = O->tol;
+        ua[k] = a;
+        a.ptr = at<int64_t>(ws, c.L.col_ptr);
+        a.idx = at<int32_t>(ws, c.L.row_idx);
+        a.val = at<void>(ws, c.L.val_t);
+        a.nlines = m;
+        a.marg = at<double>(ws, c.L.b_eff);
+        a.xin = u[(k + 1) & 1];
+        a.yout = v[(k + 1) & 1];
+        a.yprev = v[k];
+        a.role = 1;
+        va[k] = a;
+    }
+    auto iter = [&](int k, hipStream_t s) -> hipError_t {
+        hipError_t e = launch_iterate(prec, lanes, ua[k & 1], s);
+        if (e == hipSuccess) e = launch_iterate(prec, lanes, va[k & 1], s);
+        return e;
+    };
+    if (time_iters > 0) {
+        for (int k = 0; k < 2; ++k) {
+            ua[k].tol = va[k].tol = 0.0;
+            ua[k].max_iter = va[k].max_iter = time_iters;
+            ua[k].err_hist = va[k].err_hist = nullptr;
+        }
+        return time_graph(iter, time_iters, u[0], v[0], prec, n, m, O, d_state, c.st, ms_out);
+    }
+    const int G = O->graph_iters == 0 ? 16 : O->graph_iters;
+    IterState hs;
+    memset(&hs, 0, sizeof hs);
+    rc = run_loop(iter, G, O->max_iter, d_state, &hs, c.st);
+    if (rc != SS_OK) return rc;
+    tm.mark(3, c.st);
+    if (hs.nonfinite) return fail(SS_E_NONFINITE, "a scaling became NaN or Inf");
+    if (hs.stop_iter <= 0) return fail(SS_E_HIP, "loop ended without a result");
+    const int p = hs.stop_iter & 1;
+
+    ObjArgs oa;
+    oa.ptr = at<int64_t>(ws, c.L.row_ptr);
+    oa.idx = at<int32_t>(ws, c.L.col_idx);
+    oa.val = at<void>(ws, c.L.val);
+    oa.nlines = n;
+    oa.ys = u[p];
+    oa.zs = v[p];
+    oa.marg = P->a;
+    oa.x = P->x;
+    oa.y = P->y;
+    oa.d = P->d;
+    oa.inv_cmax = c.inv_cmax;
+    oa.eps = O->eps;
+    oa.uot = uot ? 1 : 0;
+    oa.role = 0;
+    oa.partials = at<double>(ws, c.L.partials);
+    oa.st = d_state;
+    oa.stats = at<double>(ws, c.L.stats);
+    HIP_TRY(launch_objective(prec, oa, c.st));
+    oa.ptr = at<int64_t>(ws, c.L.col_ptr);
+    oa.idx = at<int32_t>(ws, c.L.row_idx);
+    oa.val = at<void>(ws, c.L.val_t);
+    oa.nlines = m;
+    oa.ys = v[p];
+    oa.zs = u[p];
+    oa.marg = P->b;
+    oa.x = P->y;
+    oa.y = P->x;
+    oa.role = 1;
+    HIP_TRY(launch_objective(prec, oa, c.st));
+    HIP_TRY(launch_export_scaling(prec, u[p], O->u_out, n, c.st));
+    HIP_TRY(launch_export_scaling(prec, v[p], O->v_out, m, c.st));
+    HIP_TRY(hipMemcpyAsync(c.stats, at<double>(ws, c.L.stats), sizeof(c.stats),
+                           hipMemcpyDeviceToHost, c.st));
+    tm.mark(4, c.st);
+    HIP_TRY(hipStreamSynchronize(c.st));
+    fill_result(c, hs, R, c.nnz);
+    R->t_prep_ms = tm.ms(0, 1);
+    R->t_sample_ms = tm.ms(1, 2);
+    R->t_iter_ms = tm.ms(2, 3);
+    R->t_obj_ms = tm.ms(3, 4);
+    R->status = hs.err_final <= O->tol ? SS_OK : SS_NOT_CONVERGED;
+    return R->status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_version(void) { return 100; }
+
+const char* ss_last_error(void) { return g_last_error.c_str(); }
+
+const char* ss_status_string(int status) {
+    switch (status) {
+        case SS_OK: return "ok";
+        case SS_NOT_CONVERGED: return "not converged: max_iter reached with err > tol";
+        case SS_E_INVALID_ARG: return "invalid argument";
+        case SS_E_HIP: return "HIP runtime error";
+        case SS_E_WORKSPACE: return "workspace missing, misaligned or too small";
+        case SS_E_NONFINITE: return "non-finite scaling";
+        case SS_E_EMPTY: return "empty row or column with empty_policy FAIL";
+        case SS_E_CAPACITY: return "sampled entries exceed the workspace capacity";
+        default: return "unknown status";
+    }
+}
+
+int ss_workspace_size(const ss_problem* problem, const ss_options* opts, size_t* bytes) {
+    int rc = check_args(problem, opts, false);
+    if (rc != SS_OK) return rc;
+    if (!bytes) return fail(SS_E_INVALID_ARG, "bytes must not be NULL");
+    *bytes = plan(problem, opts).total;
+    return SS_OK;
+}
+
+int ss_sample(const ss_problem* P, const ss_options* O, ss_sparse* out, void* ws, size_t ws_bytes,
+              void* stream) {
+    int rc = check_args(P, O, false);
+    if (rc != SS_OK) return rc;
+    if (!out) return fail(SS_E_INVALID_ARG, "out must not be NULL");
+    Ctx c;
+    c.P = P;
+    c.O = O;
+    c.ws = ws;
+    c.st = (hipStream_t)stream;
+    c.uot = isfinite(O->lambda);
+    rc = check_ws(P, O, ws, ws_bytes, &c.L);
+    if (rc != SS_OK) return rc;
+    rc = stage_start(c);
+    if (rc != SS_OK) return rc;
+    rc = stage_sample(c);
+    if (rc != SS_OK) return rc;
+    const int64_t n = P->n, m = P->m;
+    const int64_t W = (m + 63) / 64;
+    const bool wants_entries = out->col_idx || out->val || out->row_idx || out->val_t;
+    if (wants_entries && out->capacity < c.nnz)
+        return fail(SS_E_CAPACITY, "out->capacity %lld < nnz %lld", (long long)out->capacity,
+                    (long long)c.nnz);
+    const size_t es = esize(O->precision);
+    auto cp = [&](void* dst, size_t off, size_t bytes) -> hipError_t {
+        if (!dst || bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(dst, at<char>(ws, off), bytes, hipMemcpyDeviceToDevice, c.st);
+    };
+    HIP_TRY(cp(out->mask, c.L.mask, (size_t)n * W * 8));
+    HIP_TRY(cp(out->row_ptr, c.L.row_ptr, (size_t)(n + 1) * 8));
+    HIP_TRY(cp(out->col_idx, c.L.col_idx, (size_t)c.nnz * 4));
+    HIP_TRY(cp(out->val, c.L.val, (size_t)c.nnz * es));
+    HIP_TRY(cp(out->col_ptr, c.L.col_ptr, (size_t)(m + 1) * 8));
+    HIP_TRY(cp(out->row_idx, c.L.row_idx, (size_t)c.nnz * 4));
+    HIP_TRY(cp(out->val_t, c.L.val_t, (size_t)c.nnz * es));
+    HIP_TRY(cp(out->row_fac, c.L.row_fac, (size_t)n * 8));
+    HIP_TRY(cp(out->col_fac, c.L.col_fac, (size_t)m * 8));
+    HIP_TRY(hipMemcpyAsync(c.stats, at<double>(ws, c.L.stats), sizeof(c.stats),
+                           hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    out->nnz = c.nnz;
+    out->cmax = c.stats[ST_CMAX];
+    out->z_norm = c.uot ? c.stats[ST_Z] : 0.0;
+    return SS_OK;
+}
+
+int spar_sink_ot(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes, void* stream,
+                 ss_result* R) {
+    return spar_sink_impl(P, O, ws, ws_bytes, stream, R, false);
+}
+
+int spar_sink_uot(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes,
+                  void* stream, ss_result* R) {
+    return spar_sink_impl(P, O, ws, ws_bytes, stream, R, true);
+}
+
+int ss_time_iterations(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes,
+                       void* stream, int32_t iters, double* ms_per_launch) {
+    if (iters < 2 || (iters & 1)) return fail(SS_E_INVALID_ARG, "iters must be even and >= 2");
+    if (!O) return fail(SS_E_INVALID_ARG, "options must not be NULL");
+    ss_result R;
+    return spar_sink_impl(P, O, ws, ws_bytes, stream, &R, isfinite(O->lambda), iters,
+                          ms_per_launch);
+}
+
+int dense_sinkhorn(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes,
+                   void* stream, ss_result* R) {
+    int rc = check_args(P, O, true);
+    if (rc != SS_OK) return rc;
+    if (!R) return fail(SS_E_INVALID_ARG, "result must not be NULL");
+    Ctx c;
+    c.P = P;
+    c.O = O;
+    c.ws = ws;
+    c.st = (hipStream_t)stream;
+    c.uot = isfinite(O->lambda);
+    rc = check_ws(P, O, ws, ws_bytes, &c.L);
+    if (rc != SS_OK) return rc;
+    memset(R, 0, sizeof *R);
+    Timer tm;
+    tm.mark(0, c.st);
+    rc = stage_start(c);
+    if (rc != SS_OK) return rc;
+    tm.mark(1, c.st);
+    tm.mark(2, c.st);
+    const int64_t n = P->n, m = P->m;
+    const int prec = O->precision;
+    void* u[2] = {at<void>(ws, c.L.u[0]), at<void>(ws, c.L.u[1])};
+    void* v[2] = {at<void>(ws, c.L.v[0]), at<void>(ws, c.L.v[1])};
+    HIP_TRY(launch_init_scaling(prec, u[0], O->init_log_u, n, c.st));
+    HIP_TRY(launch_init_scaling(prec, v[0], O->init_log_v, m, c.st));
+    IterState* d_state = at<IterState>(ws, c.L.state);
+    const double theta = c.uot ? O->lambda / (O->lambda + O->eps) : 1.0;
+    DenseArgs ua[2], va[2];
+    for (int k = 0; k < 2; ++k) {
+        DenseArgs a;
+        a.xl = P->x;
+        a.xo = P->y;
+        a.nl = n;
+        a.no = m;
+        a.d = P->d;
+        a.scale = c.inv_cmax / O->eps;
+        a.inv_cmax = c.inv_cmax;
+        a.eps = O->eps;
+        a.marg = P->a;
+        a.xin = v[k];
+        a.yout = u[(k + 1) & 1];
+        a.yprev = u[k];
+        a.theta = theta;
+        a.partials = at<double>(ws, c.L.partials);
+        a.st = d_state;
+        a.err_hist = O->err_hist;
+        a.role = 0;
+        a.stop_rule = O->stop_rule;
+        a.max_iter = O->max_iter;
+        a.tol = O->tol;
+        a.stats = at<double>(ws, c.L.stats);
+        ua[k] = a;
+        a.xl = P->y;
+        a.xo = P->x;
+        a.nl = m;
+        a.no = n;
+        a.marg = P->b;
+        a.xin = u[(k + 1) & 1];
+        a.yout = v[(k + 1) & 1];
+        a.yprev = v[k];
+        a.role = 1;
+        va[k] = a;
+    }
+    void* part = at<void>(ws, c.L.dense_part);
+    auto iter = [&](int k, hipStream_t s) -> hipError_t {
+        hipError_t e = launch_dense_half(prec, ua[k & 1], part, s);
+        if (e == hipSuccess) e = launch_dense_half(prec, va[k & 1], part, s);
+        return e;
+    };
+    const int G = O->graph_iters == 0 ? 8 : O->graph_iters;
+    IterState hs;
+    memset(&hs, 0, sizeof hs);
+    rc = run_loop(iter, G, O->max_iter, d_state, &hs, c.st);
+    if (rc != SS_OK) return rc;
+    tm.mark(3, c.st);
+    if (hs.nonfinite) return fail(SS_E_NONFINITE, "a scaling became NaN or Inf");
+    if (hs.stop_iter <= 0) return fail(SS_E_HIP, "loop ended without a result");
+    const int p = hs.stop_iter & 1;
+    DenseObjArgs oa;
+    oa.x = P->x;
+    oa.y = P->y;
+    oa.n = n;
+    oa.m = m;
+    oa.d = P->d;
+    oa.inv_cmax = c.inv_cmax;
+    oa.eps = O->eps;
+    oa.u = u[p];
+    oa.v = v[p];
+    oa.a = P->a;
+    oa.b = P->b;
+    oa.uot = c.uot ? 1 : 0;
+    oa.precision = prec;
+    oa.partials = at<double>(ws, c.L.partials);
+    oa.rowsum = at<double>(ws, c.L.rowsum);
+    oa.colsum = at<double>(ws, c.L.colsum);
+    oa.st = d_state;
+    oa.stats = at<double>(ws, c.L.stats);
+    oa.statsc = oa.stats;
+    HIP_TRY(launch_dense_objective(oa, c.st));
+    HIP_TRY(launch_export_scaling(prec, u[p], O->u_out, n, c.st));
+    HIP_TRY(launch_export_scaling(prec, v[p], O->v_out, m, c.st));
+    HIP_TRY(hipMemcpyAsync(c.stats, at<double>(ws, c.L.stats), sizeof(c.stats),
+                           hipMemcpyDeviceToHost, c.st));
+    tm.mark(4, c.st);
+    HIP_TRY(hipStreamSynchronize(c.st));
+    fill_result(c, hs, R, n * m);
+    R->t_prep_ms = tm.ms(0, 1);
+    R->t_sample_ms = 0.f;
+    R->t_iter_ms = tm.ms(2, 3);
+    R->t_obj_ms = tm.ms(3, 4);
+    R->status = hs.err_final <= O->tol ? SS_OK : SS_NOT_CONVERGED;
+    return R->status;
+}
+
+}  // extern "C"

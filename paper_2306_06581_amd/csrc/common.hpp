@@ -1,0 +1,144 @@
+// Device-side helpers shared by the Spar-Sink kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC 2011).  Each round
+// multiplies counter words 0 and 2 by the two Philox multipliers, keeps the
+// 64-bit products, and mixes the high halves with words 1/3 and the key; the
+// key is bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                           uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Words4 out;
+    out.w[0] = c0;
+    out.w[1] = c1;
+    out.w[2] = c2;
+    out.w[3] = c3;
+    return out;
+}
+
+// Hash layout of the Poisson mask.  Column j of row i in problem k uses the
+// counter (q, i, k, w) with q = (j >> 8) * 64 + (j & 63) and output slot
+// (j >> 6) & 3: the w = 0 call gives the high 32 bits, the w = 1 call the low
+// 32 bits of a 64-bit word; U = (bits >> 11) * 2^-53.  A wave therefore covers
+// 256 consecutive columns with one call per lane and four ballots.
+//
+// keep(i, j) = [U < P].  U lies in [h, h + 2^-32 - 2^-53] with h = hi * 2^-32,
+// so the high word alone decides unless P falls inside that interval, which
+// happens with probability 2^-32 per entry; only then is the low word drawn.
+__device__ __forceinline__ bool keep_decision(uint32_t hi, double P, uint32_t q, uint32_t i,
+                                              uint32_t k, uint32_t k0, uint32_t k1, int slot) {
+    const double h = (double)hi * 0x1p-32;
+    if (h >= P) return false;
+    if (h + (0x1p-32 - 0x1p-53) < P) return true;
+    const Words4 lo = philox10(q, i, k, 1u, k0, k1);
+    const uint64_t bits = ((uint64_t)hi << 32) | (uint64_t)lo.w[slot];
+    const double U = (double)(bits >> 11) * 0x1p-53;
+    return U < P;
+}
+
+// Squared Euclidean distance accumulated in coordinate order, each product and
+// sum rounded separately (the library is built with FP contraction off).
+template <int D>
+__device__ __forceinline__ double sqdist(const double* __restrict__ xi, const double* __restrict__ yj,
+                                         int d) {
+    const int dd = D > 0 ? D : d;
+    double t = xi[0] - yj[0];
+    double acc = t * t;
+#pragma unroll
+    for (int k = 1; k < (D > 0 ? D : 1); ++k) {
+        const double u = xi[k] - yj[k];
+        acc = acc + u * u;
+    }
+    if (D == 0) {
+        for (int k = 1; k < dd; ++k) {
+            const double u = xi[k] - yj[k];
+            acc = acc + u * u;
+        }
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Wave and block reductions.  xor-butterflies give every lane the same value
+// (IEEE addition is commutative), so the results are deterministic.
+// ---------------------------------------------------------------------------
+template <int WIDTH, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int off = WIDTH / 2; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, WIDTH);
+    return v;
+}
+
+template <int WIDTH, typename T>
+__device__ __forceinline__ T group_max(T v) {
+#pragma unroll
+    for (int off = WIDTH / 2; off >= 1; off >>= 1) {
+        const T o = __shfl_xor(v, off, WIDTH);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Sum over a 256-thread block in a fixed tree; result valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+    v = group_sum<kWave>(v);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return r;
+}
+
+// Inclusive prefix sum of an int over the wave.
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int o = __shfl_up(v, off, kWave);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Relaxed agent-scope load, used where a block reads values other blocks of
+// the same launch wrote (last-block reductions).
+__device__ __forceinline__ double load_agent(const double* p) {
+    const unsigned long long bits =
+        __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)bits);
+}
+
+__device__ __forceinline__ void store_agent(double* p, double v) {
+    __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace ss

@@ -1,0 +1,193 @@
+// Internal interfaces between the host driver (api.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+
+// Device-resident state of one Sinkhorn loop.  Written only by the last block
+// of each iteration kernel (ticketed), read by every block of later kernels.
+struct IterState {
+    int32_t iter;        // last completed iteration t (after its v-update)
+    int32_t stop_iter;   // 0 while running; else t of the returned iterate
+    int32_t nonfinite;   // set when a scaling became NaN/Inf
+    int32_t pad0;
+    uint32_t ticket[4];  // last-block counters (u role, v role, objective rows, cols)
+    double err_col;      // column residual of iterate `iter` (marginal rule)
+    double err_row;      // row part of the current iteration (delta rule)
+    double err_final;    // err of the returned iterate
+    double pad1;
+};
+
+// Per-solve scalars produced on the device and copied to the host once.
+enum StatSlot {
+    ST_CMAX = 0,
+    ST_SA,
+    ST_SB,
+    ST_Z,
+    ST_SUM_A_ACTIVE,
+    ST_SUM_B_ACTIVE,
+    ST_DROPPED_A,
+    ST_DROPPED_B,
+    ST_TRANSPORT,
+    ST_NEGENT,
+    ST_SPARSEOBJ,
+    ST_KL_A,
+    ST_KL_B,
+    ST_ROWSUM,
+    ST_COLSUM,
+    ST_BAD_INPUT,   // > 0 if an input was negative or non-finite
+    ST_EMPTY_ROWS,  // rows with no entry and a_i > 0 (stored as double)
+    ST_EMPTY_COLS,
+    ST_COUNT = 32
+};
+
+enum Precision { P_F64 = 0, P_F32 = 1, P_LOG = 2 };
+
+// Parameters of the sampling probabilities and entry values.
+struct ProbParams {
+    int uot;            // 0: eq. (pij-ot), 1: eq. (pij-uot)
+    double s;           // budget
+    double eps;
+    double inv_cmax;    // C = c * inv_cmax
+    double inv_tau;     // 1 / (2 lam + eps)            (UOT)
+    double kappa;       // s / Z                        (UOT; device value in stats)
+    const double* row_fac;  // OT: alpha_i;  UOT: th_u log a_i
+    const double* col_fac;  // OT: sqrt b_j; UOT: th_u log b_j
+    const double* row_bnd;  // UOT: exp(row_fac_i)
+    const double* col_bnd;  // UOT: kappa * exp(col_fac_j) * (1 + 2^-30)
+    const double* x;
+    const double* y;
+    int d;
+    uint32_t problem_index;
+    uint32_t k0, k1;
+};
+
+struct Workspace;
+
+// ---- sample.hip
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_validate(const double* a, int64_t n, const double* x, int64_t nx, double* stats,
+                           hipStream_t st);
+hipError_t launch_tree_sum(const double* in, int64_t n, double* scratch, double* out,
+                           hipStream_t st);
+hipError_t launch_cmax(const double* x, const double* y, int64_t n, int64_t m, int d,
+                       double* stats, hipStream_t st);
+hipError_t launch_ot_prep(const double* a, const double* b, int64_t n, int64_t m, double s,
+                          double* ra, double* rb, double* scratch, double* stats,
+                          hipStream_t st);
+hipError_t launch_uot_prep(const double* a, const double* b, int64_t n, int64_t m, double lam,
+                           double eps, double* la, double* lb, double* ea, hipStream_t st);
+hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, double* partials,
+                        double* scratch, double* stats, hipStream_t st);
+hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, const double* stats,
+                             double* fb, hipStream_t st);
+hipError_t launch_mask(const ProbParams& pp, int64_t n, int64_t m, uint64_t* mask,
+                       int32_t* row_cnt, const double* stats, hipStream_t st);
+hipError_t launch_transpose(const uint64_t* mask, int64_t n, int64_t m, uint64_t* maskT,
+                            int32_t* col_cnt, hipStream_t st);
+hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* ptr, int64_t* scratch,
+                       hipStream_t st);
+hipError_t launch_fill_entries(int role, int precision, const ProbParams& pp, const double* stats,
+                               const uint64_t* bits, int64_t nlines, int64_t words,
+                               const int64_t* ptr, int32_t* idx, void* val, int64_t cap,
+                               hipStream_t st);
+hipError_t launch_empty_policy(const double* a, const int32_t* cnt, int64_t n, int renormalize,
+                               int which, double* a_eff, double* tmp, double* scratch,
+                               double* stats, hipStream_t st);
+
+// ---- iterate.hip
+struct IterArgs {
+    const int64_t* ptr;
+    const int32_t* idx;
+    const void* val;
+    int64_t nlines;
+    const double* marg;   // a_eff (u role) or b_eff (v role)
+    const void* xin;      // gathered vector: v^(t-1) (u role), u^t (v role)
+    void* yout;           // new scaling / potential
+    const void* yprev;    // previous value of the same scaling
+    double theta;         // lam/(lam+eps); 1 for OT
+    double* partials;
+    IterState* st;
+    double* err_hist;
+    int role;             // 0 = u-update (closes the previous iterate), 1 = v-update
+    int stop_rule;
+    int max_iter;
+    double tol;
+};
+hipError_t launch_iterate(int precision, int lanes, const IterArgs& a, hipStream_t st);
+int iterate_blocks(int lanes, int64_t nlines);
+hipError_t launch_init_scaling(int precision, void* y, const double* init_log, int64_t n,
+                               hipStream_t st);
+hipError_t launch_export_scaling(int precision, const void* y, double* out, int64_t n,
+                                 hipStream_t st);
+
+// ---- objective.hip
+struct ObjArgs {
+    const int64_t* ptr;
+    const int32_t* idx;
+    const void* val;
+    int64_t nlines;
+    const void* ys;       // scaling of the line (u for rows, v for columns)
+    const void* zs;       // scaling of the other side
+    const double* marg;   // a (rows) / b (columns), original masses
+    const double* x;      // coordinates of the line side
+    const double* y;      // coordinates of the other side
+    int d;
+    double inv_cmax;
+    double eps;
+    int uot;
+    int role;             // 0 rows (transport, entropy, KL_a), 1 columns (KL_b)
+    double* partials;     // 4 * nblocks
+    IterState* st;
+    double* stats;
+};
+hipError_t launch_objective(int precision, const ObjArgs& a, hipStream_t st);
+
+// ---- dense.hip
+struct DenseArgs {
+    const double* xl;     // coordinates of the line side (n_l x d)
+    const double* xo;     // coordinates of the other side (n_o x d)
+    int64_t nl, no;
+    int d;
+    double scale;         // inv_cmax / eps: K = exp(-c * scale)
+    double inv_cmax, eps; // FP64 mode: K = exp(-((c * inv_cmax) / eps))
+    const double* marg;
+    const void* xin;      // other side's scaling
+    void* yout;
+    const void* yprev;
+    double theta;
+    double* partials;
+    IterState* st;
+    double* err_hist;
+    int role, stop_rule, max_iter;
+    double tol;
+    const double* stats;
+};
+hipError_t launch_dense_half(int precision, const DenseArgs& a, void* part, hipStream_t st);
+int dense_blocks(int64_t nlines);
+size_t dense_partial_bytes(int64_t nl, int64_t no);
+struct DenseObjArgs {
+    const double* x;
+    const double* y;
+    int64_t n, m;
+    int d;
+    double inv_cmax, eps;
+    const void* u;
+    const void* v;
+    const double* a;
+    const double* b;
+    int uot, precision;
+    double* partials;
+    double* rowsum;       // n
+    double* colsum;       // m (written by the column pass)
+    IterState* st;
+    double* stats;
+    const double* statsc;
+};
+hipError_t launch_dense_objective(const DenseObjArgs& a, hipStream_t st);
+
+}  // namespace ss

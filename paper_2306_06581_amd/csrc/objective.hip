@@ -1,0 +1,138 @@
+// Estimate of Alg. 3 / Alg. 4 on the returned iterate, in FP64:
+//   <T~, C> - eps H(T~)  (+ lam KL(T~ 1 | a) + lam KL(T~' 1 | b) for UOT),
+// with T~_ij = u_i K~_ij v_j over the kept entries, C recomputed from the
+// coordinates, 0 log 0 = 0 (Sec. 2 notation).  Rows pass: transport term,
+// entropy term, sparse-problem term sum T~ (log u_i + log v_j - 1) and the
+// row KL; columns pass: the column KL.  Deterministic block reductions.
+#include <math.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ss {
+
+constexpr int kObjLanes = 16;
+
+template <int PREC>
+__device__ __forceinline__ double scal_log(const void* p, int64_t i) {
+    if (PREC == P_LOG) return ((const double*)p)[i];
+    if (PREC == P_F64) return log(((const double*)p)[i]);
+    return log((double)((const float*)p)[i]);
+}
+
+template <int PREC>
+__device__ __forceinline__ double scal_lin(const void* p, int64_t i) {
+    if (PREC == P_LOG) return exp(((const double*)p)[i]);
+    if (PREC == P_F64) return ((const double*)p)[i];
+    return (double)((const float*)p)[i];
+}
+
+// T~ entry from the line scaling, the stored value and the other scaling.
+template <int PREC>
+__device__ __forceinline__ double plan_entry(double yl_lin, double yl_log, const void* val, int64_t k,
+                                             const void* zs, int64_t o) {
+    if (PREC == P_LOG) return exp(yl_log + (double)((const float*)val)[k] + ((const double*)zs)[o]);
+    if (PREC == P_F64) return yl_lin * ((const double*)val)[k] * ((const double*)zs)[o];
+    return yl_lin * (double)((const float*)val)[k] * (double)((const float*)zs)[o];
+}
+
+template <int PREC, int D>
+__global__ __launch_bounds__(256) void k_objective(ObjArgs A) {
+    __shared__ double sh[4];
+    __shared__ int is_last;
+    const int tid = threadIdx.x, sub = tid % kObjLanes;
+    const int64_t line = (int64_t)blockIdx.x * (kBlock / kObjLanes) + tid / kObjLanes;
+    double s_tc = 0.0, s_ent = 0.0, s_sp = 0.0, s_line = 0.0;
+    if (line < A.nlines) {
+        const int64_t k0 = A.ptr[line], k1 = A.ptr[line + 1];
+        const double yl = scal_lin<PREC>(A.ys, line);
+        const double ylog = scal_log<PREC>(A.ys, line);
+        const double* xl = A.x + line * A.d;
+        for (int64_t k = k0 + sub; k < k1; k += kObjLanes) {
+            const int64_t o = A.idx[k];
+            const double t = plan_entry<PREC>(yl, ylog, A.val, k, A.zs, o);
+            s_line += t;
+            if (A.role == 0 && t > 0.0) {
+                const double c = sqdist<D>(xl, A.y + o * A.d, A.d) * A.inv_cmax;
+                s_tc += t * c;
+                const double lt = log(t);
+                s_ent += t * (lt - 1.0);
+                s_sp += t * ((ylog + scal_log<PREC>(A.zs, o)) - 1.0);
+            }
+        }
+    }
+    s_tc = group_sum<kObjLanes>(s_tc);
+    s_ent = group_sum<kObjLanes>(s_ent);
+    s_sp = group_sum<kObjLanes>(s_sp);
+    s_line = group_sum<kObjLanes>(s_line);
+    double kl = 0.0;
+    if (sub == 0 && line < A.nlines && A.uot) {
+        const double m = A.marg[line];
+        kl = (s_line > 0.0 ? s_line * log(s_line / m) : 0.0) - s_line + m;
+    }
+    if (sub != 0) s_tc = s_ent = s_sp = s_line = 0.0;
+    double q[5] = {s_tc, s_ent, s_sp, kl, s_line};
+    double tot[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) tot[r] = block_sum256(q[r], sh);
+    const unsigned nb = gridDim.x;
+    if (tid == 0) {
+#pragma unroll
+        for (int r = 0; r < 5; ++r) A.partials[(int64_t)r * nb + blockIdx.x] = tot[r];
+        __threadfence();
+        const unsigned tk = atomicAdd(&A.st->ticket[2 + A.role], 1u);
+        is_last = (tk == nb - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    double fin[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        double v = 0.0;
+        for (unsigned b = tid; b < nb; b += kBlock) v += load_agent(&A.partials[(int64_t)r * nb + b]);
+        fin[r] = block_sum256(v, sh);
+    }
+    if (tid == 0) {
+        A.st->ticket[2 + A.role] = 0;
+        if (A.role == 0) {
+            A.stats[ST_TRANSPORT] = fin[0];
+            A.stats[ST_NEGENT] = fin[1];
+            A.stats[ST_SPARSEOBJ] = fin[2];
+            A.stats[ST_KL_A] = fin[3];
+            A.stats[ST_ROWSUM] = fin[4];
+        } else {
+            A.stats[ST_KL_B] = fin[3];
+            A.stats[ST_COLSUM] = fin[4];
+        }
+    }
+}
+
+template <int PREC, int D>
+static void run_obj(const ObjArgs& a, hipStream_t st) {
+    const int nb = (int)((a.nlines + (kBlock / kObjLanes) - 1) / (kBlock / kObjLanes));
+    hipLaunchKernelGGL((k_objective<PREC, D>), dim3(nb), dim3(kBlock), 0, st, a);
+}
+
+template <int D>
+static void run_obj_d(int precision, const ObjArgs& a, hipStream_t st) {
+    if (precision == P_F64)
+        run_obj<P_F64, D>(a, st);
+    else if (precision == P_F32)
+        run_obj<P_F32, D>(a, st);
+    else
+        run_obj<P_LOG, D>(a, st);
+}
+
+hipError_t launch_objective(int precision, const ObjArgs& a, hipStream_t st) {
+    if (a.nlines <= 0) return hipSuccess;
+    switch (a.d) {
+        case 2: run_obj_d<2>(precision, a, st); break;
+        case 3: run_obj_d<3>(precision, a, st); break;
+        case 10: run_obj_d<10>(precision, a, st); break;
+        default: run_obj_d<0>(precision, a, st); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -1,0 +1,165 @@
+"""Host-only checks of the C ABI: the library loads, exports every function the
+header declares, its structs have the header's layout (checked against a C
+program compiled from the header), and argument errors are reported before
+any device work.  No GPU needed."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sparsink.h")
+LIB = os.path.join(ROOT, "paper_2306_06581_amd", "libsparsink.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libsparsink.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    names = declared_functions()
+    assert len(names) >= 8
+    missing = [nme for nme in names if nme not in exported]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2306_06581_amd import native as N
+    assert sorted(N.SIGNATURES) == declared_functions()
+    assert N.lib.ss_version() == 100
+
+
+def _c_layout():
+    src = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "sparsink.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("ss_problem %zu\nss_options %zu\nss_result %zu\nss_sparse %zu\n",
+         sizeof(ss_problem), sizeof(ss_options), sizeof(ss_result), sizeof(ss_sparse));
+  P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist)
+  P(ss_result, nnz) P(ss_result, iters) P(ss_result, t_obj_ms) P(ss_sparse, capacity)
+  P(ss_sparse, z_norm)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as td:
+        c = os.path.join(td, "layout.c")
+        exe = os.path.join(td, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    return {k: int(v) for k, v in (line.split() for line in out.strip().splitlines())}
+
+
+def test_struct_layout_matches_header():
+    from paper_2306_06581_amd import native as N
+    lay = _c_layout()
+    assert ctypes.sizeof(N.SsProblem) == lay["ss_problem"]
+    assert ctypes.sizeof(N.SsOptions) == lay["ss_options"]
+    assert ctypes.sizeof(N.SsResult) == lay["ss_result"]
+    assert ctypes.sizeof(N.SsSparse) == lay["ss_sparse"]
+    assert N.SsProblem.x.offset == lay["ss_problem.x"]
+    assert N.SsOptions.seed.offset == lay["ss_options.seed"]
+    assert N.SsOptions.init_log_u.offset == lay["ss_options.init_log_u"]
+    assert N.SsOptions.err_hist.offset == lay["ss_options.err_hist"]
+    assert N.SsResult.nnz.offset == lay["ss_result.nnz"]
+    assert N.SsResult.iters.offset == lay["ss_result.iters"]
+    assert N.SsResult.t_obj_ms.offset == lay["ss_result.t_obj_ms"]
+    assert N.SsSparse.capacity.offset == lay["ss_sparse.capacity"]
+    assert N.SsSparse.z_norm.offset == lay["ss_sparse.z_norm"]
+
+
+def _fake_problem(N, n=8, m=8, d=2):
+    # non-null dummy device pointers: argument checks never dereference them
+    return N.SsProblem(n, m, d, 0, 256, 512, 768, 1024)
+
+
+@pytest.mark.parametrize("field,value", [("n", 0), ("m", -3), ("d", 0), ("d", 65)])
+def test_bad_sizes_rejected(field, value):
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd.api import make_options
+    p = _fake_problem(N)
+    setattr(p, field, value)
+    out = ctypes.c_size_t(0)
+    rc = N.lib.ss_workspace_size(ctypes.byref(p), ctypes.byref(make_options(0.1, 10.0)),
+                                 ctypes.byref(out))
+    assert rc == N.SS_E_INVALID_ARG
+    assert N.lib.ss_last_error().decode()
+
+
+@pytest.mark.parametrize("kw", [dict(eps=0.0), dict(eps=-1.0), dict(eps=math.nan),
+                                dict(s=0.0), dict(tol=-1.0), dict(max_iter=0),
+                                dict(lanes_per_row=12), dict(lam=0.0)])
+def test_bad_options_rejected(kw):
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd.api import make_options
+    base = dict(eps=0.1, s=10.0)
+    base.update(kw)
+    out = ctypes.c_size_t(0)
+    rc = N.lib.ss_workspace_size(ctypes.byref(_fake_problem(N)), ctypes.byref(make_options(**base)),
+                                 ctypes.byref(out))
+    assert rc == N.SS_E_INVALID_ARG
+
+
+def test_null_pointers_and_workspace_errors():
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd.api import make_options
+    res = N.SsResult()
+    opts = make_options(0.1, 10.0)
+    p = _fake_problem(N)
+    p.a = None
+    assert N.lib.spar_sink_ot(ctypes.byref(p), ctypes.byref(opts), None, 0, None,
+                              ctypes.byref(res)) == N.SS_E_INVALID_ARG
+    p = _fake_problem(N)
+    assert N.lib.spar_sink_ot(ctypes.byref(p), ctypes.byref(opts), None, 0, None,
+                              ctypes.byref(res)) == N.SS_E_WORKSPACE
+    assert N.lib.spar_sink_ot(ctypes.byref(p), ctypes.byref(opts), ctypes.c_void_p(4096 + 8), 1 << 30,
+                              None, ctypes.byref(res)) == N.SS_E_WORKSPACE    # misaligned
+    assert N.lib.spar_sink_ot(ctypes.byref(p), ctypes.byref(opts), ctypes.c_void_p(4096), 16,
+                              None, ctypes.byref(res)) == N.SS_E_WORKSPACE    # too small
+    # OT entry point refuses a finite lambda, UOT refuses an infinite one
+    uot = make_options(0.1, 10.0, lam=1.0)
+    assert N.lib.spar_sink_ot(ctypes.byref(p), ctypes.byref(uot), ctypes.c_void_p(4096), 1 << 40,
+                              None, ctypes.byref(res)) == N.SS_E_INVALID_ARG
+    assert N.lib.spar_sink_uot(ctypes.byref(p), ctypes.byref(opts), ctypes.c_void_p(4096), 1 << 40,
+                               None, ctypes.byref(res)) == N.SS_E_INVALID_ARG
+    # dense is limited to d <= 16
+    p = _fake_problem(N, d=17)
+    assert N.lib.dense_sinkhorn(ctypes.byref(p), ctypes.byref(opts), ctypes.c_void_p(4096), 1 << 40,
+                                None, ctypes.byref(res)) == N.SS_E_INVALID_ARG
+
+
+def test_workspace_grows_with_problem():
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd.api import make_options
+    sizes = []
+    for n in (64, 1024, 4096):
+        out = ctypes.c_size_t(0)
+        rc = N.lib.ss_workspace_size(ctypes.byref(_fake_problem(N, n, n)),
+                                     ctypes.byref(make_options(0.1, 8 * n * math.log(n))),
+                                     ctypes.byref(out))
+        assert rc == 0
+        sizes.append(out.value)
+    assert sizes[0] < sizes[1] < sizes[2]
+    # the mask dominates: at least n*m/8 bytes twice (mask and its transpose)
+    assert sizes[2] >= 2 * 4096 * 4096 // 8
+
+
+def test_status_strings():
+    from paper_2306_06581_amd import native as N
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert N.lib.ss_status_string(code).decode() != "unknown status"
+    assert N.lib.ss_status_string(99).decode() == "unknown status"

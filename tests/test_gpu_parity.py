@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Bars: integer/index/bit outputs bit-exact; FP64 scalings and estimates within
+1e-10 relative; FP32 and log-FP32 estimates within 1e-4 relative of the FP64
+oracle.  For UOT the keep decision depends on exponentials (host libm vs
+device library, which may differ in the last bit) and on a normaliser summed
+in a different order, so any differing mask bit must sit on the decision
+boundary: |U - p*| <= 1e-12 p* (probability ~1e-15 per kept entry)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sparsink_oracle as O
+from paper_2306_06581_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_06581_amd import api as A
+    return A
+
+
+def _oopt(p, **kw):
+    base = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, problem_index=p.problem_index)
+    base.update(kw)
+    return O.Options(**base)
+
+
+def _prob(api, p):
+    return api.Problem(p.x, p.y, p.a, p.b, problem_index=p.problem_index)
+
+
+def _kw(p, **kw):
+    base = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed)
+    base.update(kw)
+    return base
+
+
+def _mask_np(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def _check_sketch_structure(g, sk):
+    assert g["nnz"] == sk.nnz
+    assert np.array_equal(_mask_np(g["mask"]), sk.mask)
+    assert np.array_equal(g["row_ptr"].cpu().numpy(), sk.row_ptr)
+    assert np.array_equal(g["col_idx"].cpu().numpy(), sk.col_idx)
+    assert np.array_equal(g["col_ptr"].cpu().numpy(), sk.col_ptr)
+    assert np.array_equal(g["row_idx"].cpu().numpy(), sk.row_idx)
+
+
+OT_CASES = [
+    ("ot_gauss2d_n1024", lambda: W.ot_gauss2d(1024, seed=0)),
+    ("ragged_300x333_d2", lambda: W.ot_gauss2d(300, seed=3, m=333)),
+    ("ot_t5_d10_n700", lambda: W.ot_t5_d10(700, seed=1, s_factor=4.0)),
+    ("tiny_5x7", lambda: W.ot_gauss2d(5, seed=2, m=7)),
+    ("single_1x1", lambda: W.ot_gauss2d(1, seed=4)),
+]
+
+
+@pytest.mark.parametrize("name,make", OT_CASES)
+def test_sample_ot_bit_exact(api, name, make):
+    p = make()
+    if p.n == 1:
+        p.s = 1.0
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    _check_sketch_structure(g, sk)
+    # sqrt and the tree sums are exact operations: the p* factors match bitwise
+    assert np.array_equal(g["row_fac"].cpu().numpy(), sk.prob.alpha)
+    assert np.array_equal(g["col_fac"].cpu().numpy(), sk.prob.rb)
+    assert g["cmax"] == sk.cmax
+    # values: K / p* with K = exp(-C/eps) (host and device exp may differ by an ulp)
+    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=4e-16 * 8, atol=0)
+    np.testing.assert_allclose(g["val_t"].cpu().numpy(), sk.val_t, rtol=4e-16 * 8, atol=0)
+
+
+def test_sample_precisions_share_the_mask(api):
+    p = W.ot_gauss2d(512, seed=5)
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    g32 = api.ss_sample(_prob(api, p), **_kw(p), precision="f32")
+    glog = api.ss_sample(_prob(api, p), **_kw(p), precision="f32_log")
+    for g in (g32, glog):
+        _check_sketch_structure(g, sk)
+    # FP32 value = round-to-nearest of the FP64 value (allow the FP64 ulp wobble)
+    np.testing.assert_allclose(g32["val"].cpu().numpy(), sk.val.astype(np.float32), rtol=1.2e-7)
+    np.testing.assert_allclose(glog["val"].cpu().numpy(), sk.logval.astype(np.float32),
+                               rtol=1.2e-7, atol=1e-6)
+
+
+def _uot_mask_compare(g_mask, sk, p, rows):
+    """Equal bits, or differing bits on the decision boundary only."""
+    gm = g_mask[rows]
+    om = sk.mask[rows]
+    diff = gm ^ om
+    if not diff.any():
+        return 0
+    bits = np.unpackbits(diff.view(np.uint8), axis=1, bitorder="little")[:, : p.m]
+    rr, cc = np.nonzero(bits)
+    rr = np.asarray(rows)[rr]
+    u = O.uniform01(rr, cc, p.problem_index, p.seed)
+    pst = sk.prob.pstar(rr, cc)
+    pst = pst[np.arange(len(rr)), np.arange(len(rr))] if pst.ndim == 2 else pst
+    assert np.all(np.abs(u - pst) <= 1e-12 * pst), (rr, cc)
+    return len(rr)
+
+
+@pytest.mark.parametrize("n,eps", [(600, 0.05), (513, 0.01)])
+def test_sample_uot(api, n, eps):
+    p = W.uot_mix3(n, seed=7, eps=eps)
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
+    nd = _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
+    if nd == 0:
+        _check_sketch_structure(g, sk)
+        np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-14)
+    np.testing.assert_allclose(g["row_fac"].cpu().numpy(), sk.prob.la, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- Sinkhorn loop
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("name,make", OT_CASES[:3])
+def test_spar_sink_ot_f64_fixed_iterations(api, name, make):
+    p = make()
+    T = 40
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=T))
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=0.0, max_iter=T), precision="f64",
+                         return_scalings=True, return_hist=True)
+    assert g.status == 1 and g.iters == T == o.sinkhorn.iters
+    assert g.nnz == o.nnz and g.empty_rows == o.empty_rows and g.empty_cols == o.empty_cols
+    np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(g.v.cpu().numpy(), o.sinkhorn.v, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(g.err_hist.cpu().numpy(), np.array(o.sinkhorn.hist), rtol=1e-6,
+                               atol=1e-15)
+    assert _rel(g.estimate, o.estimate.estimate) < 1e-10
+    assert _rel(g.sparse_objective, o.estimate.sparse_objective) < 1e-10
+    assert _rel(g.transport, o.estimate.transport) < 1e-10
+    assert g.dropped_mass_a == pytest.approx(o.dropped_a, rel=1e-12, abs=1e-300)
+
+
+def test_spar_sink_ot_f64_to_tolerance(api):
+    p = W.ot_gauss2d(1024, seed=0)
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=1e-8, max_iter=500))
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=1e-8, max_iter=500), precision="f64")
+    assert g.status == 0 and abs(g.iters - o.sinkhorn.iters) <= 1
+    assert g.marginal_err <= 1e-8
+    assert _rel(g.estimate, o.estimate.estimate) < 1e-9
+
+
+@pytest.mark.parametrize("stop_rule", ["marginal", "delta"])
+def test_spar_sink_uot_f64(api, stop_rule):
+    p = W.uot_mix3(700, seed=9, eps=0.05)
+    T = 60
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=T, stop_rule=stop_rule))
+    g = api.spar_sink_uot(_prob(api, p), **_kw(p, tol=0.0, max_iter=T, stop_rule=stop_rule),
+                          precision="f64", return_scalings=True)
+    assert g.iters == T
+    np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(g.v.cpu().numpy(), o.sinkhorn.v, rtol=1e-10, atol=0)
+    assert _rel(g.estimate, o.estimate.estimate) < 1e-10
+    assert _rel(g.kl_a, o.estimate.kl_a) < 1e-10 and _rel(g.kl_b, o.estimate.kl_b) < 1e-10
+    assert _rel(g.marginal_err, o.sinkhorn.err) < 1e-6
+
+
+@pytest.mark.parametrize("precision", ["f32", "f32_log"])
+def test_spar_sink_ot_reduced_precision(api, precision):
+    p = W.ot_t5_d10(2048, seed=2)
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=1e-6, max_iter=2000))
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=1e-6, max_iter=2000), precision=precision)
+    assert g.status == 0 and g.marginal_err <= 1e-6
+    assert _rel(g.estimate, o.estimate.estimate) < 1e-4
+    assert _rel(g.sparse_objective, o.estimate.sparse_objective) < 1e-4
+
+
+@pytest.mark.parametrize("eps", [0.05, 0.01])
+def test_spar_sink_uot_log_domain(api, eps):
+    p = W.uot_mix3(1500, seed=11, eps=eps)
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=1e-6, max_iter=3000, log_domain=True))
+    g = api.spar_sink_uot(_prob(api, p), **_kw(p, tol=1e-6, max_iter=3000), precision="f32_log")
+    assert g.status == 0 and g.marginal_err <= 1e-6
+    assert abs(g.iters - o.sinkhorn.iters) <= max(2, 0.02 * o.sinkhorn.iters)
+    assert _rel(g.estimate, o.estimate.estimate) < 1e-4
+
+
+# ---------------------------------------------------------------- dense baseline
+@pytest.mark.parametrize("lam", [math.inf, 1.0])
+def test_dense_f64(api, lam):
+    p = W.uot_mix3(400, seed=12, eps=0.05) if math.isfinite(lam) else W.ot_gauss2d(500, seed=12)
+    T = 30
+    o = O.dense_sinkhorn(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=T, lam=lam))
+    g = api.dense_sinkhorn(_prob(api, p), **_kw(p, tol=0.0, max_iter=T, lam=lam), precision="f64",
+                           return_scalings=True)
+    assert g.iters == T and g.nnz == p.n * p.m
+    np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-10)
+    np.testing.assert_allclose(g.v.cpu().numpy(), o.sinkhorn.v, rtol=1e-10)
+    assert _rel(g.estimate, o.estimate.estimate) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["f32", "f32_log"])
+def test_dense_reduced_precision(api, precision):
+    p = W.ot_gauss2d(1024, seed=13)
+    o = O.dense_sinkhorn(p.x, p.y, p.a, p.b, _oopt(p, tol=1e-6, max_iter=1000))
+    g = api.dense_sinkhorn(_prob(api, p), **_kw(p, tol=1e-6, max_iter=1000), precision=precision)
+    assert g.status == 0 and g.marginal_err <= 1e-6
+    assert _rel(g.estimate, o.estimate.estimate) < 1e-4
+
+
+# ---------------------------------------------------------------- edge cases
+def test_empty_rows_renormalised(api):
+    p = W.ot_gauss2d(400, seed=14)
+    p.s = 2.0 * 400   # ~2 entries per row: many empty lines
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=20))
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=0.0, max_iter=20), precision="f64",
+                         return_scalings=True)
+    assert o.empty_rows > 0 and g.empty_rows == o.empty_rows and g.empty_cols == o.empty_cols
+    assert g.dropped_mass_a == pytest.approx(o.dropped_a, rel=1e-12)
+    np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-10, atol=0)
+
+
+def test_fail_policy_and_bad_inputs(api):
+    from paper_2306_06581_amd import native as N
+    p = W.ot_gauss2d(400, seed=15)
+    p.s = 400.0
+    with pytest.raises(N.SparSinkError) as ei:
+        api.spar_sink_ot(_prob(api, p), **_kw(p), empty_policy="fail")
+    assert ei.value.code == N.SS_E_EMPTY
+    q = W.ot_gauss2d(64, seed=16)
+    q.a[3] = -1.0
+    with pytest.raises(N.SparSinkError) as ei:
+        api.spar_sink_ot(_prob(api, q), **_kw(q))
+    assert ei.value.code == N.SS_E_INVALID_ARG
+    q = W.ot_gauss2d(64, seed=16)
+    q.x[5, 1] = math.nan
+    with pytest.raises(N.SparSinkError) as ei:
+        api.spar_sink_ot(_prob(api, q), **_kw(q))
+    assert ei.value.code == N.SS_E_INVALID_ARG
+
+
+def test_max_iter_one_and_determinism(api):
+    p = W.ot_gauss2d(1024, seed=17)
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=1e-12, max_iter=1))
+    assert g.status == 1 and g.iters == 1
+    r1 = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=1e-9), precision="f32", return_scalings=True)
+    r2 = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=1e-9), precision="f32", return_scalings=True,
+                          graph_iters=-1)
+    assert r1.iters == r2.iters and r1.estimate == r2.estimate
+    assert torch.equal(r1.u, r2.u) and torch.equal(r1.v, r2.v)
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
+def test_lane_schedules_agree(api, lanes):
+    p = W.ot_gauss2d(777, seed=18, m=901)
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=15))
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=0.0, max_iter=15), precision="f64",
+                         lanes_per_row=lanes, return_scalings=True)
+    np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-11)
+
+
+def test_warm_start_from_solution_converges_immediately(api):
+    p = W.ot_gauss2d(1024, seed=19)
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=1e-10, max_iter=500), return_scalings=True)
+    w = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=1e-10, max_iter=500),
+                         init_log_u=torch.log(g.u), init_log_v=torch.log(g.v))
+    assert w.iters <= 2 and w.status == 0
