@@ -89,7 +89,10 @@ typedef struct ss_problem {
  * empty_policy rows/columns of K~ with no entry: AUTO = RENORMALIZE for OT
  *              (a, b rescaled to mass 1 on the non-empty support), ZERO for UOT
  *              (u_i = 0, the sparse UOT optimum); FAIL returns SS_E_EMPTY.
- * lanes_per_row  sparse-product schedule: 0 = automatic, else one of 4..64.
+ * block_threads  sparse-product schedule: threads per block of the iteration
+ *              kernel (each block owns block_threads/4 lines and sweeps the
+ *              gathered vector through LDS in 128 KB (1024) or 32 KB (256)
+ *              slices); 0 = automatic, else 256 or 1024.
  * graph_iters  iterations per captured HIP graph; 0 = automatic, < 0 = plain
  *              launches.
  * init_log_u, init_log_v  optional device FP64 warm start (log u^0, log v^0).
@@ -100,7 +103,7 @@ typedef struct ss_options {
     double eps, lambda, s, tol;
     uint64_t seed;
     int32_t max_iter, precision, cost, stop_rule, empty_policy;
-    int32_t lanes_per_row, graph_iters, reserved0;
+    int32_t block_threads, graph_iters, reserved0;
     const double *init_log_u, *init_log_v;
     double *u_out, *v_out, *err_hist;
 } ss_options;

@@ -44,7 +44,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t mask, maskT, row_cnt, col_cnt, row_ptr, col_ptr, scan, col_idx, row_idx, val, val_t;
     size_t row_fac, col_fac, row_bnd, col_bnd, a_eff, b_eff, tmp, tree, u[2], v[2];
-    size_t partials, state, stats, hstage, dense_part, rowsum, colsum;
+    size_t partials, loop_part[2], split[2], state, stats, hstage, dense_part, rowsum, colsum;
+    int64_t loop_part_len;
     size_t total;
     int64_t cap;
     int64_t partials_len;
@@ -79,10 +80,12 @@ Layout plan(const ss_problem* P, const ss_options* O) {
     L.row_ptr = take((size_t)(n + 1) * 8);
     L.col_ptr = take((size_t)(m + 1) * 8);
     L.scan = take((size_t)((nm + 1023) / 1024 + 1) * 8);
-    L.col_idx = take((size_t)L.cap * 4);
-    L.row_idx = take((size_t)L.cap * 4);
-    L.val = take((size_t)L.cap * esize(O->precision));
-    L.val_t = take((size_t)L.cap * esize(O->precision));
+    // entry arrays carry 16 entries of padding: the iteration kernel reads
+    // whole 16-byte quads around each line
+    L.col_idx = take((size_t)(L.cap + 16) * 4);
+    L.row_idx = take((size_t)(L.cap + 16) * 4);
+    L.val = take((size_t)(L.cap + 16) * esize(O->precision));
+    L.val_t = take((size_t)(L.cap + 16) * esize(O->precision));
     L.row_fac = take((size_t)n * 8);
     L.col_fac = take((size_t)m * 8);
     L.row_bnd = take((size_t)n * 8);
@@ -104,6 +107,16 @@ Layout plan(const ss_problem* P, const ss_options* O) {
     pl += 8 * ((nm + 255) / 256) + 3 * 4096 + 64;
     L.partials_len = pl;
     L.partials = take((size_t)pl * 8);
+    L.loop_part_len = ((nm + 255) / 256 > kMaxLoopBlocks ? (nm + 255) / 256 : kMaxLoopBlocks) + 64;
+    L.loop_part[0] = take((size_t)L.loop_part_len * 8);
+    L.loop_part[1] = take((size_t)L.loop_part_len * 8);
+    // slice split points of every line (at most the 256-thread slice size)
+    {
+        const int64_t sl = 32768 / 8;  // smallest slice: 32 KB of FP64
+        L.split[0] = take((size_t)n * (size_t)((m + sl - 1) / sl + 1) * 4);
+        L.split[1] = take((size_t)m * (size_t)((n + sl - 1) / sl + 1) * 4);
+    }
+
     L.state = take(sizeof(IterState));
     L.stats = take(ST_COUNT * 8);
     L.hstage = take(64);
@@ -141,10 +154,18 @@ int check_args(const ss_problem* P, const ss_options* O, bool dense) {
         return fail(SS_E_INVALID_ARG, "unknown stop rule %d", O->stop_rule);
     if (O->empty_policy < SS_EMPTY_AUTO || O->empty_policy > SS_EMPTY_FAIL)
         return fail(SS_E_INVALID_ARG, "unknown empty policy %d", O->empty_policy);
-    const int l = O->lanes_per_row;
-    if (!(l == 0 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64))
-        return fail(SS_E_INVALID_ARG, "lanes_per_row must be 0, 4, 8, 16, 32 or 64");
+    const int bt = O->block_threads;
+    if (!(bt == 0 || bt == 256 || bt == 1024))
+        return fail(SS_E_INVALID_ARG, "block_threads must be 0, 256 or 1024");
     if (!(O->lambda > 0.0)) return fail(SS_E_INVALID_ARG, "lambda must be > 0 (or +INFINITY)");
+    if (!dense) {
+        // the sparse iteration cuts the gathered vector into at most a fixed
+        // number of LDS slices
+        const int pr = O->precision == SS_F64 ? P_F64 : O->precision == SS_F32 ? P_F32 : P_LOG;
+        const int bu = bt ? bt : iterate_block_size(P->n), bv = bt ? bt : iterate_block_size(P->m);
+        if (iterate_lines_per_step(pr, bu, P->m) == 0 || iterate_lines_per_step(pr, bv, P->n) == 0)
+            return fail(SS_E_INVALID_ARG, "n or m too large for block_threads %d", bt);
+    }
     return SS_OK;
 }
 
@@ -177,14 +198,6 @@ struct Timer {
         return t;
     }
 };
-
-int auto_lanes(double avg) {
-    if (avg <= 6) return 4;
-    if (avg <= 14) return 8;
-    if (avg <= 40) return 16;
-    if (avg <= 100) return 32;
-    return 64;
-}
 
 // Runs the Sinkhorn loop: `iter(k, stream)` enqueues iteration k (its
 // ping-pong parity is k & 1).  With graph_iters > 0 an even number of
@@ -448,11 +461,25 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     HIP_TRY(launch_init_scaling(prec, v[0], O->init_log_v, m, c.st));
     IterState* d_state = at<IterState>(ws, c.L.state);
     const double theta = uot ? O->lambda / (O->lambda + O->eps) : 1.0;
-    const int lanes = O->lanes_per_row ? O->lanes_per_row
-                                       : auto_lanes((double)c.nnz / (double)(n < m ? n : m));
+    HIP_TRY(iterate_init());
+    const int bs_u = O->block_threads ? O->block_threads : iterate_block_size(n);
+    const int bs_v = O->block_threads ? O->block_threads : iterate_block_size(m);
+    const int ns_u = iterate_slices(prec, bs_u, m), ns_v = iterate_slices(prec, bs_v, n);
+    const int rps_u = iterate_lines_per_step(prec, bs_u, m);
+    const int rps_v = iterate_lines_per_step(prec, bs_v, n);
+    int32_t* split_u = at<int32_t>(ws, c.L.split[0]);
+    int32_t* split_v = at<int32_t>(ws, c.L.split[1]);
+    HIP_TRY(launch_split(at<int64_t>(ws, c.L.row_ptr), at<int32_t>(ws, c.L.col_idx), n, ns_u,
+                         slice_elems(prec, bs_u), split_u, c.st));
+    HIP_TRY(launch_split(at<int64_t>(ws, c.L.col_ptr), at<int32_t>(ws, c.L.row_idx), m, ns_v,
+                         slice_elems(prec, bs_v), split_v, c.st));
     IterArgs ua[2], va[2];
     for (int k = 0; k < 2; ++k) {
         IterArgs a;
+        a.nx = m;
+        a.split = split_u;
+        a.nslices = ns_u;
+        a.lines_per_step = rps_u;
         a.ptr = at<int64_t>(ws, c.L.row_ptr);
         a.idx = at<int32_t>(ws, c.L.col_idx);
         a.val = at<void>(ws, c.L.val);
@@ -462,7 +489,9 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.yout = u[(k + 1) & 1];
         a.yprev = u[k];
         a.theta = theta;
-        a.partials = at<double>(ws, c.L.partials);
+        a.partials = at<double>(ws, c.L.loop_part[0]);
+        a.prev_partials = at<double>(ws, c.L.loop_part[1]);
+        a.prev_nblocks = iterate_blocks(m, rps_v);
         a.st = d_state;
         a.err_hist = O->err_hist;
         a.role = 0;
@@ -470,6 +499,13 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.max_iter = O->max_iter;
         a.tol = O->tol;
         ua[k] = a;
+        a.partials = at<double>(ws, c.L.loop_part[1]);
+        a.prev_partials = at<double>(ws, c.L.loop_part[0]);
+        a.prev_nblocks = iterate_blocks(n, rps_u);
+        a.nx = n;
+        a.split = split_v;
+        a.nslices = ns_v;
+        a.lines_per_step = rps_v;
         a.ptr = at<int64_t>(ws, c.L.col_ptr);
         a.idx = at<int32_t>(ws, c.L.row_idx);
         a.val = at<void>(ws, c.L.val_t);
@@ -482,8 +518,8 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         va[k] = a;
     }
     auto iter = [&](int k, hipStream_t s) -> hipError_t {
-        hipError_t e = launch_iterate(prec, lanes, ua[k & 1], s);
-        if (e == hipSuccess) e = launch_iterate(prec, lanes, va[k & 1], s);
+        hipError_t e = launch_iterate(prec, bs_u, ua[k & 1], s);
+        if (e == hipSuccess) e = launch_iterate(prec, bs_v, va[k & 1], s);
         return e;
     };
     if (time_iters > 0) {
@@ -688,7 +724,9 @@ int dense_sinkhorn(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.yout = u[(k + 1) & 1];
         a.yprev = u[k];
         a.theta = theta;
-        a.partials = at<double>(ws, c.L.partials);
+        a.partials = at<double>(ws, c.L.loop_part[0]);
+        a.prev_partials = at<double>(ws, c.L.loop_part[1]);
+        a.prev_nblocks = dense_blocks(m);
         a.st = d_state;
         a.err_hist = O->err_hist;
         a.role = 0;
@@ -697,6 +735,9 @@ int dense_sinkhorn(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.tol = O->tol;
         a.stats = at<double>(ws, c.L.stats);
         ua[k] = a;
+        a.partials = at<double>(ws, c.L.loop_part[1]);
+        a.prev_partials = at<double>(ws, c.L.loop_part[0]);
+        a.prev_nblocks = dense_blocks(n);
         a.xl = P->y;
         a.xo = P->x;
         a.nl = m;

@@ -117,6 +117,32 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
     return r;
 }
 
+// Sum over a block of any size (up to 16 waves) in a fixed tree; result valid
+// in every thread.  sh: at least 16 doubles of LDS.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = group_sum<kWave>(v);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < nw; ++w) r += sh[w];
+    return r;
+}
+
+__device__ __forceinline__ int block_max_int(int v, int* sh) {
+    v = group_max<kWave>(v);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    int r = sh[0];
+    for (int w = 1; w < nw; ++w) r = sh[w] > r ? sh[w] : r;
+    return r;
+}
+
 // Inclusive prefix sum of an int over the wave.
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
     const int lane = threadIdx.x & (kWave - 1);

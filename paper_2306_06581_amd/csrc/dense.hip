@@ -6,7 +6,7 @@
 //                    of 256 and every thread keeps R lines in registers.
 //   k_dense_finish:  one thread per line sums its segment partials in order,
 //                    applies the scaling update and the residual, and the
-//                    ticketed last block closes the iteration.
+//                    next launch's block 0 closes the iteration.
 // FP32 mode: FP32 coordinates (converted on load), one v_exp_f32 per entry.
 // LOG mode: stabilised streaming log-sum-exp, FP64 potentials, FP32 exp.
 // FP64 mode: everything FP64 (small problems, parity).
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_dense_partial(DensePartial P) {
     constexpr int R = DenseT<PREC>::R;
     constexpr int DD = D > 0 ? D : 16;
     const DenseArgs& A = P.a;
-    if (iteration_begin(A.st, A.role, A.stop_rule == 0, A.max_iter) == 0) return;
+    if (loop_peek(A.st, A.role, A.stop_rule == 0, A.max_iter) == 0) return;
     __shared__ Cf ys[kDenseTile * DD];
     __shared__ double vs[kDenseTile];
     const int d = D > 0 ? D : A.d;
@@ -147,9 +147,11 @@ __global__ __launch_bounds__(256) void k_dense_partial(DensePartial P) {
 
 template <int PREC, bool UOT>
 __global__ __launch_bounds__(256) void k_dense_finish(DensePartial P) {
+    __shared__ double sh[4];
     const DenseArgs& A = P.a;
     const int marginal = A.stop_rule == 0;
-    const int t = iteration_begin(A.st, A.role, marginal, A.max_iter);
+    const int t = loop_enter(A.st, A.role, marginal, A.max_iter, A.tol, A.prev_partials,
+                             A.prev_nblocks, A.err_hist);
     if (t == 0) return;
     const int64_t line = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double res = 0.0;
@@ -172,10 +174,13 @@ __global__ __launch_bounds__(256) void k_dense_finish(DensePartial P) {
             }
             w = (M == -INFINITY || !(S > 0.0f)) ? -INFINITY : M + log((double)S);
         }
-        res = line_update<PREC, UOT>(A.role, marginal, t, A.no > 0, A.marg[line], A.theta, A.yprev,
+        const double yp = PREC == P_F32 ? (double)((const float*)A.yprev)[line]
+                                        : ((const double*)A.yprev)[line];
+        res = line_update<PREC, UOT>(A.role, marginal, t, A.no > 0, A.marg[line], A.theta, yp,
                                      A.yout, line, w, A.st);
     }
-    iteration_end(res, A.st, A.partials, A.role, marginal, t, A.max_iter, A.tol, A.err_hist);
+    const double bsum = block_sum256(res, sh);
+    if (threadIdx.x == 0) A.partials[blockIdx.x] = bsum;
 }
 
 int dense_blocks(int64_t nlines) { return (int)((nlines + kBlock - 1) / kBlock); }
@@ -317,7 +322,6 @@ __global__ __launch_bounds__(256) void k_dense_obj_partial(DenseObj O) {
 
 __global__ __launch_bounds__(256) void k_dense_obj_finish(DenseObj O, unsigned nbpart) {
     __shared__ double sh[4];
-    __shared__ int is_last;
     const DenseObjArgs& A = O.a;
     const int64_t line = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double kl = 0.0, tot_l = 0.0;
@@ -333,37 +337,6 @@ __global__ __launch_bounds__(256) void k_dense_obj_finish(DenseObj O, unsigned n
     if (threadIdx.x == 0) {
         A.partials[blockIdx.x] = bk;
         A.partials[gridDim.x + blockIdx.x] = bl;
-        __threadfence();
-        const unsigned tk = atomicAdd(&A.st->ticket[2 + O.role], 1u);
-        is_last = (tk == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    double f[5];
-    for (int r = 0; r < 2; ++r) {
-        double v = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock)
-            v += load_agent(&A.partials[(int64_t)r * gridDim.x + b]);
-        f[r] = block_sum256(v, sh);
-    }
-    for (int r = 0; r < 3; ++r) {
-        double v = 0.0;
-        for (unsigned b = threadIdx.x; b < nbpart; b += kBlock) v += O.bpart[(int64_t)r * nbpart + b];
-        f[2 + r] = block_sum256(v, sh);
-    }
-    if (threadIdx.x == 0) {
-        A.st->ticket[2 + O.role] = 0;
-        if (O.role == 0) {
-            A.stats[ST_KL_A] = f[0];
-            A.stats[ST_ROWSUM] = f[1];
-            A.stats[ST_TRANSPORT] = f[2];
-            A.stats[ST_NEGENT] = f[3];
-            A.stats[ST_SPARSEOBJ] = f[4];
-        } else {
-            A.stats[ST_KL_B] = f[0];
-            A.stats[ST_COLSUM] = f[1];
-        }
     }
 }
 
@@ -384,8 +357,25 @@ static void run_dense_obj(const DenseObjArgs& a, hipStream_t st) {
         O.bpart = a.partials + 2 * dense_blocks(O.nl) + 8;
         const unsigned nbp = (unsigned)(O.row_tiles * O.nseg);
         hipLaunchKernelGGL((k_dense_obj_partial<PREC, D>), dim3(nbp), dim3(kBlock), 0, st, O);
-        hipLaunchKernelGGL(k_dense_obj_finish, dim3(dense_blocks(O.nl)), dim3(kBlock), 0, st, O,
-                           nbp);
+        const unsigned nbl = (unsigned)dense_blocks(O.nl);
+        hipLaunchKernelGGL(k_dense_obj_finish, dim3(nbl), dim3(kBlock), 0, st, O, nbp);
+        // line-level sums (KL, mass) then the per-entry sums of the partial pass
+        ReduceSpec r;
+        r.nq = role == 0 ? 5 : 2;
+        r.src[0] = a.partials;
+        r.len[0] = nbl;
+        r.slot[0] = role == 0 ? ST_KL_A : ST_KL_B;
+        r.src[1] = a.partials + nbl;
+        r.len[1] = nbl;
+        r.slot[1] = role == 0 ? ST_ROWSUM : ST_COLSUM;
+        for (int q = 0; q < 3; ++q) {
+            r.src[2 + q] = O.bpart + (int64_t)q * nbp;
+            r.len[2 + q] = nbp;
+        }
+        r.slot[2] = ST_TRANSPORT;
+        r.slot[3] = ST_NEGENT;
+        r.slot[4] = ST_SPARSEOBJ;
+        (void)launch_reduce_stats(r, a.stats, st);
     }
 }
 

@@ -6,19 +6,21 @@
 
 namespace ss {
 
-// Device-resident state of one Sinkhorn loop.  Written only by the last block
-// of each iteration kernel (ticketed), read by every block of later kernels.
+// Device-resident state of one Sinkhorn loop.  Written only by block 0 of
+// the iteration launches, read by every block of later launches.
 struct IterState {
-    int32_t iter;        // last completed iteration t (after its v-update)
+    int32_t cnt_u;       // iteration of the last v-launch (read by u-launches)
+    int32_t cnt_v;       // iteration of the last u-launch (read by v-launches)
     int32_t stop_iter;   // 0 while running; else t of the returned iterate
     int32_t nonfinite;   // set when a scaling became NaN/Inf
-    int32_t pad0;
-    uint32_t ticket[4];  // last-block counters (u role, v role, objective rows, cols)
-    double err_col;      // column residual of iterate `iter` (marginal rule)
-    double err_row;      // row part of the current iteration (delta rule)
+    double err_col;      // column residual of the previous iterate (marginal rule)
+    double err_row;      // |du| of the current iteration (delta rule)
     double err_final;    // err of the returned iterate
-    double pad1;
+    double pad;
 };
+
+// Grid cap of the iteration kernels (grid-stride over lines): 8 blocks per CU.
+constexpr int kMaxLoopBlocks = 2048;
 
 // Per-solve scalars produced on the device and copied to the host once.
 enum StatSlot {
@@ -99,18 +101,33 @@ hipError_t launch_empty_policy(const double* a, const int32_t* cnt, int64_t n, i
                                int which, double* a_eff, double* tmp, double* scratch,
                                double* stats, hipStream_t st);
 
+// Fixed-order sums of up to 8 partial arrays into stats slots (one block).
+struct ReduceSpec {
+    int nq;
+    const double* src[8];
+    int64_t len[8];
+    int slot[8];
+};
+hipError_t launch_reduce_stats(const ReduceSpec& r, double* stats, hipStream_t st);
+
 // ---- iterate.hip
 struct IterArgs {
     const int64_t* ptr;
     const int32_t* idx;
-    const void* val;
+    const void* val;      // entry arrays are padded by 16 entries (quad loads)
     int64_t nlines;
+    int64_t nx;           // length of the gathered vector
+    const int32_t* split; // per line: entry offsets at the slice boundaries (launch_split)
+    int nslices;          // slices of the gathered vector
+    int lines_per_step;   // lines a block takes at a time
     const double* marg;   // a_eff (u role) or b_eff (v role)
     const void* xin;      // gathered vector: v^(t-1) (u role), u^t (v role)
     void* yout;           // new scaling / potential
     const void* yprev;    // previous value of the same scaling
     double theta;         // lam/(lam+eps); 1 for OT
-    double* partials;
+    double* partials;     // this launch's residual partials (one per block)
+    const double* prev_partials;  // the previous launch's partials
+    int prev_nblocks;
     IterState* st;
     double* err_hist;
     int role;             // 0 = u-update (closes the previous iterate), 1 = v-update
@@ -118,8 +135,15 @@ struct IterArgs {
     int max_iter;
     double tol;
 };
-hipError_t launch_iterate(int precision, int lanes, const IterArgs& a, hipStream_t st);
-int iterate_blocks(int lanes, int64_t nlines);
+hipError_t iterate_init();
+int iterate_block_size(int64_t nlines);
+int slice_elems(int precision, int block);
+int iterate_slices(int precision, int block, int64_t nx);
+int iterate_lines_per_step(int precision, int block, int64_t nx);
+int iterate_blocks(int64_t nlines, int lines_per_step);
+hipError_t launch_split(const int64_t* ptr, const int32_t* idx, int64_t nlines, int ns,
+                        int64_t slice, int32_t* split, hipStream_t st);
+hipError_t launch_iterate(int precision, int block, const IterArgs& a, hipStream_t st);
 hipError_t launch_init_scaling(int precision, void* y, const double* init_log, int64_t n,
                                hipStream_t st);
 hipError_t launch_export_scaling(int precision, const void* y, double* out, int64_t n,
@@ -161,6 +185,8 @@ struct DenseArgs {
     const void* yprev;
     double theta;
     double* partials;
+    const double* prev_partials;
+    int prev_nblocks;
     IterState* st;
     double* err_hist;
     int role, stop_rule, max_iter;

@@ -3,7 +3,8 @@
 // with T~_ij = u_i K~_ij v_j over the kept entries, C recomputed from the
 // coordinates, 0 log 0 = 0 (Sec. 2 notation).  Rows pass: transport term,
 // entropy term, sparse-problem term sum T~ (log u_i + log v_j - 1) and the
-// row KL; columns pass: the column KL.  Deterministic block reductions.
+// row KL; columns pass: the column KL.  Per-block partials are summed in
+// index order by a one-block reduction launch (deterministic, no atomics).
 #include <math.h>
 
 #include "common.hpp"
@@ -39,7 +40,6 @@ __device__ __forceinline__ double plan_entry(double yl_lin, double yl_log, const
 template <int PREC, int D>
 __global__ __launch_bounds__(256) void k_objective(ObjArgs A) {
     __shared__ double sh[4];
-    __shared__ int is_last;
     const int tid = threadIdx.x, sub = tid % kObjLanes;
     const int64_t line = (int64_t)blockIdx.x * (kBlock / kObjLanes) + tid / kObjLanes;
     double s_tc = 0.0, s_ent = 0.0, s_sp = 0.0, s_line = 0.0;
@@ -79,39 +79,42 @@ __global__ __launch_bounds__(256) void k_objective(ObjArgs A) {
     if (tid == 0) {
 #pragma unroll
         for (int r = 0; r < 5; ++r) A.partials[(int64_t)r * nb + blockIdx.x] = tot[r];
-        __threadfence();
-        const unsigned tk = atomicAdd(&A.st->ticket[2 + A.role], 1u);
-        is_last = (tk == nb - 1);
     }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    double fin[5];
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
+}
+
+// One block: stats[slot[q]] = fixed-order sum of src[q][0..len[q]).
+__global__ __launch_bounds__(256) void k_reduce_stats(ReduceSpec r, double* stats) {
+    __shared__ double sh[4];
+    for (int q = 0; q < r.nq; ++q) {
         double v = 0.0;
-        for (unsigned b = tid; b < nb; b += kBlock) v += load_agent(&A.partials[(int64_t)r * nb + b]);
-        fin[r] = block_sum256(v, sh);
+        for (int64_t b = threadIdx.x; b < r.len[q]; b += kBlock) v += r.src[q][b];
+        const double tot = block_sum256(v, sh);
+        if (threadIdx.x == 0) stats[r.slot[q]] = tot;
     }
-    if (tid == 0) {
-        A.st->ticket[2 + A.role] = 0;
-        if (A.role == 0) {
-            A.stats[ST_TRANSPORT] = fin[0];
-            A.stats[ST_NEGENT] = fin[1];
-            A.stats[ST_SPARSEOBJ] = fin[2];
-            A.stats[ST_KL_A] = fin[3];
-            A.stats[ST_ROWSUM] = fin[4];
-        } else {
-            A.stats[ST_KL_B] = fin[3];
-            A.stats[ST_COLSUM] = fin[4];
-        }
-    }
+}
+
+hipError_t launch_reduce_stats(const ReduceSpec& r, double* stats, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(kBlock), 0, st, r, stats);
+    return hipGetLastError();
 }
 
 template <int PREC, int D>
 static void run_obj(const ObjArgs& a, hipStream_t st) {
     const int nb = (int)((a.nlines + (kBlock / kObjLanes) - 1) / (kBlock / kObjLanes));
     hipLaunchKernelGGL((k_objective<PREC, D>), dim3(nb), dim3(kBlock), 0, st, a);
+    ReduceSpec r;
+    r.nq = 0;
+    const int rows[5] = {ST_TRANSPORT, ST_NEGENT, ST_SPARSEOBJ, ST_KL_A, ST_ROWSUM};
+    const int cols[5] = {-1, -1, -1, ST_KL_B, ST_COLSUM};
+    for (int q = 0; q < 5; ++q) {
+        const int slot = a.role == 0 ? rows[q] : cols[q];
+        if (slot < 0) continue;
+        r.src[r.nq] = a.partials + (int64_t)q * nb;
+        r.len[r.nq] = nb;
+        r.slot[r.nq] = slot;
+        ++r.nq;
+    }
+    (void)launch_reduce_stats(r, a.stats, st);
 }
 
 template <int D>

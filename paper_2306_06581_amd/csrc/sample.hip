@@ -569,23 +569,37 @@ __device__ __forceinline__ double entry_value(const ProbParams& pp, double kappa
     return K / P;
 }
 
-// One wave per line (row for the CSR, column for the CSC): prefix-popcount
-// of the line's mask words gives each kept entry its slot, in ascending order.
+// One wave per line (row for the CSR, column for the CSC).  Phase 1: a
+// prefix-popcount of the line's mask words gives each kept entry its slot, in
+// ascending order; the index is written out and queued in LDS.  Phase 2: the
+// whole wave computes the queued values, one entry per lane (a line's entries
+// are too sparse among its words to keep the lanes busy in phase 1).
+constexpr int kFillQueue = 512;
+
+template <int PREC>
+__device__ __forceinline__ void store_value(void* val, int64_t pos, double v, double lv) {
+    if (PREC == P_F64) ((double*)val)[pos] = v;
+    if (PREC == P_F32) ((float*)val)[pos] = (float)v;
+    if (PREC == P_LOG) ((float*)val)[pos] = (float)lv;
+}
+
 template <int ROLE, bool UOT, int PREC, int D>
 __global__ __launch_bounds__(256) void k_fill(ProbParams pp, const double* __restrict__ stats,
                                               const uint64_t* __restrict__ bits, int64_t nlines,
                                               int64_t words, const int64_t* __restrict__ ptr,
                                               int32_t* __restrict__ idx, void* __restrict__ val,
                                               int64_t cap) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (line >= nlines) return;
+    __shared__ int32_t queue[4][kFillQueue];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    const int64_t line = (int64_t)blockIdx.x * 4 + wv;
+    const bool active = line < nlines;
     const double kappa = UOT ? pp.s / stats[ST_Z] : 0.0;
-    const uint64_t* row = bits + line * words;
-    int64_t run = ptr[line];
+    const uint64_t* row = bits + (active ? line : 0) * words;
+    const int64_t base = active ? ptr[line] : 0;
+    int64_t run = base;
     for (int64_t w0 = 0; w0 < words; w0 += kWave) {
         const int64_t widx = w0 + lane;
-        uint64_t word = widx < words ? row[widx] : 0ull;
+        uint64_t word = (active && widx < words) ? row[widx] : 0ull;
         const int c = __popcll(word);
         const int incl = wave_inclusive_scan(c);
         int64_t pos = run + (incl - c);
@@ -593,19 +607,33 @@ __global__ __launch_bounds__(256) void k_fill(ProbParams pp, const double* __res
             const int b = __ffsll((unsigned long long)word) - 1;
             word &= word - 1;
             const int64_t other = 64 * widx + b;
-            const int64_t i = ROLE == 0 ? line : other;
-            const int64_t j = ROLE == 0 ? other : line;
-            double lv;
-            const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
-            if (pos < cap) {
-                idx[pos] = (int32_t)other;
-                if (PREC == P_F64) ((double*)val)[pos] = v;
-                if (PREC == P_F32) ((float*)val)[pos] = (float)v;
-                if (PREC == P_LOG) ((float*)val)[pos] = (float)lv;
+            const int64_t local = pos - base;
+            if (pos < cap) idx[pos] = (int32_t)other;
+            if (local < kFillQueue) {
+                queue[wv][local] = (int32_t)other;
+            } else if (pos < cap) {
+                const int64_t i = ROLE == 0 ? line : other;
+                const int64_t j = ROLE == 0 ? other : line;
+                double lv;
+                const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
+                store_value<PREC>(val, pos, v, lv);
             }
             ++pos;
         }
         run += __shfl(incl, kWave - 1, kWave);
+    }
+    __syncthreads();
+    const int64_t cnt = run - base;
+    const int64_t nq = cnt < kFillQueue ? cnt : kFillQueue;
+    for (int64_t e = lane; e < nq; e += kWave) {
+        const int64_t pos = base + e;
+        if (pos >= cap) break;
+        const int64_t other = queue[wv][e];
+        const int64_t i = ROLE == 0 ? line : other;
+        const int64_t j = ROLE == 0 ? other : line;
+        double lv;
+        const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
+        store_value<PREC>(val, pos, v, lv);
     }
 }
 

@@ -1,5 +1,14 @@
-// Per-line scaling update and the ticketed end-of-iteration logic shared by the
+// Per-line scaling update and the end-of-iteration logic shared by the
 // sparse (iterate.hip) and dense (dense.hip) Sinkhorn loops.
+//
+// Iteration t is two launches, the u-update (role 0) and the v-update
+// (role 1).  No launch waits on another block of itself: every block writes
+// one residual partial, and block 0 of the NEXT launch reduces those partials
+// in index order (kernel boundaries order the two) and takes the stop
+// decision.  So there are no atomics and no device-wide fences in the loop.
+// The iteration number travels in two counters (cnt_u read by u-launches,
+// written by v-launches' block 0; cnt_v the other way round), so no launch
+// reads a word that its own block 0 writes.
 #pragma once
 
 #include <math.h>
@@ -27,14 +36,91 @@ struct Scal<P_LOG> {
     typedef double Y;
 };
 
-// Common entry test of an iteration kernel; returns the iteration number t or
-// 0 if the kernel has nothing to do (stopped, non-finite, or past max_iter).
-__device__ __forceinline__ int iteration_begin(const IterState* st, int role, int marginal,
-                                               int max_iter) {
-    const int t = st->iter + 1;
-    if (st->stop_iter != 0 || st->nonfinite != 0) return 0;
-    const int tmax = max_iter + ((role == 0 && marginal) ? 1 : 0);
-    return t > tmax ? 0 : t;
+// Sum of nb partials in a fixed order (all threads of the block call it).
+__device__ __forceinline__ double reduce_partials(const double* p, int nb, double* sh) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v += p[b];
+    return block_sum(v, sh);
+}
+
+// Entry of an iteration launch.  Block 0 closes the previous launch:
+//  u-launch of iteration t (t >= 2) reduces the v-launch partials of t-1:
+//     marginal rule: the column residual of iterate t-1 -> err_col;
+//     delta rule:    err(t-1) = |du| + |dv| -> history, stop test.
+//  v-launch of iteration t reduces the u-launch partials of t:
+//     marginal rule: err(t-1) = row residual + err_col -> history, stop test;
+//     delta rule:    |du| of iteration t -> err_row.
+// Returns t if this launch updates scalings, 0 if it has nothing (more) to do.
+__device__ __forceinline__ int loop_enter(IterState* st, int role, int marginal, int max_iter,
+                                          double tol, const double* prev, int prev_nb,
+                                          double* err_hist) {
+    __shared__ double sh[16];
+    // The flags may change while this launch runs (block 0 below, or a block
+    // that meets a non-finite value), so one thread reads them and the block
+    // takes a single decision: no divergent exit before a barrier.
+    __shared__ int s_t;
+    if (threadIdx.x == 0) {
+        const int tt = role == 0 ? st->cnt_u + 1 : st->cnt_v;
+        const bool go = st->stop_iter == 0 && st->nonfinite == 0 && tt <= max_iter + 1;
+        s_t = go ? tt : 0;
+    }
+    __syncthreads();
+    const int t = s_t;
+    if (t == 0) return 0;
+    if (blockIdx.x == 0) {
+        const bool close = role == 1 || t >= 2;
+        const double total = close ? reduce_partials(prev, prev_nb, sh) : 0.0;
+        if (threadIdx.x == 0) {
+            bool decide = false;
+            double err = 0.0;
+            if (role == 0) {
+                if (t >= 2) {
+                    if (marginal) {
+                        st->err_col = total;
+                    } else {
+                        err = st->err_row + total;
+                        decide = true;
+                    }
+                }
+                st->cnt_v = t;
+            } else {
+                if (marginal) {
+                    if (t >= 2) {
+                        err = total + st->err_col;
+                        decide = true;
+                    }
+                } else {
+                    st->err_row = total;
+                }
+                st->cnt_u = t;
+            }
+            if (decide) {
+                if (err_hist) err_hist[t - 2] = err;
+                if (err <= tol || t - 1 >= max_iter) {
+                    st->err_final = err;
+                    st->stop_iter = t - 1;
+                }
+            }
+        }
+    }
+    // u-launch t = max_iter + 1 still forms the row residual of iterate
+    // max_iter (marginal rule); everything else past max_iter only closes.
+    if (role == 0) return (t <= max_iter || (marginal && t == max_iter + 1)) ? t : 0;
+    return t <= max_iter ? t : 0;
+}
+
+// Same test as loop_enter without the closing work (for launches that only
+// produce inputs of the launch that closes, e.g. the dense partial sums).
+__device__ __forceinline__ int loop_peek(const IterState* st, int role, int marginal, int max_iter) {
+    __shared__ int s_t;
+    if (threadIdx.x == 0) {
+        const int t = role == 0 ? st->cnt_u + 1 : st->cnt_v;
+        int go = st->stop_iter == 0 && st->nonfinite == 0 && t <= max_iter + 1;
+        if (go) go = role == 0 ? (t <= max_iter || (marginal && t == max_iter + 1)) : t <= max_iter;
+        s_t = go ? t : 0;
+    }
+    __syncthreads();
+    return s_t;
 }
 
 // New scaling of one line and its residual term.
@@ -43,18 +129,20 @@ __device__ __forceinline__ int iteration_begin(const IterState* st, int role, in
 //                     |u_prev^(1/th) w - a| (valid for t >= 2);
 //  role 1 (v-update): marginal residual of the new iterate |v^(1/th) w - b|.
 //  delta rule: |y_new - y_prev| in the linear scale.
+// `yp` is the previous value (scaling, or potential in the log domain).
+// Not inlined: its FP64 transcendental code would otherwise pin constants in
+// registers across the callers' streaming loops.
 template <int PREC, bool UOT>
-__device__ __forceinline__ double line_update(int role, int marginal, int t, bool nonempty,
-                                              double m, double theta, const void* yprev, void* yout,
+__device__ __attribute__((noinline)) double line_update(int role, int marginal, int t, bool nonempty,
+                                              double m, double theta, double yp, void* yout,
                                               int64_t line, double w, IterState* st) {
     typedef typename Scal<PREC>::Y Y;
     double res = 0.0;
     if (PREC != P_LOG) {
-        const double yp = (double)((const Y*)yprev)[line];
         double yn = 0.0;
         if (nonempty && w > 0.0) {
             const double q = m / w;
-            yn = UOT ? pow(q, theta) : q;
+            yn = UOT ? exp(theta * log(q)) : q;
         }
         const Y ys = (Y)yn;
         ((Y*)yout)[line] = ys;
@@ -62,14 +150,14 @@ __device__ __forceinline__ double line_update(int role, int marginal, int t, boo
         if (nonempty) {
             if (marginal) {
                 const double yr = role == 0 ? yp : (double)ys;
-                const double yq = UOT ? pow(yr, 1.0 / theta) : yr;
+                const double yq = UOT ? (yr > 0.0 ? exp(log(yr) / theta) : 0.0) : yr;
                 if (role == 1 || t >= 2) res = fabs(yq * w - m);
             } else {
                 res = fabs((double)ys - yp);
             }
         }
     } else {
-        const double fp = ((const double*)yprev)[line];
+        const double fp = yp;
         double fn = -INFINITY;
         if (nonempty && w != -INFINITY) fn = theta * (log(m) - w);
         ((double*)yout)[line] = fn;
@@ -84,58 +172,6 @@ __device__ __forceinline__ double line_update(int role, int marginal, int t, boo
         }
     }
     return res;
-}
-
-// Block reduction of the residual, then the last block of the launch closes
-// the iteration: role 0 completes err(t-1) (marginal rule) and may stop; role
-// 1 records the column residual (marginal) or err(t) (delta) and bumps iter.
-__device__ __forceinline__ void iteration_end(double res, IterState* st, double* partials, int role,
-                                              int marginal, int t, int max_iter, double tol,
-                                              double* err_hist) {
-    __shared__ double sh[4];
-    __shared__ int is_last;
-    const int tid = threadIdx.x;
-    const double bsum = block_sum256(res, sh);
-    if (tid == 0) {
-        partials[blockIdx.x] = bsum;
-        __threadfence();
-        const unsigned tk = atomicAdd(&st->ticket[role], 1u);
-        is_last = (tk == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    double v = 0.0;
-    for (unsigned b = tid; b < gridDim.x; b += kBlock) v += load_agent(&partials[b]);
-    const double total = block_sum256(v, sh);
-    if (tid != 0) return;
-    st->ticket[role] = 0;
-    if (role == 0) {
-        if (marginal) {
-            if (t >= 2) {
-                const double err = total + st->err_col;
-                if (err_hist) err_hist[t - 2] = err;
-                if (err <= tol || t - 1 >= max_iter) {
-                    st->err_final = err;
-                    st->stop_iter = t - 1;
-                }
-            }
-        } else {
-            st->err_row = total;
-        }
-    } else {
-        if (marginal) {
-            st->err_col = total;
-        } else {
-            const double err = st->err_row + total;
-            if (err_hist) err_hist[t - 1] = err;
-            if (err <= tol || t >= max_iter) {
-                st->err_final = err;
-                st->stop_iter = t;
-            }
-        }
-        st->iter = t;
-    }
 }
 
 }  // namespace ss

@@ -40,7 +40,7 @@ class SsOptions(ctypes.Structure):
     _fields_ = [("eps", c_double), ("lambda_", c_double), ("s", c_double), ("tol", c_double),
                 ("seed", c_uint64), ("max_iter", c_int32), ("precision", c_int32),
                 ("cost", c_int32), ("stop_rule", c_int32), ("empty_policy", c_int32),
-                ("lanes_per_row", c_int32), ("graph_iters", c_int32), ("reserved0", c_int32),
+                ("block_threads", c_int32), ("graph_iters", c_int32), ("reserved0", c_int32),
                 ("init_log_u", c_void_p), ("init_log_v", c_void_p), ("u_out", c_void_p),
                 ("v_out", c_void_p), ("err_hist", c_void_p)]
 

@@ -102,7 +102,7 @@ def test_bad_sizes_rejected(field, value):
 
 @pytest.mark.parametrize("kw", [dict(eps=0.0), dict(eps=-1.0), dict(eps=math.nan),
                                 dict(s=0.0), dict(tol=-1.0), dict(max_iter=0),
-                                dict(lanes_per_row=12), dict(lam=0.0)])
+                                dict(block_threads=512), dict(lam=0.0)])
 def test_bad_options_rejected(kw):
     from paper_2306_06581_amd import native as N
     from paper_2306_06581_amd.api import make_options

@@ -257,12 +257,27 @@ def test_max_iter_one_and_determinism(api):
     assert torch.equal(r1.u, r2.u) and torch.equal(r1.v, r2.v)
 
 
-@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
-def test_lane_schedules_agree(api, lanes):
-    p = W.ot_gauss2d(777, seed=18, m=901)
+@pytest.mark.parametrize("threads", [256, 1024])
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_log"])
+def test_block_schedules_agree(api, threads, precision):
+    # 40000 columns: several LDS slices per sweep in every precision
+    p = W.ot_gauss2d(777, seed=18, m=40000)
     o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=15))
-    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=0.0, max_iter=15), precision="f64",
-                         lanes_per_row=lanes, return_scalings=True)
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=0.0, max_iter=15), precision=precision,
+                         block_threads=threads, return_scalings=True)
+    rtol = 1e-11 if precision == "f64" else 2e-4
+    np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=rtol)
+    np.testing.assert_allclose(g.v.cpu().numpy(), o.sinkhorn.v, rtol=rtol, atol=1e-300)
+
+
+def test_long_lines_take_several_chunks(api):
+    # s large enough that rows hold ~1500 entries (> one register chunk)
+    p = W.ot_gauss2d(300, seed=21, m=2000)
+    p.s = 0.75 * 300 * 2000
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=10))
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=0.0, max_iter=10), precision="f64",
+                         return_scalings=True)
+    assert g.nnz == o.nnz
     np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-11)
 
 
