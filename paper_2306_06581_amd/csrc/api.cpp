@@ -43,8 +43,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Byte offsets of every region of the caller's workspace.
 struct Layout {
     size_t mask, maskT, row_cnt, col_cnt, row_ptr, col_ptr, scan, col_idx, row_idx, val, val_t;
-    size_t row_fac, col_fac, row_bnd, col_bnd, a_eff, b_eff, tmp, tree, u[2], v[2];
-    size_t partials, loop_part[2], split[2], state, stats, hstage, dense_part, rowsum, colsum;
+    size_t row_fac, col_fac, row_bnd, col_bnd, a_eff, b_eff, tmp, tree, u[2], v[2], ug[2], vg[2];
+    size_t partials, loop_part[2], state, stats, hstage, dense_part, rowsum, colsum;
+    // lane plans of the iteration kernel: [0] rows (u-update), [1] columns
+    struct PlanOff {
+        size_t split, lanes, weight, lane_ptr, wptr, rstart, info, scan, lst, lseg, pval, poff;
+    } po[2];
+    IterPlan plan[2];
     int64_t loop_part_len;
     size_t total;
     int64_t cap;
@@ -61,6 +66,18 @@ int64_t entry_capacity(double s, int64_t n, int64_t m) {
 size_t esize(int precision) { return precision == SS_F64 ? 8 : 4; }
 size_t ysize(int precision) { return precision == SS_F32 ? 4 : 8; }
 
+int block_for(const ss_options* O, int64_t nlines) {
+    return O->block_threads ? O->block_threads : iterate_block_size(nlines);
+}
+
+// Shapes of the two lane plans; false when a dimension is beyond the slice
+// limit of the iteration kernel.
+bool plan_shapes(const ss_problem* P, const ss_options* O, int64_t cap, IterPlan* pl) {
+    const int pr = O->precision;
+    return plan_shape(pr, block_for(O, P->n), P->n, P->m, cap, &pl[0]) &&
+           plan_shape(pr, block_for(O, P->m), P->m, P->n, cap, &pl[1]);
+}
+
 Layout plan(const ss_problem* P, const ss_options* O) {
     Layout L;
     const int64_t n = P->n, m = P->m;
@@ -73,8 +90,21 @@ Layout plan(const ss_problem* P, const ss_options* O) {
         off += align_up(bytes);
         return o;
     };
-    L.mask = take((size_t)n * W * 8);
-    L.maskT = take((size_t)m * Wn * 8);
+    // The sampling masks are dead once the CSR and CSC are filled; the packed
+    // entry arrays of the lane plans reuse their memory.
+    plan_shapes(P, O, L.cap, L.plan);
+    {
+        const size_t base = off;
+        L.mask = take((size_t)n * W * 8);
+        L.maskT = take((size_t)m * Wn * 8);
+        const size_t end_masks = off;
+        off = base;
+        for (int d = 0; d < 2; ++d) {
+            L.po[d].pval = take(plan_value_bytes(O->precision, L.plan[d]));
+            L.po[d].poff = take(plan_offset_bytes(O->precision, L.plan[d]));
+        }
+        if (off < end_masks) off = end_masks;
+    }
     L.row_cnt = take((size_t)n * 4);
     L.col_cnt = take((size_t)m * 4);
     L.row_ptr = take((size_t)(n + 1) * 8);
@@ -99,6 +129,9 @@ Layout plan(const ss_problem* P, const ss_options* O) {
     for (int k = 0; k < 2; ++k) {
         L.u[k] = take((size_t)n * ysize(O->precision));
         L.v[k] = take((size_t)m * ysize(O->precision));
+        // log domain: FP32 copies of the potentials for the sparse gathers
+        L.ug[k] = take(O->precision == SS_F32_LOG ? (size_t)n * 4 : 0);
+        L.vg[k] = take(O->precision == SS_F32_LOG ? (size_t)m * 4 : 0);
     }
     // block partials: iteration kernels (<= nm lines / 4 per block), objective
     // (5 per block of 16 lines), UOT normaliser, dense objective.
@@ -110,11 +143,21 @@ Layout plan(const ss_problem* P, const ss_options* O) {
     L.loop_part_len = ((nm + 255) / 256 > kMaxLoopBlocks ? (nm + 255) / 256 : kMaxLoopBlocks) + 64;
     L.loop_part[0] = take((size_t)L.loop_part_len * 8);
     L.loop_part[1] = take((size_t)L.loop_part_len * 8);
-    // slice split points of every line (at most the 256-thread slice size)
-    {
-        const int64_t sl = 32768 / 8;  // smallest slice: 32 KB of FP64
-        L.split[0] = take((size_t)n * (size_t)((m + sl - 1) / sl + 1) * 4);
-        L.split[1] = take((size_t)m * (size_t)((n + sl - 1) / sl + 1) * 4);
+    for (int d = 0; d < 2; ++d) {
+        const IterPlan& p = L.plan[d];
+        const int64_t nl = d == 0 ? n : m;
+        const int64_t kmax = p.kmax;
+        const int64_t scan_len = nl > kmax ? nl : kmax;
+        L.po[d].split = take((size_t)nl * (size_t)(p.ns + 1) * 4);
+        L.po[d].lanes = take((size_t)nl * 4);
+        L.po[d].weight = take((size_t)nl * 4);
+        L.po[d].lane_ptr = take((size_t)(nl + 1) * 8);
+        L.po[d].wptr = take((size_t)(nl + 1) * 8);
+        L.po[d].rstart = take((size_t)(kmax + 1) * 4);
+        L.po[d].info = take(sizeof(PlanInfo));
+        L.po[d].scan = take((size_t)((scan_len + 1023) / 1024 + 1) * 8);
+        L.po[d].lst = take((size_t)(nl * p.ns + kmax + 1) * 4);
+        L.po[d].lseg = take((size_t)p.lanes_max * 4);
     }
 
     L.state = take(sizeof(IterState));
@@ -161,9 +204,8 @@ int check_args(const ss_problem* P, const ss_options* O, bool dense) {
     if (!dense) {
         // the sparse iteration cuts the gathered vector into at most a fixed
         // number of LDS slices
-        const int pr = O->precision == SS_F64 ? P_F64 : O->precision == SS_F32 ? P_F32 : P_LOG;
-        const int bu = bt ? bt : iterate_block_size(P->n), bv = bt ? bt : iterate_block_size(P->m);
-        if (iterate_lines_per_step(pr, bu, P->m) == 0 || iterate_lines_per_step(pr, bv, P->n) == 0)
+        IterPlan pl[2];
+        if (!plan_shapes(P, O, entry_capacity(O->s, P->n, P->m), pl))
             return fail(SS_E_INVALID_ARG, "n or m too large for block_threads %d", bt);
     }
     return SS_OK;
@@ -367,8 +409,9 @@ int stage_sample(Ctx& c) {
 // between two events, and reports the mean time of one kernel launch
 // (2 launches per iteration for the sparse loop, `launches_per_iter` in general).
 int time_graph(const std::function<hipError_t(int, hipStream_t)>& iter, int iters, void* u0,
-               void* v0, int prec, int64_t n, int64_t m, const ss_options* O, IterState* d_state,
-               hipStream_t st, double* ms_out, int launches_per_iter = 2) {
+               void* v0, float* ug0, float* vg0, int prec, int64_t n, int64_t m,
+               const ss_options* O, IterState* d_state, hipStream_t st, double* ms_out,
+               int launches_per_iter = 2) {
     if (!ms_out) return fail(SS_E_INVALID_ARG, "ms_out must not be NULL");
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -385,8 +428,8 @@ int time_graph(const std::function<hipError_t(int, hipStream_t)>& iter, int iter
     float ms = 0.f;
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
         e = launch_fill_u32((uint32_t*)d_state, sizeof(IterState) / 4, 0u, st);
-        if (e == hipSuccess) e = launch_init_scaling(prec, u0, O->init_log_u, n, st);
-        if (e == hipSuccess) e = launch_init_scaling(prec, v0, O->init_log_v, m, st);
+        if (e == hipSuccess) e = launch_init_scaling(prec, u0, ug0, O->init_log_u, n, st);
+        if (e == hipSuccess) e = launch_init_scaling(prec, v0, vg0, O->init_log_v, m, st);
         if (e == hipSuccess && rep == 1) e = hipEventRecord(a, st);
         if (e == hipSuccess) e = hipGraphLaunch(exec, st);
         if (e == hipSuccess && rep == 1) e = hipEventRecord(b, st);
@@ -457,41 +500,61 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     const int prec = O->precision;
     void* u[2] = {at<void>(ws, c.L.u[0]), at<void>(ws, c.L.u[1])};
     void* v[2] = {at<void>(ws, c.L.v[0]), at<void>(ws, c.L.v[1])};
-    HIP_TRY(launch_init_scaling(prec, u[0], O->init_log_u, n, c.st));
-    HIP_TRY(launch_init_scaling(prec, v[0], O->init_log_v, m, c.st));
+    const bool lg = prec == SS_F32_LOG;
+    float* ug[2] = {lg ? at<float>(ws, c.L.ug[0]) : nullptr, lg ? at<float>(ws, c.L.ug[1]) : nullptr};
+    float* vg[2] = {lg ? at<float>(ws, c.L.vg[0]) : nullptr, lg ? at<float>(ws, c.L.vg[1]) : nullptr};
+    HIP_TRY(launch_init_scaling(prec, u[0], ug[0], O->init_log_u, n, c.st));
+    HIP_TRY(launch_init_scaling(prec, v[0], vg[0], O->init_log_v, m, c.st));
     IterState* d_state = at<IterState>(ws, c.L.state);
     const double theta = uot ? O->lambda / (O->lambda + O->eps) : 1.0;
     HIP_TRY(iterate_init());
-    const int bs_u = O->block_threads ? O->block_threads : iterate_block_size(n);
-    const int bs_v = O->block_threads ? O->block_threads : iterate_block_size(m);
-    const int ns_u = iterate_slices(prec, bs_u, m), ns_v = iterate_slices(prec, bs_v, n);
-    const int rps_u = iterate_lines_per_step(prec, bs_u, m);
-    const int rps_v = iterate_lines_per_step(prec, bs_v, n);
-    int32_t* split_u = at<int32_t>(ws, c.L.split[0]);
-    int32_t* split_v = at<int32_t>(ws, c.L.split[1]);
-    HIP_TRY(launch_split(at<int64_t>(ws, c.L.row_ptr), at<int32_t>(ws, c.L.col_idx), n, ns_u,
-                         slice_elems(prec, bs_u), split_u, c.st));
-    HIP_TRY(launch_split(at<int64_t>(ws, c.L.col_ptr), at<int32_t>(ws, c.L.row_idx), m, ns_v,
-                         slice_elems(prec, bs_v), split_v, c.st));
+    IterPlan pl[2];
+    for (int d = 0; d < 2; ++d) {
+        IterPlan p = c.L.plan[d];
+        const Layout::PlanOff& po = c.L.po[d];
+        p.grid = iterate_grid(prec, p.block);
+        p.split = at<int32_t>(ws, po.split);
+        p.lanes = at<int32_t>(ws, po.lanes);
+        p.weight = at<int32_t>(ws, po.weight);
+        p.lane_ptr = at<int64_t>(ws, po.lane_ptr);
+        p.wptr = at<int64_t>(ws, po.wptr);
+        p.rstart = at<int32_t>(ws, po.rstart);
+        p.info = at<PlanInfo>(ws, po.info);
+        p.scan = at<int64_t>(ws, po.scan);
+        p.lst = at<int32_t>(ws, po.lst);
+        p.lseg = at<int32_t>(ws, po.lseg);
+        p.pval = at<void>(ws, po.pval);
+        p.poff = at<uint16_t>(ws, po.poff);
+        pl[d] = p;
+    }
+    HIP_TRY(build_plan(prec, pl[0], at<int64_t>(ws, c.L.row_ptr), at<int32_t>(ws, c.L.col_idx),
+                       at<void>(ws, c.L.val), n, c.st));
+    HIP_TRY(build_plan(prec, pl[1], at<int64_t>(ws, c.L.col_ptr), at<int32_t>(ws, c.L.row_idx),
+                       at<void>(ws, c.L.val_t), m, c.st));
     IterArgs ua[2], va[2];
     for (int k = 0; k < 2; ++k) {
         IterArgs a;
-        a.nx = m;
-        a.split = split_u;
-        a.nslices = ns_u;
-        a.lines_per_step = rps_u;
         a.ptr = at<int64_t>(ws, c.L.row_ptr);
-        a.idx = at<int32_t>(ws, c.L.col_idx);
-        a.val = at<void>(ws, c.L.val);
         a.nlines = n;
+        a.nx = m;
+        a.split = pl[0].split;
+        a.nslices = pl[0].ns;
+        a.rstart = pl[0].rstart;
+        a.lane_ptr = pl[0].lane_ptr;
+        a.lst = pl[0].lst;
+        a.lseg = pl[0].lseg;
+        a.info = pl[0].info;
+        a.pval = pl[0].pval;
+        a.poff = pl[0].poff;
         a.marg = at<double>(ws, c.L.a_eff);
-        a.xin = v[k];
+        a.xin = lg ? (const void*)vg[k] : v[k];
         a.yout = u[(k + 1) & 1];
+        a.yg = ug[(k + 1) & 1];
         a.yprev = u[k];
         a.theta = theta;
         a.partials = at<double>(ws, c.L.loop_part[0]);
         a.prev_partials = at<double>(ws, c.L.loop_part[1]);
-        a.prev_nblocks = iterate_blocks(m, rps_v);
+        a.prev_nblocks = pl[1].grid;
         a.st = d_state;
         a.err_hist = O->err_hist;
         a.role = 0;
@@ -499,27 +562,32 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.max_iter = O->max_iter;
         a.tol = O->tol;
         ua[k] = a;
+        a.ptr = at<int64_t>(ws, c.L.col_ptr);
+        a.nlines = m;
+        a.nx = n;
+        a.split = pl[1].split;
+        a.nslices = pl[1].ns;
+        a.rstart = pl[1].rstart;
+        a.lane_ptr = pl[1].lane_ptr;
+        a.lst = pl[1].lst;
+        a.lseg = pl[1].lseg;
+        a.info = pl[1].info;
+        a.pval = pl[1].pval;
+        a.poff = pl[1].poff;
+        a.marg = at<double>(ws, c.L.b_eff);
+        a.xin = lg ? (const void*)ug[(k + 1) & 1] : u[(k + 1) & 1];
+        a.yout = v[(k + 1) & 1];
+        a.yg = vg[(k + 1) & 1];
+        a.yprev = v[k];
         a.partials = at<double>(ws, c.L.loop_part[1]);
         a.prev_partials = at<double>(ws, c.L.loop_part[0]);
-        a.prev_nblocks = iterate_blocks(n, rps_u);
-        a.nx = n;
-        a.split = split_v;
-        a.nslices = ns_v;
-        a.lines_per_step = rps_v;
-        a.ptr = at<int64_t>(ws, c.L.col_ptr);
-        a.idx = at<int32_t>(ws, c.L.row_idx);
-        a.val = at<void>(ws, c.L.val_t);
-        a.nlines = m;
-        a.marg = at<double>(ws, c.L.b_eff);
-        a.xin = u[(k + 1) & 1];
-        a.yout = v[(k + 1) & 1];
-        a.yprev = v[k];
+        a.prev_nblocks = pl[0].grid;
         a.role = 1;
         va[k] = a;
     }
     auto iter = [&](int k, hipStream_t s) -> hipError_t {
-        hipError_t e = launch_iterate(prec, bs_u, ua[k & 1], s);
-        if (e == hipSuccess) e = launch_iterate(prec, bs_v, va[k & 1], s);
+        hipError_t e = launch_iterate(prec, pl[0].block, pl[0].grid, ua[k & 1], s);
+        if (e == hipSuccess) e = launch_iterate(prec, pl[1].block, pl[1].grid, va[k & 1], s);
         return e;
     };
     if (time_iters > 0) {
@@ -528,7 +596,8 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
             ua[k].max_iter = va[k].max_iter = time_iters;
             ua[k].err_hist = va[k].err_hist = nullptr;
         }
-        return time_graph(iter, time_iters, u[0], v[0], prec, n, m, O, d_state, c.st, ms_out);
+        return time_graph(iter, time_iters, u[0], v[0], ug[0], vg[0], prec, n, m, O, d_state, c.st,
+                          ms_out);
     }
     const int G = O->graph_iters == 0 ? 16 : O->graph_iters;
     IterState hs;
@@ -704,8 +773,8 @@ int dense_sinkhorn(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     const int prec = O->precision;
     void* u[2] = {at<void>(ws, c.L.u[0]), at<void>(ws, c.L.u[1])};
     void* v[2] = {at<void>(ws, c.L.v[0]), at<void>(ws, c.L.v[1])};
-    HIP_TRY(launch_init_scaling(prec, u[0], O->init_log_u, n, c.st));
-    HIP_TRY(launch_init_scaling(prec, v[0], O->init_log_v, m, c.st));
+    HIP_TRY(launch_init_scaling(prec, u[0], nullptr, O->init_log_u, n, c.st));
+    HIP_TRY(launch_init_scaling(prec, v[0], nullptr, O->init_log_v, m, c.st));
     IterState* d_state = at<IterState>(ws, c.L.state);
     const double theta = c.uot ? O->lambda / (O->lambda + O->eps) : 1.0;
     DenseArgs ua[2], va[2];

@@ -111,18 +111,55 @@ struct ReduceSpec {
 hipError_t launch_reduce_stats(const ReduceSpec& r, double* stats, hipStream_t st);
 
 // ---- iterate.hip
+// Device-side parameters of a lane plan (see build_plan).
+struct PlanInfo {
+    int64_t T;     // lane weight per step
+    int64_t K;     // number of steps
+    int32_t maxw;  // largest line weight
+    int32_t pad;
+};
+
+// Lane plan of one sparse matrix for the iteration kernel: the lines are cut
+// into steps, each step's (slice, line) segments get lanes, and the entries
+// are repacked lane by lane.  Built once per solve, on the device.
+struct IterPlan {
+    int block = 0;          // threads per block
+    int ns = 0;             // slices of the gathered vector
+    int64_t slice = 0;      // elements per slice
+    int grid = 0;           // blocks per launch (resident blocks, <= kMaxLoopBlocks)
+    int64_t kmax = 0;       // bound on the number of steps
+    int64_t lanes_max = 0;  // bound on the number of lanes
+    int32_t* split = nullptr;     // [nlines][ns + 1] entry offsets at the slice boundaries
+    int32_t* lanes = nullptr;     // [nlines] lanes of each line
+    int32_t* weight = nullptr;    // [nlines] step weight of each line
+    int64_t* lane_ptr = nullptr;  // [nlines + 1] exclusive scan of lanes
+    int64_t* wptr = nullptr;      // [nlines + 1] exclusive scan of weights
+    int32_t* rstart = nullptr;    // [kmax + 1] first line of each step
+    PlanInfo* info = nullptr;
+    int64_t* scan = nullptr;      // scan scratch
+    int32_t* lst = nullptr;       // per step k: lane starts of its segments at r0 * ns + k
+    int32_t* lseg = nullptr;      // [lanes_max] segment of every lane inside its step
+    void* pval = nullptr;         // [lanes_max * E] packed values
+    uint16_t* poff = nullptr;     // [lanes_max * E] packed slice offsets
+};
+
 struct IterArgs {
-    const int64_t* ptr;
-    const int32_t* idx;
-    const void* val;      // entry arrays are padded by 16 entries (quad loads)
+    const int64_t* ptr;   // line pointers (empty-line test)
     int64_t nlines;
     int64_t nx;           // length of the gathered vector
-    const int32_t* split; // per line: entry offsets at the slice boundaries (launch_split)
-    int nslices;          // slices of the gathered vector
-    int lines_per_step;   // lines a block takes at a time
+    const int32_t* split;
+    int nslices;
+    const int32_t* rstart;
+    const int64_t* lane_ptr;
+    const int32_t* lst;
+    const int32_t* lseg;
+    const PlanInfo* info;
+    const void* pval;
+    const uint16_t* poff;
     const double* marg;   // a_eff (u role) or b_eff (v role)
     const void* xin;      // gathered vector: v^(t-1) (u role), u^t (v role)
     void* yout;           // new scaling / potential
+    float* yg;            // log domain: FP32 copy of yout for the next gather (else NULL)
     const void* yprev;    // previous value of the same scaling
     double theta;         // lam/(lam+eps); 1 for OT
     double* partials;     // this launch's residual partials (one per block)
@@ -139,13 +176,18 @@ hipError_t iterate_init();
 int iterate_block_size(int64_t nlines);
 int slice_elems(int precision, int block);
 int iterate_slices(int precision, int block, int64_t nx);
-int iterate_lines_per_step(int precision, int block, int64_t nx);
-int iterate_blocks(int64_t nlines, int lines_per_step);
-hipError_t launch_split(const int64_t* ptr, const int32_t* idx, int64_t nlines, int ns,
-                        int64_t slice, int32_t* split, hipStream_t st);
-hipError_t launch_iterate(int precision, int block, const IterArgs& a, hipStream_t st);
-hipError_t launch_init_scaling(int precision, void* y, const double* init_log, int64_t n,
-                               hipStream_t st);
+// Fills the sizes of a plan (block, ns, slice, grid, kmax, lanes_max) for a
+// matrix of nlines lines over a gathered vector of nx entries holding at most
+// cap entries; returns false when nx is beyond the slice limit.
+bool plan_shape(int precision, int block, int64_t nlines, int64_t nx, int64_t cap, IterPlan* p);
+size_t plan_value_bytes(int precision, const IterPlan& p);
+size_t plan_offset_bytes(int precision, const IterPlan& p);
+int iterate_grid(int precision, int block);  // valid after iterate_init()
+hipError_t build_plan(int precision, const IterPlan& p, const int64_t* ptr, const int32_t* idx,
+                      const void* val, int64_t nlines, hipStream_t st);
+hipError_t launch_iterate(int precision, int block, int grid, const IterArgs& a, hipStream_t st);
+hipError_t launch_init_scaling(int precision, void* y, float* yg, const double* init_log,
+                               int64_t n, hipStream_t st);
 hipError_t launch_export_scaling(int precision, const void* y, double* out, int64_t n,
                                  hipStream_t st);
 

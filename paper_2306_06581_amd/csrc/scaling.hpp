@@ -24,16 +24,22 @@ template <>
 struct Scal<P_F64> {
     typedef double V;  // stored matrix value / accumulator
     typedef double Y;  // stored scaling or potential
+    typedef double G;  // gathered copy of the other side's scaling
 };
 template <>
 struct Scal<P_F32> {
     typedef float V;
     typedef float Y;
+    typedef float G;
 };
+// Log domain: potentials are kept in FP64; the sparse product gathers an FP32
+// copy (absolute error |f| 2^-24, the same order as the FP32 log-kernel
+// entries it is added to).
 template <>
 struct Scal<P_LOG> {
     typedef float V;
     typedef double Y;
+    typedef float G;
 };
 
 // Sum of nb partials in a fixed order (all threads of the block call it).
@@ -133,9 +139,10 @@ __device__ __forceinline__ int loop_peek(const IterState* st, int role, int marg
 // Not inlined: its FP64 transcendental code would otherwise pin constants in
 // registers across the callers' streaming loops.
 template <int PREC, bool UOT>
+// `yg` (log domain, may be NULL) receives the FP32 gathered copy.
 __device__ __attribute__((noinline)) double line_update(int role, int marginal, int t, bool nonempty,
                                               double m, double theta, double yp, void* yout,
-                                              int64_t line, double w, IterState* st) {
+                                              float* yg, int64_t line, double w, IterState* st) {
     typedef typename Scal<PREC>::Y Y;
     double res = 0.0;
     if (PREC != P_LOG) {
@@ -161,6 +168,7 @@ __device__ __attribute__((noinline)) double line_update(int role, int marginal, 
         double fn = -INFINITY;
         if (nonempty && w != -INFINITY) fn = theta * (log(m) - w);
         ((double*)yout)[line] = fn;
+        if (yg) yg[line] = (float)fn;
         if (isnan(fn) || fn == INFINITY) st->nonfinite = 1;
         if (nonempty) {
             if (marginal) {
