@@ -41,22 +41,67 @@ def parse():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--timing-iters", type=int, default=64)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only sample once and time the iteration kernel (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB device to device three times (PMC byte-counter scale)")
     return ap.parse_args()
+
+
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_iterate_uot_mix3_n65536_f32_log_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2306_06581_amd", "csrc", "iterate.hip")
 
 
 def iteration_bytes_per_launch(precision: str, nnz: int, n: int, m: int) -> float:
     """Algorithmic HBM bytes of one iteration-kernel launch, averaged over the
     u-launch (CSR, n lines) and the v-launch (CSC, m lines).
 
-    Per stored entry: value + int32 index.  Per line: int64 offset, FP64 mass,
-    the previous and the new scaling.  The gathered vector of the other side
-    is counted once (it stays in L2)."""
-    ev = 8 if precision == "f64" else 4          # stored value
-    ys = 4 if precision == "f32" else 8          # stored scaling / potential
-    per_line = 8 + 8 + 2 * ys
-    u = nnz * (ev + 4) + n * per_line + 8 + m * ys
-    v = nnz * (ev + 4) + m * per_line + 8 + n * ys
+    Per stored entry: its value and a 4-byte column index.  Per line: its
+    int64 offset, FP64 mass, the previous and the new scaling (FP64 potential
+    plus its FP32 gathered copy in the log domain).  The gathered vector of
+    the other side is counted once (it stays in cache)."""
+    ev = 8 if precision == "f64" else 4                  # stored value
+    ys = {"f64": 8, "f32": 4, "f32_log": 8}[precision]   # stored scaling / potential
+    gs = 8 if precision == "f64" else 4                  # gathered copy
+    per_line = 8 + 8 + 2 * ys + (4 if precision == "f32_log" else 0)
+    u = nnz * (ev + 4) + n * per_line + m * gs
+    v = nnz * (ev + 4) + m * per_line + n * gs
     return (u + v) / 2.0
+
+
+def measured_traffic(bytes_launch: float):
+    """HBM bytes per iteration launch from the committed PMC summary, scaled
+    by the copy calibration; None when the summary is missing or the kernel
+    source changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(PROFILE_TRAFFIC):
+            parts = line.split()
+            if len(parts) == 2 and not line.startswith("#"):
+                kv[parts[0]] = parts[1]
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != src:
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["copy_fetch_scale"])
+        write = float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["copy_write_scale"])
+        return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+                "ratio_to_algorithmic": (fetch + write) / bytes_launch}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """1 GiB device-to-device copies: each reads and writes exactly 2^30 bytes."""
+    import torch
+    torch.cuda.set_device(0)
+    n = 2 ** 30 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty(n, device="cuda")
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 2 ** 30, "copy_bytes_written": 2 ** 30, "copies": 3}))
 
 
 def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
@@ -67,7 +112,7 @@ def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
     from paper_2306_06581_amd import workloads as W
 
     t_all = time.perf_counter()
-    R = 32
+    R = 256
     opt = O.Options(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, log_domain=precision_log)
     _, inv_cmax = O.cost_scale(p.x[:R], p.y, opt)  # cost scan of R rows, the rest scaled below
     t0 = time.perf_counter()
@@ -84,7 +129,7 @@ def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
     # iteration cost measured on the same generator at n_small, scaled by size
     ns = 4096
     q = W.uot_mix3(ns, seed=p.seed, eps=p.eps) if math.isfinite(p.lam) else W.ot_t5_d10(ns)
-    it = 10
+    it = 100
     optq = O.Options(eps=q.eps, s=q.s, lam=q.lam, seed=q.seed, tol=0.0, max_iter=it,
                      log_domain=precision_log)
     sk = O.build_sketch(q.x, q.y, q.a, q.b, optq)
@@ -110,9 +155,12 @@ def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs a problem (or a batch) on a "
+              "single device and has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     from paper_2306_06581_amd import api as A
@@ -123,6 +171,12 @@ def main():
     prob = A.Problem(p.x, p.y, p.a, p.b)
     kw = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, tol=1e-6, max_iter=5000,
               precision=args.precision)
+    if args.kernel_only:
+        ms_launch = A.ss_time_iterations(prob, args.timing_iters, eps=p.eps, s=p.s, lam=p.lam,
+                                         seed=p.seed, precision=args.precision)
+        print(json.dumps({"kernel": "k_iterate", "ms_per_launch": ms_launch,
+                          "launches": 4 * args.timing_iters}))
+        return
 
     for _ in range(args.warmup):
         A.spar_sink_uot(prob, **kw)
@@ -157,9 +211,13 @@ def main():
         "spmv_GBps": gbps,
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_iterate (sparse iteration, log-domain)",
+                     "kernel": "k_iterate (sparse iteration)",
                      "ms_per_launch": ms_launch, "bytes_per_launch": bytes_launch},
     }
+    tr = measured_traffic(bytes_launch)
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["bytes"]
+        out["roofline"]["traffic_detail"] = tr
     if not args.no_dense:
         dp = args.dense_precision
         if dp == "auto":
