@@ -189,6 +189,72 @@ int dense_sinkhorn(const ss_problem *problem, const ss_options *opts, void *ws,
 int ss_time_iterations(const ss_problem *problem, const ss_options *opts, void *ws,
                        size_t ws_bytes, void *stream, int32_t iters, double *ms_per_launch);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent OT problems (Alg. 3 applied to each problem, with
+ * the probabilities of Sec. 3.1 eq. (pij-ot) and the subsampling of eq.
+ * (pois)).  All problems share d and the options; sizes and budgets differ.
+ *
+ * count          number of problems, >= 1.
+ * d              point dimension, 1..64.
+ * n, m           host arrays [count]: points of x and of y per problem,
+ *                each in 1..SS_BATCH_MAX_SIDE.
+ * s              host array [count]: subsample budget s_k > 0 per problem.
+ * problem_index  host array [count] or NULL (then problem k uses k): third
+ *                word of the hash counter, so problem k samples exactly the
+ *                mask spar_sink_ot would sample with that problem_index.
+ * x, y, a, b     device FP64 arrays, the problems concatenated in order:
+ *                x is sum(n) x d row-major, y sum(m) x d, a sum(n), b sum(m).
+ * Options: lambda must be +INFINITY; precision SS_F64 or SS_F32; stop rule
+ * SS_STOP_MARGINAL_L1; empty_policy AUTO (= RENORMALIZE), RENORMALIZE or
+ * ZERO (FAIL is rejected for batches); s, block_threads and graph_iters are
+ * ignored;
+ * init_log_u / init_log_v (warm start) and u_out / v_out are device FP64
+ * arrays of sum(n) / sum(m) entries, concatenated like a and b; err_hist
+ * must be NULL. */
+#define SS_BATCH_MAX_SIDE 4096
+
+typedef struct ss_batch {
+    int32_t count;
+    int32_t d;
+    const int64_t *n, *m;
+    const double *s;
+    const uint32_t *problem_index;
+    const double *x, *y, *a, *b;
+} ss_batch;
+
+/* Schedule of the batched iteration kernel: each line (row or column) of a
+ * problem is reduced by `lanes_per_line` lanes (4, 8, 16 or 32) of a block of
+ * `block_threads` threads (256, 512 or 1024); one block solves one problem at
+ * a time, taking problems largest-first from a device queue. */
+typedef struct ss_schedule {
+    int32_t lanes_per_line;
+    int32_t block_threads;
+} ss_schedule;
+
+/* Workspace bytes for spar_sink_batched / ss_autotune_batched. */
+int ss_batch_workspace_size(const ss_batch *batch, const ss_options *opts, size_t *bytes);
+
+/* Solves every problem of the batch on `stream`: one launch per sampling
+ * stage over all problems, one persistent iteration launch in which every
+ * problem runs Alg. 1 to its own tolerance, one objective launch; the device
+ * part is captured in a hipGraph and replayed once.  `schedule` NULL picks
+ * the schedule with ss_autotune_batched (cached per process for batches of
+ * the same precision and size class).  outs: host array [count]; each entry
+ * is filled as by spar_sink_ot (z_norm 0; stage times are those of the whole
+ * batch).  Returns SS_OK when every problem converged, SS_NOT_CONVERGED when
+ * some did not (see outs[k].status), or an error code for the whole batch. */
+int spar_sink_batched(const ss_batch *batch, const ss_options *opts, const ss_schedule *schedule,
+                      void *ws, size_t ws_bytes, void *stream, ss_result *outs);
+
+/* Project autotuner: samples the batch once, then times the iteration kernel
+ * (16 iterations, every problem active) under each candidate schedule with
+ * HIP events and returns the fastest in *best.  cand_ms (host, may be NULL)
+ * receives up to *ncand times in the order lanes_per_line in {4, 8, 16, 32}
+ * major, block_threads in {256, 512, 1024} minor; *ncand is set to the
+ * number of candidates (12). */
+int ss_autotune_batched(const ss_batch *batch, const ss_options *opts, void *ws, size_t ws_bytes,
+                        void *stream, ss_schedule *best, float *cand_ms, int32_t *ncand);
+
 const char *ss_status_string(int status);
 const char *ss_last_error(void);
 int ss_version(void);

@@ -211,3 +211,98 @@ def ss_sample(prob: Problem, *, eps, s, lam=math.inf, seed=0, precision="f64", c
         out[k] = out[k][:nnz]
     out["nnz"], out["cmax"], out["z_norm"] = nnz, sp.cmax, sp.z_norm
     return out
+
+
+class Batch:
+    """Device-resident inputs of a batch of OT problems (concatenated FP64)."""
+
+    def __init__(self, xs, ys, as_, bs, s, problem_index=None):
+        if not (len(xs) == len(ys) == len(as_) == len(bs) == len(s)) or len(xs) == 0:
+            raise ValueError("a batch needs the same number (>= 1) of x, y, a, b and s")
+        self.count = len(xs)
+        self.n = np.array([len(x) for x in xs], dtype=np.int64)
+        self.m = np.array([len(y) for y in ys], dtype=np.int64)
+        self.d = int(np.asarray(xs[0]).shape[1])
+        self.s = np.ascontiguousarray(s, dtype=np.float64)
+        self.pidx = (np.arange(self.count, dtype=np.uint32) if problem_index is None
+                     else np.ascontiguousarray(problem_index, dtype=np.uint32))
+        self.x = _dev(np.concatenate([np.asarray(x, np.float64) for x in xs]))
+        self.y = _dev(np.concatenate([np.asarray(y, np.float64) for y in ys]))
+        self.a = _dev(np.concatenate([np.asarray(a, np.float64) for a in as_]))
+        self.b = _dev(np.concatenate([np.asarray(b, np.float64) for b in bs]))
+        self.row_off = np.concatenate([[0], np.cumsum(self.n)])
+        self.col_off = np.concatenate([[0], np.cumsum(self.m)])
+        self.c = N.SsBatch(self.count, self.d, self.n.ctypes.data, self.m.ctypes.data,
+                           self.s.ctypes.data, self.pidx.ctypes.data, _ptr(self.x), _ptr(self.y),
+                           _ptr(self.a), _ptr(self.b))
+
+    @classmethod
+    def from_problems(cls, probs):
+        """From workload Problems (x, y, a, b, s, problem_index attributes)."""
+        return cls([p.x for p in probs], [p.y for p in probs], [p.a for p in probs],
+                   [p.b for p in probs], [p.s for p in probs],
+                   [p.problem_index for p in probs])
+
+
+def batch_workspace_size(batch: Batch, opts: N.SsOptions) -> int:
+    out = ctypes.c_size_t(0)
+    rc = N.lib.ss_batch_workspace_size(ctypes.byref(batch.c), ctypes.byref(opts), ctypes.byref(out))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_batch_workspace_size")
+    return int(out.value)
+
+
+def spar_sink_batched(batch: Batch, *, eps, tol=1e-6, max_iter=1000, seed=0, precision="f32",
+                      cost="maxnorm", empty_policy="auto", schedule=None, init_log_u=None,
+                      init_log_v=None, return_scalings=False, stream=None,
+                      raise_on_error=True):
+    """Alg. 3 for every problem of the batch; returns (status, [Result per problem]).
+
+    schedule: (lanes_per_line, block_threads) or None for the autotuned one.
+    With return_scalings, each Result carries its u and v (FP64 device views)."""
+    rows, cols = int(batch.row_off[-1]), int(batch.col_off[-1])
+    u_out = torch.empty(rows, dtype=torch.float64, device="cuda") if return_scalings else None
+    v_out = torch.empty(cols, dtype=torch.float64, device="cuda") if return_scalings else None
+    ilu = _dev(init_log_u) if init_log_u is not None else None
+    ilv = _dev(init_log_v) if init_log_v is not None else None
+    if (ilu is not None and ilu.numel() != rows) or (ilv is not None and ilv.numel() != cols):
+        raise ValueError("init_log_u / init_log_v need sum(n) / sum(m) entries")
+    opts = make_options(eps, 1.0, math.inf, tol, max_iter, seed, precision, cost, "marginal",
+                        empty_policy, 0, 0, ilu, ilv, u_out, v_out, None)
+    ws = workspace(batch_workspace_size(batch, opts))
+    outs = (N.SsResult * batch.count)()
+    sched = N.SsSchedule(*schedule) if schedule is not None else None
+    rc = N.lib.spar_sink_batched(ctypes.byref(batch.c), ctypes.byref(opts),
+                                 ctypes.byref(sched) if sched is not None else None,
+                                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                 _stream(stream), outs)
+    if rc < 0 and raise_on_error and rc not in (N.SS_E_NONFINITE, N.SS_E_EMPTY):
+        raise N.SparSinkError(rc, "spar_sink_batched")
+    results = []
+    for k in range(batch.count):
+        r = outs[k]
+        res = Result(status=r.status, **{f: getattr(r, f) for f, _ in N.SsResult._fields_
+                                         if f != "status"})
+        if return_scalings:
+            res.u = u_out[batch.row_off[k]:batch.row_off[k + 1]]
+            res.v = v_out[batch.col_off[k]:batch.col_off[k + 1]]
+        results.append(res)
+    return rc, results
+
+
+def ss_autotune_batched(batch: Batch, *, eps, seed=0, precision="f32", cost="maxnorm",
+                        stream=None):
+    """Times every candidate schedule; returns ((lanes_per_line, block_threads), {schedule: ms})."""
+    opts = make_options(eps, 1.0, math.inf, 1e-6, 16, seed, precision, cost, "marginal")
+    ws = workspace(batch_workspace_size(batch, opts))
+    best = N.SsSchedule()
+    ms = (ctypes.c_float * 16)()
+    nc = ctypes.c_int32(16)
+    rc = N.lib.ss_autotune_batched(ctypes.byref(batch.c), ctypes.byref(opts),
+                                   ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                   _stream(stream), ctypes.byref(best), ms, ctypes.byref(nc))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_autotune_batched")
+    cands = [(l, b) for l in (4, 8, 16, 32) for b in (256, 512, 1024)]
+    return (best.lanes_per_line, best.block_threads), {c: float(ms[i]) for i, c in
+                                                          enumerate(cands[: nc.value])}

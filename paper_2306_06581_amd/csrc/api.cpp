@@ -8,7 +8,11 @@
 #include <string.h>
 
 #include <functional>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "../../include/sparsink.h"
 #include "internal.hpp"
@@ -653,6 +657,481 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     R->status = hs.err_final <= O->tol ? SS_OK : SS_NOT_CONVERGED;
     return R->status;
 }
+
+
+// ------------------------------------------------------------------ batches
+struct BLayout {
+    size_t prob, stat, tile_cmax, tile_mask, tile_tr, row_off, col_off, order, queue, gstats;
+    size_t row_fac, col_fac, a_eff, b_eff, mask, maskT, row_cnt, col_cnt, row_ptr, col_ptr, scan;
+    size_t col_idx, row_idx, val, val_t, u, v;
+    size_t total;
+    int64_t rows, cols, cap, nt_cmax, nt_mask, nt_tr;
+    int nmax, mmax;
+};
+
+int check_batch(const ss_batch* B, const ss_options* O) {
+    if (!B || !O) return fail(SS_E_INVALID_ARG, "batch and options must not be NULL");
+    if (B->count < 1) return fail(SS_E_INVALID_ARG, "count must be >= 1");
+    if (B->d <= 0 || B->d > 64) return fail(SS_E_INVALID_ARG, "d must be in [1, 64]");
+    if (!B->n || !B->m || !B->s) return fail(SS_E_INVALID_ARG, "n, m, s must not be NULL");
+    if (!B->x || !B->y || !B->a || !B->b)
+        return fail(SS_E_INVALID_ARG, "x, y, a, b must not be NULL");
+    for (int k = 0; k < B->count; ++k) {
+        if (B->n[k] < 1 || B->n[k] > SS_BATCH_MAX_SIDE || B->m[k] < 1 || B->m[k] > SS_BATCH_MAX_SIDE)
+            return fail(SS_E_INVALID_ARG, "problem %d: n and m must be in [1, %d]", k, SS_BATCH_MAX_SIDE);
+        if (!(B->s[k] > 0.0) || !isfinite(B->s[k]))
+            return fail(SS_E_INVALID_ARG, "problem %d: s must be a positive finite number", k);
+    }
+    if (!(O->eps > 0.0) || !isfinite(O->eps)) return fail(SS_E_INVALID_ARG, "eps must be > 0");
+    if (!(O->tol >= 0.0)) return fail(SS_E_INVALID_ARG, "tol must be >= 0");
+    if (O->max_iter < 1) return fail(SS_E_INVALID_ARG, "max_iter must be >= 1");
+    if (isfinite(O->lambda)) return fail(SS_E_INVALID_ARG, "batches solve OT: lambda must be +INFINITY");
+    if (O->precision != SS_F64 && O->precision != SS_F32)
+        return fail(SS_E_INVALID_ARG, "batches support precision SS_F64 or SS_F32");
+    if (O->cost != SS_COST_SQEUCLID_MAXNORM && O->cost != SS_COST_SQEUCLID)
+        return fail(SS_E_INVALID_ARG, "unknown cost %d", O->cost);
+    if (O->stop_rule != SS_STOP_MARGINAL_L1)
+        return fail(SS_E_INVALID_ARG, "batches support the marginal stop rule only");
+    if (O->empty_policy != SS_EMPTY_AUTO && O->empty_policy != SS_EMPTY_RENORMALIZE &&
+        O->empty_policy != SS_EMPTY_ZERO)
+        return fail(SS_E_INVALID_ARG, "batches support empty_policy AUTO, RENORMALIZE or ZERO");
+    if (O->err_hist) return fail(SS_E_INVALID_ARG, "err_hist must be NULL for batches");
+    return SS_OK;
+}
+
+BLayout bplan(const ss_batch* B, const ss_options* O) {
+    BLayout L;
+    const int K = B->count;
+    L.rows = L.cols = L.cap = 0;
+    L.nt_cmax = L.nt_mask = L.nt_tr = 0;
+    L.nmax = L.mmax = 0;
+    int64_t mask_words = 0, maskT_words = 0;
+    for (int k = 0; k < K; ++k) {
+        const int64_t n = B->n[k], m = B->m[k];
+        const int64_t W = (m + 63) / 64, Wn = (n + 63) / 64;
+        L.rows += n;
+        L.cols += m;
+        L.cap += entry_capacity(B->s[k], n, m);
+        mask_words += n * W;
+        maskT_words += m * Wn;
+        L.nt_cmax += ((n + 255) / 256) * ((m + 2047) / 2048);
+        L.nt_mask += ((n + 15) / 16) * ((W + 63) / 64);
+        L.nt_tr += ((Wn + 7) / 8) * ((W + 15) / 16);
+        if (n > L.nmax) L.nmax = (int)n;
+        if (m > L.mmax) L.mmax = (int)m;
+    }
+    const size_t es = O->precision == SS_F64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.prob = take((size_t)K * sizeof(BProb));
+    L.stat = take((size_t)K * sizeof(BStat));
+    L.tile_cmax = take((size_t)(K + 1) * 8);
+    L.tile_mask = take((size_t)(K + 1) * 8);
+    L.tile_tr = take((size_t)(K + 1) * 8);
+    L.row_off = take((size_t)(K + 1) * 8);
+    L.col_off = take((size_t)(K + 1) * 8);
+    L.order = take((size_t)K * 4);
+    L.queue = take(64);
+    L.gstats = take(ST_COUNT * 8);
+    L.row_fac = take((size_t)L.rows * 8);
+    L.col_fac = take((size_t)L.cols * 8);
+    L.a_eff = take((size_t)L.rows * 8);
+    L.b_eff = take((size_t)L.cols * 8);
+    L.mask = take((size_t)mask_words * 8);
+    L.maskT = take((size_t)maskT_words * 8);
+    L.row_cnt = take((size_t)L.rows * 4);
+    L.col_cnt = take((size_t)L.cols * 4);
+    L.row_ptr = take((size_t)(L.rows + 1) * 8);
+    L.col_ptr = take((size_t)(L.cols + 1) * 8);
+    const int64_t big = L.rows > L.cols ? L.rows : L.cols;
+    L.scan = take((size_t)((big + 1023) / 1024 + 1) * 8);
+    L.col_idx = take((size_t)(L.cap + 64) * 2);
+    L.row_idx = take((size_t)(L.cap + 64) * 2);
+    L.val = take((size_t)(L.cap + 64) * es);
+    L.val_t = take((size_t)(L.cap + 64) * es);
+    L.u = take((size_t)L.rows * es);
+    L.v = take((size_t)L.cols * es);
+    L.total = off;
+    return L;
+}
+
+struct BHost {
+    std::vector<BProb> prob;
+    std::vector<int64_t> tc, tm, tt, ro, co;
+    std::vector<int32_t> order;
+};
+
+void build_batch_tables(const ss_batch* B, BHost* H) {
+    const int K = B->count;
+    H->prob.resize(K);
+    H->tc.assign(K + 1, 0);
+    H->tm.assign(K + 1, 0);
+    H->tt.assign(K + 1, 0);
+    H->ro.assign(K + 1, 0);
+    H->co.assign(K + 1, 0);
+    int64_t mo = 0, mto = 0;
+    for (int k = 0; k < K; ++k) {
+        BProb& P = H->prob[k];
+        P.n = B->n[k];
+        P.m = B->m[k];
+        P.W = (P.m + 63) / 64;
+        P.Wn = (P.n + 63) / 64;
+        P.xo = H->ro[k];
+        P.yo = H->co[k];
+        P.mo = mo;
+        P.mto = mto;
+        P.s = B->s[k];
+        P.pidx = B->problem_index ? B->problem_index[k] : (uint32_t)k;
+        P.pad = 0;
+        mo += P.n * P.W;
+        mto += P.m * P.Wn;
+        H->ro[k + 1] = H->ro[k] + P.n;
+        H->co[k + 1] = H->co[k] + P.m;
+        H->tc[k + 1] = H->tc[k] + ((P.n + 255) / 256) * ((P.m + 2047) / 2048);
+        H->tm[k + 1] = H->tm[k] + ((P.n + 15) / 16) * ((P.W + 63) / 64);
+        H->tt[k + 1] = H->tt[k] + ((P.Wn + 7) / 8) * ((P.W + 15) / 16);
+    }
+    // longest first: entries grow with s, iterations roughly with size
+    H->order.resize(K);
+    for (int k = 0; k < K; ++k) H->order[k] = k;
+    std::stable_sort(H->order.begin(), H->order.end(), [&](int x, int y) {
+        return B->s[x] * (double)(B->n[x] + B->m[x]) > B->s[y] * (double)(B->n[y] + B->m[y]);
+    });
+}
+
+struct BCtx {
+    const ss_batch* B;
+    const ss_options* O;
+    void* ws;
+    hipStream_t st;
+    BLayout L;
+    BHost H;
+    BatchArgs ba;
+    BIterArgs ia;
+    BObjArgs oa;
+};
+
+// Uploads the tables and fills the kernel arguments.
+int batch_setup(BCtx& c) {
+    const ss_batch* B = c.B;
+    const ss_options* O = c.O;
+    void* ws = c.ws;
+    build_batch_tables(B, &c.H);
+    const int K = B->count;
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, c.L.prob), c.H.prob.data(), (size_t)K * sizeof(BProb),
+                           hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, c.L.tile_cmax), c.H.tc.data(), (K + 1) * 8, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, c.L.tile_mask), c.H.tm.data(), (K + 1) * 8, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, c.L.tile_tr), c.H.tt.data(), (K + 1) * 8, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, c.L.row_off), c.H.ro.data(), (K + 1) * 8, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, c.L.col_off), c.H.co.data(), (K + 1) * 8, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, c.L.order), c.H.order.data(), (size_t)K * 4, hipMemcpyHostToDevice, c.st));
+
+    BatchArgs& a = c.ba;
+    a.count = K;
+    a.d = B->d;
+    a.prob = at<BProb>(ws, c.L.prob);
+    a.stat = at<BStat>(ws, c.L.stat);
+    a.tile_cmax = at<int64_t>(ws, c.L.tile_cmax);
+    a.tile_mask = at<int64_t>(ws, c.L.tile_mask);
+    a.tile_tr = at<int64_t>(ws, c.L.tile_tr);
+    a.row_off = at<int64_t>(ws, c.L.row_off);
+    a.col_off = at<int64_t>(ws, c.L.col_off);
+    a.rows = c.L.rows;
+    a.cols = c.L.cols;
+    a.x = B->x;
+    a.y = B->y;
+    a.a = B->a;
+    a.b = B->b;
+    a.row_fac = at<double>(ws, c.L.row_fac);
+    a.col_fac = at<double>(ws, c.L.col_fac);
+    a.a_eff = at<double>(ws, c.L.a_eff);
+    a.b_eff = at<double>(ws, c.L.b_eff);
+    a.mask = at<uint64_t>(ws, c.L.mask);
+    a.maskT = at<uint64_t>(ws, c.L.maskT);
+    a.row_cnt = at<int32_t>(ws, c.L.row_cnt);
+    a.col_cnt = at<int32_t>(ws, c.L.col_cnt);
+    a.row_ptr = at<int64_t>(ws, c.L.row_ptr);
+    a.col_ptr = at<int64_t>(ws, c.L.col_ptr);
+    a.col_idx = at<uint16_t>(ws, c.L.col_idx);
+    a.row_idx = at<uint16_t>(ws, c.L.row_idx);
+    a.val = at<void>(ws, c.L.val);
+    a.val_t = at<void>(ws, c.L.val_t);
+    a.cap = c.L.cap;
+    a.cost = O->cost;
+    a.empty_policy = O->empty_policy == SS_EMPTY_AUTO ? SS_EMPTY_RENORMALIZE : O->empty_policy;
+    a.eps = O->eps;
+    a.k0 = (uint32_t)(O->seed & 0xFFFFFFFFull);
+    a.k1 = (uint32_t)(O->seed >> 32);
+    a.gstats = at<double>(ws, c.L.gstats);
+
+    BIterArgs& it = c.ia;
+    it.count = K;
+    it.order = at<int32_t>(ws, c.L.order);
+    it.queue = at<int32_t>(ws, c.L.queue);
+    it.prob = a.prob;
+    it.stat = a.stat;
+    it.row_ptr = a.row_ptr;
+    it.col_ptr = a.col_ptr;
+    it.col_idx = a.col_idx;
+    it.row_idx = a.row_idx;
+    it.val = a.val;
+    it.val_t = a.val_t;
+    it.a_eff = a.a_eff;
+    it.b_eff = a.b_eff;
+    it.rows = a.rows;
+    it.cols = a.cols;
+    it.cap = a.cap;
+    it.nmax = c.L.nmax;
+    it.mmax = c.L.mmax;
+    it.init_log_u = O->init_log_u;
+    it.init_log_v = O->init_log_v;
+    it.u = at<void>(ws, c.L.u);
+    it.v = at<void>(ws, c.L.v);
+    it.u_out = O->u_out;
+    it.v_out = O->v_out;
+    it.max_iter = O->max_iter;
+    it.tol = O->tol;
+
+    BObjArgs& ob = c.oa;
+    ob.d = B->d;
+    ob.prob = a.prob;
+    ob.stat = a.stat;
+    ob.row_ptr = a.row_ptr;
+    ob.col_idx = a.col_idx;
+    ob.val = a.val;
+    ob.u = it.u;
+    ob.v = it.v;
+    ob.x = B->x;
+    ob.y = B->y;
+    ob.rows = a.rows;
+    ob.cols = a.cols;
+    ob.cap = a.cap;
+    ob.col_ptr = a.col_ptr;
+    return SS_OK;
+}
+
+hipError_t batch_sample(const BCtx& c, hipStream_t s) {
+    return launch_batch_sample(c.O->precision, c.ba, c.L.nt_cmax, c.L.nt_mask, c.L.nt_tr,
+                               at<int64_t>(c.ws, c.L.scan), s);
+}
+
+hipError_t batch_iterate(const BCtx& c, const BIterArgs& ia, const ss_schedule& sc, hipStream_t s) {
+    hipError_t e = launch_fill_u32((uint32_t*)ia.queue, 1, 0u, s);
+    if (e != hipSuccess) return e;
+    const int grid = batch_iter_grid(c.O->precision, sc.lanes_per_line, sc.block_threads,
+                                     c.L.nmax, c.L.mmax);
+    if (grid <= 0) return hipErrorInvalidConfiguration;
+    return launch_batch_iterate(c.O->precision, sc.lanes_per_line, sc.block_threads, grid, ia, s);
+}
+
+// Captures fn into a graph on a private stream, replays it once on st and
+// waits for it.
+hipError_t run_captured(const std::function<hipError_t(hipStream_t)>& fn, hipStream_t st) {
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t e1 = fn(cs);
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        e = e1 != hipSuccess ? e1 : e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the exec is destroyed below
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    return e;
+}
+
+const int kLanesCand[4] = {4, 8, 16, 32};
+const int kBlockCand[3] = {256, 512, 1024};
+
+int batch_autotune(BCtx& c, ss_schedule* best, float* cand_ms, int32_t* ncand) {
+    BIterArgs ia = c.ia;
+    ia.tol = 0.0;
+    ia.max_iter = 16;
+    ia.u_out = ia.v_out = nullptr;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    int nc = 0;
+    hipError_t e = hipSuccess;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {  // pass 0 warms up
+        nc = 0;
+        for (int li = 0; li < 4 && e == hipSuccess; ++li)
+            for (int bi = 0; bi < 3 && e == hipSuccess; ++bi) {
+                const ss_schedule sc = {kLanesCand[li], kBlockCand[bi]};
+                e = hipEventRecord(e0, c.st);
+                if (e == hipSuccess) e = batch_iterate(c, ia, sc, c.st);
+                if (e == hipSuccess) e = hipEventRecord(e1, c.st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (pass == 1) {
+                    if (cand_ms && ncand && nc < *ncand) cand_ms[nc] = ms;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        *best = sc;
+                    }
+                }
+                ++nc;
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(SS_E_HIP, "autotuning failed: %s", hipGetErrorString(e));
+    if (ncand) *ncand = nc;
+    return SS_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t>, ss_schedule> g_tuned;
+
+int batch_start(BCtx& c, const ss_batch* B, const ss_options* O, void* ws, size_t ws_bytes,
+                void* stream) {
+    int rc = check_batch(B, O);
+    if (rc != SS_OK) return rc;
+    c.B = B;
+    c.O = O;
+    c.ws = ws;
+    c.st = (hipStream_t)stream;
+    c.L = bplan(B, O);
+    if (!ws) return fail(SS_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(SS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < c.L.total)
+        return fail(SS_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, c.L.total);
+    HIP_TRY(batch_init());
+    return batch_setup(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_batch_workspace_size(const ss_batch* batch, const ss_options* opts, size_t* bytes) {
+    int rc = check_batch(batch, opts);
+    if (rc != SS_OK) return rc;
+    if (!bytes) return fail(SS_E_INVALID_ARG, "bytes must not be NULL");
+    *bytes = bplan(batch, opts).total;
+    return SS_OK;
+}
+
+int ss_autotune_batched(const ss_batch* B, const ss_options* O, void* ws, size_t ws_bytes,
+                        void* stream, ss_schedule* best, float* cand_ms, int32_t* ncand) {
+    if (!best) return fail(SS_E_INVALID_ARG, "best must not be NULL");
+    BCtx c;
+    int rc = batch_start(c, B, O, ws, ws_bytes, stream);
+    if (rc != SS_OK) return rc;
+    HIP_TRY(batch_sample(c, c.st));
+    return batch_autotune(c, best, cand_ms, ncand);
+}
+
+int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule* schedule, void* ws,
+                      size_t ws_bytes, void* stream, ss_result* outs) {
+    if (!outs) return fail(SS_E_INVALID_ARG, "outs must not be NULL");
+    if (schedule) {
+        bool ok = false;
+        for (int l : kLanesCand) ok = ok || l == schedule->lanes_per_line;
+        bool okb = false;
+        for (int b : kBlockCand) okb = okb || b == schedule->block_threads;
+        if (!ok || !okb)
+            return fail(SS_E_INVALID_ARG, "schedule: lanes_per_line in {4,8,16,32}, block_threads in {256,512,1024}");
+    }
+    BCtx c;
+    int rc = batch_start(c, B, O, ws, ws_bytes, stream);
+    if (rc != SS_OK) return rc;
+    Timer tm;
+    tm.mark(0, c.st);
+    HIP_TRY(run_captured([&](hipStream_t s) { return batch_sample(c, s); }, c.st));
+    tm.mark(1, c.st);
+    ss_schedule sc;
+    if (schedule) {
+        sc = *schedule;
+    } else {
+        const auto key = std::make_tuple(O->precision, B->count, (int64_t)(c.L.rows / 256));
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) {
+                sc = it->second;
+                have = true;
+            }
+        }
+        if (!have) {
+            rc = batch_autotune(c, &sc, nullptr, nullptr);
+            if (rc != SS_OK) return rc;
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            g_tuned[key] = sc;
+        }
+    }
+    tm.mark(2, c.st);
+    HIP_TRY(run_captured([&](hipStream_t s) { return batch_iterate(c, c.ia, sc, s); }, c.st));
+    tm.mark(3, c.st);
+    HIP_TRY(run_captured(
+        [&](hipStream_t s) { return launch_batch_objective(O->precision, B->count, c.oa, s); }, c.st));
+    tm.mark(4, c.st);
+    const int K = B->count;
+    std::vector<BStat> stat(K);
+    double gst[ST_COUNT];
+    int64_t tot[2];
+    HIP_TRY(hipMemcpyAsync(stat.data(), at<void>(ws, c.L.stat), (size_t)K * sizeof(BStat),
+                           hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipMemcpyAsync(gst, at<void>(ws, c.L.gstats), sizeof gst, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipMemcpyAsync(&tot[0], at<int64_t>(ws, c.L.row_ptr) + c.L.rows, 8, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipMemcpyAsync(&tot[1], at<int64_t>(ws, c.L.col_ptr) + c.L.cols, 8, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    if (gst[ST_BAD_INPUT] != 0.0)
+        return fail(SS_E_INVALID_ARG, "a, b must be finite and >= 0 and x, y finite");
+    if (tot[0] > c.L.cap || tot[1] > c.L.cap)
+        return fail(SS_E_CAPACITY, "sampled entries %lld exceed the capacity %lld", (long long)tot[0],
+                    (long long)c.L.cap);
+    // stage times: sampling graph, schedule choice (autotuning when not cached),
+    // iteration graph, objective graph
+    const float t_sample = tm.ms(0, 1), t_tune = tm.ms(1, 2), t_iter = tm.ms(2, 3),
+                t_obj = tm.ms(3, 4);
+    int worst = SS_OK;
+    for (int k = 0; k < K; ++k) {
+        const BStat& S = stat[k];
+        ss_result& R = outs[k];
+        memset(&R, 0, sizeof R);
+        R.transport = S.transport;
+        R.neg_entropy = S.negent;
+        R.estimate = S.transport + O->eps * S.negent;
+        R.sparse_objective = O->eps * S.sparseobj;
+        R.marginal_err = S.err;
+        R.cmax = S.cmax;
+        R.dropped_mass_a = S.dropped_a;
+        R.dropped_mass_b = S.dropped_b;
+        R.nnz = S.nnz;
+        R.empty_rows = (int64_t)S.empty_rows;
+        R.empty_cols = (int64_t)S.empty_cols;
+        R.iters = S.iters;
+        R.status = S.status;
+        R.t_prep_ms = t_tune;
+        R.t_sample_ms = t_sample;
+        R.t_iter_ms = t_iter;
+        R.t_obj_ms = t_obj;
+        if (S.status < 0 && (worst >= 0)) worst = S.status;
+        if (S.status == SS_NOT_CONVERGED && worst == SS_OK) worst = SS_NOT_CONVERGED;
+    }
+    if (worst < 0) return fail(worst, "a problem of the batch failed: %s", "see outs[k].status");
+    return worst;
+}
+
+}  // extern "C"
+
+namespace {
 
 }  // namespace
 

@@ -1,0 +1,301 @@
+// Batches of independent OT problems: the Sinkhorn loop (Alg. 1) of every
+// problem inside one persistent launch, and the estimate (Alg. 3) per problem.
+//
+// Every side of a batched problem has at most 4096 points, so a problem's
+// scalings (u, its next value, v) fit in LDS and one block can run the whole
+// loop of a problem with block barriers only: no grid synchronisation, no
+// per-iteration launches.  Blocks take problems from a device queue in
+// decreasing size order (longest first), so uneven sizes balance over the
+// persistent grid.  Each line (row of the CSR for u, column of the CSC for v)
+// is reduced by a group of L lanes; the sparse entries stream from HBM with
+// 16-bit local indices, the gathered scaling comes from LDS.
+//
+// The stop test is the one of the single-problem solver: err(t) is the L1
+// marginal error of the iterate (u^t, v^t) on K~ -- the column part is formed
+// in the v-update of iteration t, the row part in the u-update of iteration
+// t + 1 -- and the solver returns the first iterate with err(t) <= tol.  All
+// sums have a fixed order for a given schedule.
+#include <math.h>
+
+#include <type_traits>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ss {
+
+template <int PREC>
+struct BTypes {
+    typedef typename std::conditional<PREC == P_F64, double, float>::type V;  // value, scaling
+};
+
+// One half-step of problem-local lines 0..nl: w = sum_k val_k x[idx_k],
+// y_new = marg / w (0 on an empty line or w <= 0).  Returns this thread's
+// share of the residual: ROLE 0 |y_prev w - marg| (iterate t - 1, t >= 2),
+// ROLE 1 |y_new w - marg| (iterate t).
+template <int ROLE, int PREC, int L>
+__device__ __forceinline__ double b_half(const int64_t* __restrict__ ptr,
+                                         const uint16_t* __restrict__ idx,
+                                         const typename BTypes<PREC>::V* __restrict__ val,
+                                         int64_t nl, const typename BTypes<PREC>::V* xin,
+                                         const typename BTypes<PREC>::V* yprev,
+                                         typename BTypes<PREC>::V* yout,
+                                         const double* __restrict__ marg, int t, int* bad) {
+    typedef typename BTypes<PREC>::V V;
+    const int lane = threadIdx.x % L;
+    const int g = threadIdx.x / L, ng = blockDim.x / L;
+    double res = 0.0;
+    for (int64_t r = g; r < nl; r += ng) {
+        const int64_t k0 = ptr[r], k1 = ptr[r + 1];
+        V acc = 0;
+        for (int64_t k = k0 + lane; k < k1; k += L) acc = fma(val[k], xin[idx[k]], acc);
+        acc = group_sum<L>(acc);
+        if (lane == 0) {
+            const double w = (double)acc;
+            const double m = marg[r];
+            const bool ne = k1 > k0;
+            const double yn = (ne && w > 0.0) ? m / w : 0.0;
+            const V ys = (V)yn;
+            yout[r] = ys;
+            if (!isfinite((double)ys)) *bad = 1;
+            if (ne) {
+                if (ROLE == 0) {
+                    if (t >= 2) res += fabs((double)yprev[r] * w - m);
+                } else {
+                    res += fabs((double)ys * w - m);
+                }
+            }
+        }
+    }
+    return res;
+}
+
+template <int PREC, int L>
+__global__ __launch_bounds__(1024) void k_b_iterate(BIterArgs A) {
+    typedef typename BTypes<PREC>::V V;
+    extern __shared__ __align__(16) unsigned char dsm[];
+    V* ua = (V*)dsm;
+    V* ub = ua + A.nmax;
+    V* vv = ub + A.nmax;
+    __shared__ int s_q;
+    __shared__ double sh[16];
+    // a sketch larger than its arrays was not stored: nothing to iterate
+    if (A.row_ptr[A.rows] > A.cap || A.col_ptr[A.cols] > A.cap) return;
+    const V* val = (const V*)A.val;
+    const V* val_t = (const V*)A.val_t;
+    for (;;) {
+        if (threadIdx.x == 0) s_q = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= A.count) break;
+        const int k = A.order[q];
+        const BProb P = A.prob[k];
+        for (int64_t i = threadIdx.x; i < P.n; i += blockDim.x)
+            ua[i] = A.init_log_u ? (V)exp(A.init_log_u[P.xo + i]) : (V)1;
+        for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x)
+            vv[j] = A.init_log_v ? (V)exp(A.init_log_v[P.yo + j]) : (V)1;
+        __syncthreads();
+        V* u = ua;
+        V* un = ub;
+        double res_col = 0.0, err = INFINITY;
+        int iters = 0, status = SS_NOT_CONVERGED;
+        for (int t = 1;; ++t) {
+            int bad = 0;
+            double r = b_half<0, PREC, L>(A.row_ptr + P.xo, A.col_idx, val, P.n, vv, u, un,
+                                          A.a_eff + P.xo, t, &bad);
+            r = block_sum(r, sh);
+            if (__syncthreads_or(bad)) {
+                status = SS_E_NONFINITE;
+                iters = t - 1;
+                break;
+            }
+            if (t >= 2) {
+                err = r + res_col;
+                if (err <= A.tol) {
+                    status = SS_OK;
+                    iters = t - 1;
+                    break;
+                }
+            }
+            if (t == A.max_iter + 1) {
+                iters = A.max_iter;
+                break;
+            }
+            V* tmp = u;
+            u = un;
+            un = tmp;
+            double c = b_half<1, PREC, L>(A.col_ptr + P.yo, A.row_idx, val_t, P.m, u, vv, vv,
+                                          A.b_eff + P.yo, t, &bad);
+            res_col = block_sum(c, sh);
+            if (__syncthreads_or(bad)) {
+                status = SS_E_NONFINITE;
+                iters = t;
+                break;
+            }
+        }
+        // the returned iterate: u (the value before the last u-update) and v
+        for (int64_t i = threadIdx.x; i < P.n; i += blockDim.x) {
+            ((V*)A.u)[P.xo + i] = u[i];
+            if (A.u_out) A.u_out[P.xo + i] = (double)u[i];
+        }
+        for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x) {
+            ((V*)A.v)[P.yo + j] = vv[j];
+            if (A.v_out) A.v_out[P.yo + j] = (double)vv[j];
+        }
+        if (threadIdx.x == 0) {
+            A.stat[k].iters = iters;
+            A.stat[k].err = err;
+            A.stat[k].status = status;
+        }
+        __syncthreads();
+    }
+}
+
+size_t batch_iter_lds(int precision, int nmax, int mmax) {
+    return (size_t)(2 * nmax + mmax) * (precision == P_F64 ? 8 : 4);
+}
+
+template <int PREC, int L>
+static const void* iter_fn() {
+    return (const void*)&k_b_iterate<PREC, L>;
+}
+
+static const void* iter_kernel(int precision, int lanes) {
+    if (precision == P_F64) {
+        switch (lanes) {
+            case 4: return iter_fn<P_F64, 4>();
+            case 8: return iter_fn<P_F64, 8>();
+            case 16: return iter_fn<P_F64, 16>();
+            default: return iter_fn<P_F64, 32>();
+        }
+    }
+    switch (lanes) {
+        case 4: return iter_fn<P_F32, 4>();
+        case 8: return iter_fn<P_F32, 8>();
+        case 16: return iter_fn<P_F32, 16>();
+        default: return iter_fn<P_F32, 32>();
+    }
+}
+
+// Largest dynamic LDS any batch needs: u, u', v of 4096 FP64 each.
+constexpr size_t kBatchLdsMax = 3 * kBatchMaxSide * 8;
+
+hipError_t batch_init() {
+    static hipError_t status = [] {
+        hipError_t e = hipSuccess;
+        for (int prec : {P_F64, P_F32})
+            for (int lanes : {4, 8, 16, 32}) {
+                const hipError_t r = hipFuncSetAttribute(iter_kernel(prec, lanes),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                         (int)kBatchLdsMax);
+                if (r != hipSuccess) e = r;
+            }
+        return e;
+    }();
+    return status;
+}
+
+int batch_iter_grid(int precision, int lanes, int block, int nmax, int mmax) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, iter_kernel(precision, lanes), block,
+                                                     batch_iter_lds(precision, nmax, mmax)) != hipSuccess)
+        return 0;
+    return cus * (per > 0 ? per : 1);
+}
+
+hipError_t launch_batch_iterate(int precision, int lanes, int block, int grid, const BIterArgs& a,
+                                hipStream_t st) {
+    const size_t lds = batch_iter_lds(precision, a.nmax, a.mmax);
+    const dim3 g((unsigned)grid), b((unsigned)block);
+#define SS_BITER(P, L) hipLaunchKernelGGL((k_b_iterate<P, L>), g, b, lds, st, a)
+    if (precision == P_F64) {
+        switch (lanes) {
+            case 4: SS_BITER(P_F64, 4); break;
+            case 8: SS_BITER(P_F64, 8); break;
+            case 16: SS_BITER(P_F64, 16); break;
+            default: SS_BITER(P_F64, 32); break;
+        }
+    } else {
+        switch (lanes) {
+            case 4: SS_BITER(P_F32, 4); break;
+            case 8: SS_BITER(P_F32, 8); break;
+            case 16: SS_BITER(P_F32, 16); break;
+            default: SS_BITER(P_F32, 32); break;
+        }
+    }
+#undef SS_BITER
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ estimate
+// One block per problem, 16 lanes per row: sum T~ C, sum T~ (log T~ - 1) and
+// sum T~ (log u + log v - 1) over the kept entries (Alg. 3; 0 log 0 = 0).
+constexpr int kBObjLanes = 16;
+
+template <int PREC, int D>
+__global__ __launch_bounds__(256) void k_b_objective(BObjArgs A) {
+    typedef typename BTypes<PREC>::V V;
+    __shared__ double sh[16];
+    if (A.row_ptr[A.rows] > A.cap || A.col_ptr[A.cols] > A.cap) return;
+    const int k = blockIdx.x;
+    const BProb P = A.prob[k];
+    const int sub = threadIdx.x % kBObjLanes;
+    const double inv_cmax = A.stat[k].inv_cmax;
+    const V* u = (const V*)A.u + P.xo;
+    const V* v = (const V*)A.v + P.yo;
+    const V* val = (const V*)A.val;
+    const double* x = A.x + P.xo * A.d;
+    const double* y = A.y + P.yo * A.d;
+    double s_tc = 0.0, s_ent = 0.0, s_sp = 0.0;
+    for (int64_t r = threadIdx.x / kBObjLanes; r < P.n; r += blockDim.x / kBObjLanes) {
+        const int64_t k0 = A.row_ptr[P.xo + r], k1 = A.row_ptr[P.xo + r + 1];
+        const double ur = (double)u[r];
+        const double lu = log(ur);
+        for (int64_t e = k0 + sub; e < k1; e += kBObjLanes) {
+            const int64_t o = A.col_idx[e];
+            const double t = ur * (double)val[e] * (double)v[o];
+            if (t > 0.0) {
+                const double c = sqdist<D>(x + r * A.d, y + o * A.d, A.d) * inv_cmax;
+                s_tc += t * c;
+                s_ent += t * (log(t) - 1.0);
+                s_sp += t * ((lu + log((double)v[o])) - 1.0);
+            }
+        }
+    }
+    s_tc = block_sum(s_tc, sh);
+    s_ent = block_sum(s_ent, sh);
+    s_sp = block_sum(s_sp, sh);
+    if (threadIdx.x == 0) {
+        A.stat[k].transport = s_tc;
+        A.stat[k].negent = s_ent;
+        A.stat[k].sparseobj = s_sp;
+    }
+}
+
+template <int PREC, int D>
+static void run_b_obj(int count, const BObjArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((k_b_objective<PREC, D>), dim3(count), dim3(256), 0, st, a);
+}
+
+template <int D>
+static void run_b_obj_d(int precision, int count, const BObjArgs& a, hipStream_t st) {
+    if (precision == P_F64)
+        run_b_obj<P_F64, D>(count, a, st);
+    else
+        run_b_obj<P_F32, D>(count, a, st);
+}
+
+hipError_t launch_batch_objective(int precision, int count, const BObjArgs& a, hipStream_t st) {
+    switch (a.d) {
+        case 2: run_b_obj_d<2>(precision, count, a, st); break;
+        case 3: run_b_obj_d<3>(precision, count, a, st); break;
+        case 10: run_b_obj_d<10>(precision, count, a, st); break;
+        default: run_b_obj_d<0>(precision, count, a, st); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/sparsink.h"
+
 namespace ss {
 
 // Device-resident state of one Sinkhorn loop.  Written only by block 0 of
@@ -257,5 +259,96 @@ struct DenseObjArgs {
     const double* statsc;
 };
 hipError_t launch_dense_objective(const DenseObjArgs& a, hipStream_t st);
+
+// ---- batches (sample.hip: sampling stages; batch.hip: loop, objective)
+constexpr int kBatchMaxSide = 4096;
+
+// Per problem, written by the host.
+struct BProb {
+    int64_t n, m;      // points of x and y
+    int64_t xo, yo;    // first row / column in the concatenated arrays
+    int64_t mo, mto;   // first word of its mask / transposed mask
+    int64_t W, Wn;     // words per mask row (ceil(m/64)) / per transposed row (ceil(n/64))
+    double s;          // budget
+    uint32_t pidx;     // hash counter word
+    int32_t pad;
+};
+
+// Per problem, written by the device.
+struct BStat {
+    double cmax, inv_cmax, sa, sb;
+    double sum_a_act, sum_b_act, dropped_a, dropped_b, empty_rows, empty_cols;
+    double transport, negent, sparseobj, err;
+    int64_t nnz;
+    int32_t iters, status;
+};
+
+struct BatchArgs {
+    int count, d;
+    const BProb* prob;          // [count]
+    BStat* stat;                // [count]
+    const int64_t* tile_cmax;   // [count + 1] prefix of cost-scan tiles
+    const int64_t* tile_mask;   // [count + 1] prefix of mask tiles
+    const int64_t* tile_tr;     // [count + 1] prefix of transpose tiles
+    const int64_t* row_off;     // [count + 1] prefix of n
+    const int64_t* col_off;     // [count + 1] prefix of m
+    int64_t rows, cols;         // sum n, sum m
+    const double *x, *y, *a, *b;
+    double *row_fac, *col_fac;  // alpha_i, sqrt(b_j)
+    double *a_eff, *b_eff;
+    uint64_t *mask, *maskT;
+    int32_t *row_cnt, *col_cnt;
+    int64_t *row_ptr, *col_ptr;
+    uint16_t *col_idx, *row_idx;
+    void *val, *val_t;
+    int64_t cap;
+    int cost;                   // SS_COST_*
+    int empty_policy;           // SS_EMPTY_RENORMALIZE or SS_EMPTY_ZERO
+    double eps;
+    uint32_t k0, k1;
+    double* gstats;             // ST_COUNT slots (input validation)
+};
+
+struct BIterArgs {
+    int count;
+    const int32_t* order;       // problems, largest first
+    int32_t* queue;             // next position in `order` (zeroed before the launch)
+    const BProb* prob;
+    BStat* stat;
+    const int64_t *row_ptr, *col_ptr;
+    const uint16_t *col_idx, *row_idx;
+    const void *val, *val_t;
+    const double *a_eff, *b_eff;
+    int64_t rows, cols, cap;
+    int nmax, mmax;             // largest n, m (LDS sizing)
+    const double *init_log_u, *init_log_v;
+    void *u, *v;                // iterate of every problem (FP64 or FP32)
+    double *u_out, *v_out;      // optional FP64 copies
+    int max_iter;
+    double tol;
+};
+
+struct BObjArgs {
+    int d;
+    const BProb* prob;
+    BStat* stat;
+    const int64_t* row_ptr;
+    const uint16_t* col_idx;
+    const void* val;
+    const void *u, *v;
+    const double *x, *y;
+    int64_t rows, cols, cap;
+    const int64_t* col_ptr;
+};
+
+hipError_t launch_batch_sample(int precision, const BatchArgs& a, int64_t ntile_cmax,
+                               int64_t ntile_mask, int64_t ntile_tr, int64_t* scan_scratch,
+                               hipStream_t st);
+hipError_t batch_init();
+size_t batch_iter_lds(int precision, int nmax, int mmax);
+int batch_iter_grid(int precision, int lanes, int block, int nmax, int mmax);
+hipError_t launch_batch_iterate(int precision, int lanes, int block, int grid, const BIterArgs& a,
+                                hipStream_t st);
+hipError_t launch_batch_objective(int precision, int count, const BObjArgs& a, hipStream_t st);
 
 }  // namespace ss

@@ -290,17 +290,15 @@ hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, const double
 // and keeps its 16 column factors in registers while it walks the 16 rows.
 constexpr int kMaskRows = 16;
 
+// One tile: rows row0 .. row0 + 15 of one problem, mask words ct * 64 ..
+// ct * 64 + 63; adds the popcounts to row_cnt.  All 256 threads call it.
 template <bool UOT, int D>
-__global__ __launch_bounds__(256) void k_mask(ProbParams pp, int64_t n, int64_t m, int64_t W,
-                                              int64_t ncol_tiles, uint64_t* __restrict__ mask,
-                                              int32_t* __restrict__ row_cnt,
-                                              const double* __restrict__ stats) {
-    __shared__ uint64_t tile[kMaskRows][64];
+__device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64_t m, int64_t W,
+                                          int64_t rt, int64_t ct, uint64_t* __restrict__ mask,
+                                          int32_t* __restrict__ row_cnt, double kappa,
+                                          uint64_t (*tile)[64]) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
-    const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
     const int64_t row0 = rt * kMaskRows;
-    const double kappa = UOT ? pp.s / stats[ST_Z] : 0.0;
-
     double cf[16];
 #pragma unroll
     for (int gg = 0; gg < 4; ++gg) {
@@ -361,6 +359,17 @@ __global__ __launch_bounds__(256) void k_mask(ProbParams pp, int64_t n, int64_t 
 }
 
 template <bool UOT, int D>
+__global__ __launch_bounds__(256) void k_mask(ProbParams pp, int64_t n, int64_t m, int64_t W,
+                                              int64_t ncol_tiles, uint64_t* __restrict__ mask,
+                                              int32_t* __restrict__ row_cnt,
+                                              const double* __restrict__ stats) {
+    __shared__ uint64_t tile[kMaskRows][64];
+    const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
+    const double kappa = UOT ? pp.s / stats[ST_Z] : 0.0;
+    mask_tile<UOT, D>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile);
+}
+
+template <bool UOT, int D>
 static void run_mask(const ProbParams& pp, int64_t n, int64_t m, uint64_t* mask, int32_t* row_cnt,
                      const double* stats, hipStream_t st) {
     const int64_t W = (m + 63) / 64;
@@ -408,13 +417,14 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t w) {
 constexpr int kTrRowBlocks = 8;   // 64-row blocks per tile
 constexpr int kTrWordCols = 16;   // mask word columns per tile
 
-__global__ __launch_bounds__(256) void k_transpose(const uint64_t* __restrict__ mask, int64_t n,
-                                                   int64_t m, int64_t W, int64_t Wn,
-                                                   int64_t ncol_tiles, uint64_t* __restrict__ maskT,
-                                                   int32_t* __restrict__ col_cnt) {
-    __shared__ uint64_t tile[64][kTrWordCols + 1];
+// One tile: 64-row blocks rt * 8 .. rt * 8 + 7, mask word columns ct * 16 ..
+// ct * 16 + 15; adds the popcounts to col_cnt.  All 256 threads call it.
+__device__ __forceinline__ void transpose_tile(const uint64_t* __restrict__ mask, int64_t n,
+                                               int64_t m, int64_t W, int64_t Wn, int64_t rt,
+                                               int64_t ct, uint64_t* __restrict__ maskT,
+                                               int32_t* __restrict__ col_cnt,
+                                               uint64_t (*tile)[kTrWordCols + 1]) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
-    const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
     uint64_t out[4][kTrRowBlocks];
     const int lr = threadIdx.x >> 2;          // row of the tile this thread loads
     const int lq = (threadIdx.x & 3) * 4;     // first of its 4 words
@@ -448,6 +458,15 @@ __global__ __launch_bounds__(256) void k_transpose(const uint64_t* __restrict__ 
         }
         if (cnt) atomicAdd(&col_cnt[j], cnt);
     }
+}
+
+__global__ __launch_bounds__(256) void k_transpose(const uint64_t* __restrict__ mask, int64_t n,
+                                                   int64_t m, int64_t W, int64_t Wn,
+                                                   int64_t ncol_tiles, uint64_t* __restrict__ maskT,
+                                                   int32_t* __restrict__ col_cnt) {
+    __shared__ uint64_t tile[64][kTrWordCols + 1];
+    const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
+    transpose_tile(mask, n, m, W, Wn, rt, ct, maskT, col_cnt, tile);
 }
 
 hipError_t launch_transpose(const uint64_t* mask, int64_t n, int64_t m, uint64_t* maskT,
@@ -583,19 +602,14 @@ __device__ __forceinline__ void store_value(void* val, int64_t pos, double v, do
     if (PREC == P_LOG) ((float*)val)[pos] = (float)lv;
 }
 
-template <int ROLE, bool UOT, int PREC, int D>
-__global__ __launch_bounds__(256) void k_fill(ProbParams pp, const double* __restrict__ stats,
-                                              const uint64_t* __restrict__ bits, int64_t nlines,
-                                              int64_t words, const int64_t* __restrict__ ptr,
-                                              int32_t* __restrict__ idx, void* __restrict__ val,
-                                              int64_t cap) {
-    __shared__ int32_t queue[4][kFillQueue];
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
-    const int64_t line = (int64_t)blockIdx.x * 4 + wv;
-    const bool active = line < nlines;
-    const double kappa = UOT ? pp.s / stats[ST_Z] : 0.0;
-    const uint64_t* row = bits + (active ? line : 0) * words;
-    const int64_t base = active ? ptr[line] : 0;
+// One line, by one wave: `row` is the line's mask words, `base` its first
+// entry slot, `line` its index in the problem; indices are written as IdxT.
+template <int ROLE, bool UOT, int PREC, int D, typename IdxT>
+__device__ __forceinline__ void fill_line(const ProbParams& pp, double kappa, bool active,
+                                          const uint64_t* __restrict__ row, int64_t line,
+                                          int64_t words, int64_t base, IdxT* __restrict__ idx,
+                                          void* __restrict__ val, int64_t cap, int32_t* queue) {
+    const int lane = threadIdx.x & (kWave - 1);
     int64_t run = base;
     for (int64_t w0 = 0; w0 < words; w0 += kWave) {
         const int64_t widx = w0 + lane;
@@ -608,9 +622,9 @@ __global__ __launch_bounds__(256) void k_fill(ProbParams pp, const double* __res
             word &= word - 1;
             const int64_t other = 64 * widx + b;
             const int64_t local = pos - base;
-            if (pos < cap) idx[pos] = (int32_t)other;
+            if (pos < cap) idx[pos] = (IdxT)other;
             if (local < kFillQueue) {
-                queue[wv][local] = (int32_t)other;
+                queue[local] = (int32_t)other;
             } else if (pos < cap) {
                 const int64_t i = ROLE == 0 ? line : other;
                 const int64_t j = ROLE == 0 ? other : line;
@@ -628,13 +642,29 @@ __global__ __launch_bounds__(256) void k_fill(ProbParams pp, const double* __res
     for (int64_t e = lane; e < nq; e += kWave) {
         const int64_t pos = base + e;
         if (pos >= cap) break;
-        const int64_t other = queue[wv][e];
+        const int64_t other = queue[e];
         const int64_t i = ROLE == 0 ? line : other;
         const int64_t j = ROLE == 0 ? other : line;
         double lv;
         const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
         store_value<PREC>(val, pos, v, lv);
     }
+}
+
+template <int ROLE, bool UOT, int PREC, int D>
+__global__ __launch_bounds__(256) void k_fill(ProbParams pp, const double* __restrict__ stats,
+                                              const uint64_t* __restrict__ bits, int64_t nlines,
+                                              int64_t words, const int64_t* __restrict__ ptr,
+                                              int32_t* __restrict__ idx, void* __restrict__ val,
+                                              int64_t cap) {
+    __shared__ int32_t queue[4][kFillQueue];
+    const int wv = threadIdx.x >> 6;
+    const int64_t line = (int64_t)blockIdx.x * 4 + wv;
+    const bool active = line < nlines;
+    const double kappa = UOT ? pp.s / stats[ST_Z] : 0.0;
+    fill_line<ROLE, UOT, PREC, D, int32_t>(pp, kappa, active, bits + (active ? line : 0) * words,
+                                          line, words, active ? ptr[line] : 0, idx, val, cap,
+                                          queue[wv]);
 }
 
 template <int ROLE, bool UOT, int PREC, int D>
@@ -709,6 +739,231 @@ hipError_t launch_empty_policy(const double* a, const int32_t* cnt, int64_t n, i
     if (renormalize)
         hipLaunchKernelGGL(k_scale_by, dim3(grid_for(n)), dim3(kBlock), 0, st, a_eff, n,
                            stats + s_act, a_eff);
+    return hipGetLastError();
+}
+
+// ================================================================== batches
+// The sampling stages of a batch of OT problems, one launch per stage over
+// all problems: block b works on tile b - pre[k] of the problem k that owns
+// it (pre = prefix of the per-problem tile counts, searched by every block).
+
+// Last k in [0, count) with pre[k] <= key.
+__device__ __forceinline__ int owner_of(const int64_t* __restrict__ pre, int count, int64_t key) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= key)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Perfect binary tree (adjacent pairs) over v[0..4096), zero padded past n,
+// with 1024 threads; the result (in every thread) equals the tree sum of the
+// vector padded to any power of two >= n.  sh: 1024 doubles.  Callers may
+// have just written v: the first barrier orders those writes.
+__device__ double block_tree4096(const double* v, int64_t n, double* sh) {
+    const int tid = threadIdx.x;
+    __syncthreads();  // v was just written by other threads
+    double e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = (tid * 4 + k < n) ? v[tid * 4 + k] : 0.0;
+    sh[tid] = (e[0] + e[1]) + (e[2] + e[3]);
+    __syncthreads();
+    for (int s = 1; s < 1024; s <<= 1) {
+        if ((tid & (2 * s - 1)) == 0) sh[tid] = sh[tid] + sh[tid + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_b_cmax(BatchArgs A) {
+    const int k = owner_of(A.tile_cmax, A.count, blockIdx.x);
+    const BProb P = A.prob[k];
+    const int64_t t = blockIdx.x - A.tile_cmax[k];
+    const int64_t nct = (P.m + kCostTileCols - 1) / kCostTileCols;
+    const int64_t rt = t / nct, ct = t % nct;
+    const int d = A.d;
+    const double* x = A.x + P.xo * d;
+    const double* y = A.y + P.yo * d;
+    const int64_t i = rt * 256 + threadIdx.x;
+    const int64_t j0 = ct * kCostTileCols;
+    const int64_t j1 = (j0 + kCostTileCols < P.m) ? j0 + kCostTileCols : P.m;
+    double mx = 0.0;
+    if (i < P.n) {
+        for (int64_t j = j0; j < j1; ++j) {
+            const double c = sqdist<D>(x + i * d, y + j * d, d);
+            mx = c > mx ? c : mx;
+        }
+    }
+    mx = group_max<kWave>(mx);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        atomicMax((unsigned long long*)&A.stat[k].cmax, (unsigned long long)__double_as_longlong(mx));
+}
+
+// One block (1024 threads) per problem: C scale, S_a, S_b (tree sums of
+// sqrt a, sqrt b), alpha_i = s sqrt(a_i) / (S_a S_b), sqrt(b_j)  (eq. (pij-ot)).
+__global__ __launch_bounds__(1024) void k_b_prep(BatchArgs A) {
+    __shared__ double v[kBatchMaxSide];
+    __shared__ double sh[1024];
+    const int k = blockIdx.x;
+    const BProb P = A.prob[k];
+    const double cmax = A.stat[k].cmax;
+    for (int64_t i = threadIdx.x; i < P.n; i += blockDim.x) v[i] = sqrt(A.a[P.xo + i]);
+    const double sa = block_tree4096(v, P.n, sh);
+    for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x) v[j] = sqrt(A.b[P.yo + j]);
+    const double sb = block_tree4096(v, P.m, sh);
+    const double kappa = P.s / (sa * sb);
+    for (int64_t i = threadIdx.x; i < P.n; i += blockDim.x)
+        A.row_fac[P.xo + i] = kappa * sqrt(A.a[P.xo + i]);
+    for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x) A.col_fac[P.yo + j] = v[j];
+    if (threadIdx.x == 0) {
+        A.stat[k].inv_cmax = (A.cost == 0 && cmax > 0.0) ? 1.0 / cmax : 1.0;
+        A.stat[k].sa = sa;
+        A.stat[k].sb = sb;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_b_mask(BatchArgs A) {
+    __shared__ uint64_t tile[kMaskRows][64];
+    const int k = owner_of(A.tile_mask, A.count, blockIdx.x);
+    const BProb P = A.prob[k];
+    const int64_t t = blockIdx.x - A.tile_mask[k];
+    const int64_t nct = (P.W + 63) / 64;
+    ProbParams pp;
+    pp.uot = 0;
+    pp.row_fac = A.row_fac + P.xo;
+    pp.col_fac = A.col_fac + P.yo;
+    pp.problem_index = P.pidx;
+    pp.k0 = A.k0;
+    pp.k1 = A.k1;
+    mask_tile<false, 2>(pp, P.n, P.m, P.W, t / nct, t % nct, A.mask + P.mo, A.row_cnt + P.xo, 0.0,
+                        tile);
+}
+
+__global__ __launch_bounds__(256) void k_b_transpose(BatchArgs A) {
+    __shared__ uint64_t tile[64][kTrWordCols + 1];
+    const int k = owner_of(A.tile_tr, A.count, blockIdx.x);
+    const BProb P = A.prob[k];
+    const int64_t t = blockIdx.x - A.tile_tr[k];
+    const int64_t nct = (P.W + kTrWordCols - 1) / kTrWordCols;
+    transpose_tile(A.mask + P.mo, P.n, P.m, P.W, P.Wn, t / nct, t % nct, A.maskT + P.mto,
+                   A.col_cnt + P.yo, tile);
+}
+
+template <int ROLE, int PREC, int D>
+__global__ __launch_bounds__(256) void k_b_fill(BatchArgs A) {
+    __shared__ int32_t queue[4][kFillQueue];
+    const int wv = threadIdx.x >> 6;
+    const int64_t lines = ROLE == 0 ? A.rows : A.cols;
+    const int64_t L = (int64_t)blockIdx.x * 4 + wv;
+    const bool active = L < lines;
+    const int64_t* off = ROLE == 0 ? A.row_off : A.col_off;
+    const int k = owner_of(off, A.count, active ? L : lines - 1);
+    const BProb P = A.prob[k];
+    const int64_t local = (active ? L : lines - 1) - off[k];
+    ProbParams pp;
+    pp.uot = 0;
+    pp.s = P.s;
+    pp.eps = A.eps;
+    pp.inv_cmax = A.stat[k].inv_cmax;
+    pp.row_fac = A.row_fac + P.xo;
+    pp.col_fac = A.col_fac + P.yo;
+    pp.x = A.x + P.xo * A.d;
+    pp.y = A.y + P.yo * A.d;
+    pp.d = A.d;
+    const uint64_t* bits = ROLE == 0 ? A.mask + P.mo + local * P.W : A.maskT + P.mto + local * P.Wn;
+    const int64_t words = ROLE == 0 ? P.W : P.Wn;
+    const int64_t* ptr = ROLE == 0 ? A.row_ptr : A.col_ptr;
+    fill_line<ROLE, false, PREC, D, uint16_t>(pp, 0.0, active, bits, local, words,
+                                             active ? ptr[L] : 0, ROLE == 0 ? A.col_idx : A.row_idx,
+                                             ROLE == 0 ? A.val : A.val_t, A.cap, queue[wv]);
+}
+
+// One block (1024 threads) per problem, after the counts: the empty-line
+// policy on both sides and the problem's entry count.
+__global__ __launch_bounds__(1024) void k_b_empty(BatchArgs A) {
+    __shared__ double v[kBatchMaxSide];
+    __shared__ double sh[1024];
+    const int k = blockIdx.x;
+    const BProb P = A.prob[k];
+    double res[2][3];
+    for (int side = 0; side < 2; ++side) {
+        const int64_t n = side == 0 ? P.n : P.m;
+        const int64_t o = side == 0 ? P.xo : P.yo;
+        const double* a = side == 0 ? A.a : A.b;
+        const int32_t* cnt = side == 0 ? A.row_cnt : A.col_cnt;
+        double* eff = side == 0 ? A.a_eff : A.b_eff;
+        for (int q = 0; q < 3; ++q) {
+            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+                const bool on = cnt[o + i] > 0;
+                const double ai = a[o + i];
+                v[i] = q == 0 ? (on ? ai : 0.0) : q == 1 ? (on ? 0.0 : ai) : ((!on && ai > 0.0) ? 1.0 : 0.0);
+            }
+            res[side][q] = block_tree4096(v, n, sh);
+        }
+        const bool renorm = A.empty_policy == SS_EMPTY_RENORMALIZE;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const double act = cnt[o + i] > 0 ? a[o + i] : 0.0;
+            eff[o + i] = renorm ? act / res[side][0] : act;
+        }
+    }
+    if (threadIdx.x == 0) {
+        BStat& S = A.stat[k];
+        S.sum_a_act = res[0][0];
+        S.dropped_a = res[0][1];
+        S.empty_rows = res[0][2];
+        S.sum_b_act = res[1][0];
+        S.dropped_b = res[1][1];
+        S.empty_cols = res[1][2];
+        S.nnz = A.row_ptr[P.xo + P.n] - A.row_ptr[P.xo];
+    }
+}
+
+template <int D>
+static void run_b_cmax(const BatchArgs& a, int64_t nt, hipStream_t st) {
+    hipLaunchKernelGGL(k_b_cmax<D>, dim3((unsigned)nt), dim3(256), 0, st, a);
+}
+
+template <int PREC, int D>
+static void run_b_fill(const BatchArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((k_b_fill<0, PREC, D>), dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_b_fill<1, PREC, D>), dim3((unsigned)((a.cols + 3) / 4)), dim3(256), 0, st, a);
+}
+
+template <int D>
+static void run_b_fill_d(int precision, const BatchArgs& a, hipStream_t st) {
+    if (precision == P_F64)
+        run_b_fill<P_F64, D>(a, st);
+    else
+        run_b_fill<P_F32, D>(a, st);
+}
+
+hipError_t launch_batch_sample(int precision, const BatchArgs& a, int64_t ntile_cmax,
+                               int64_t ntile_mask, int64_t ntile_tr, int64_t* scan_scratch,
+                               hipStream_t st) {
+    hipError_t e = launch_fill_f64(a.gstats, ST_COUNT, 0.0, st);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)a.stat, (int64_t)a.count * sizeof(BStat) / 4, 0u, st);
+    if (e == hipSuccess) e = launch_fill_i32(a.row_cnt, a.rows, 0, st);
+    if (e == hipSuccess) e = launch_fill_i32(a.col_cnt, a.cols, 0, st);
+    if (e == hipSuccess) e = launch_validate(a.a, a.rows, a.x, a.rows * a.d, a.gstats, st);
+    if (e == hipSuccess) e = launch_validate(a.b, a.cols, a.y, a.cols * a.d, a.gstats, st);
+    if (e != hipSuccess) return e;
+    SS_DISPATCH_D(a.d, run_b_cmax, a, ntile_cmax, st);
+    hipLaunchKernelGGL(k_b_prep, dim3(a.count), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_b_mask, dim3((unsigned)ntile_mask), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_b_transpose, dim3((unsigned)ntile_tr), dim3(256), 0, st, a);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_scan(a.row_cnt, a.rows, a.row_ptr, scan_scratch, st);
+    if (e == hipSuccess) e = launch_scan(a.col_cnt, a.cols, a.col_ptr, scan_scratch, st);
+    if (e != hipSuccess) return e;
+    SS_DISPATCH_D(a.d, run_b_fill_d, precision, a, st);
+    hipLaunchKernelGGL(k_b_empty, dim3(a.count), dim3(1024), 0, st, a);
     return hipGetLastError();
 }
 

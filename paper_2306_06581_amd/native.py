@@ -64,6 +64,19 @@ class SsSparse(ctypes.Structure):
                 ("z_norm", c_double)]
 
 
+class SsBatch(ctypes.Structure):
+    _fields_ = [("count", c_int32), ("d", c_int32), ("n", c_void_p), ("m", c_void_p),
+                ("s", c_void_p), ("problem_index", c_void_p), ("x", c_void_p), ("y", c_void_p),
+                ("a", c_void_p), ("b", c_void_p)]
+
+
+class SsSchedule(ctypes.Structure):
+    _fields_ = [("lanes_per_line", c_int32), ("block_threads", c_int32)]
+
+
+BATCH_MAX_SIDE = 4096
+
+
 # Every symbol the header declares, with its signature.
 SIGNATURES = {
     "ss_workspace_size": (c_int, [POINTER(SsProblem), POINTER(SsOptions), POINTER(c_size_t)]),
@@ -77,6 +90,12 @@ SIGNATURES = {
                                c_void_p, POINTER(SsResult)]),
     "ss_time_iterations": (c_int, [POINTER(SsProblem), POINTER(SsOptions), c_void_p, c_size_t,
                                    c_void_p, c_int32, POINTER(c_double)]),
+    "ss_batch_workspace_size": (c_int, [POINTER(SsBatch), POINTER(SsOptions), POINTER(c_size_t)]),
+    "spar_sink_batched": (c_int, [POINTER(SsBatch), POINTER(SsOptions), POINTER(SsSchedule),
+                                  c_void_p, c_size_t, c_void_p, POINTER(SsResult)]),
+    "ss_autotune_batched": (c_int, [POINTER(SsBatch), POINTER(SsOptions), c_void_p, c_size_t,
+                                    c_void_p, POINTER(SsSchedule), POINTER(c_float),
+                                    POINTER(c_int32)]),
     "ss_status_string": (c_char_p, [c_int]),
     "ss_last_error": (c_char_p, []),
     "ss_version": (c_int, []),

@@ -49,6 +49,8 @@ def _c_layout():
 int main(void) {
   printf("ss_problem %zu\nss_options %zu\nss_result %zu\nss_sparse %zu\n",
          sizeof(ss_problem), sizeof(ss_options), sizeof(ss_result), sizeof(ss_sparse));
+  printf("ss_batch %zu\nss_schedule %zu\n", sizeof(ss_batch), sizeof(ss_schedule));
+  P(ss_batch, s) P(ss_batch, x) P(ss_batch, b) P(ss_schedule, block_threads)
   P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist)
   P(ss_result, nnz) P(ss_result, iters) P(ss_result, t_obj_ms) P(ss_sparse, capacity)
   P(ss_sparse, z_norm)
@@ -80,6 +82,12 @@ def test_struct_layout_matches_header():
     assert N.SsResult.t_obj_ms.offset == lay["ss_result.t_obj_ms"]
     assert N.SsSparse.capacity.offset == lay["ss_sparse.capacity"]
     assert N.SsSparse.z_norm.offset == lay["ss_sparse.z_norm"]
+    assert ctypes.sizeof(N.SsBatch) == lay["ss_batch"]
+    assert ctypes.sizeof(N.SsSchedule) == lay["ss_schedule"]
+    assert N.SsBatch.s.offset == lay["ss_batch.s"]
+    assert N.SsBatch.x.offset == lay["ss_batch.x"]
+    assert N.SsBatch.b.offset == lay["ss_batch.b"]
+    assert N.SsSchedule.block_threads.offset == lay["ss_schedule.block_threads"]
 
 
 def _fake_problem(N, n=8, m=8, d=2):
@@ -163,3 +171,69 @@ def test_status_strings():
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert N.lib.ss_status_string(code).decode() != "unknown status"
     assert N.lib.ss_status_string(99).decode() == "unknown status"
+
+
+def _fake_batch(N, ns=(3, 5), ms=(4, 6), ss=(10.0, 20.0), d=3):
+    import numpy as np
+    keep = dict(n=np.array(ns, dtype=np.int64), m=np.array(ms, dtype=np.int64),
+                s=np.array(ss, dtype=np.float64))
+    b = N.SsBatch(len(ns), d, keep["n"].ctypes.data, keep["m"].ctypes.data, keep["s"].ctypes.data,
+                  None, 256, 512, 768, 1024)
+    return b, keep
+
+
+@pytest.mark.parametrize("change", ["count0", "n_big", "m0", "s_neg", "d0", "lam", "log",
+                                    "delta", "hist", "fail_policy"])
+def test_batch_arguments_rejected(change):
+    import numpy as np
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd.api import make_options
+    b, keep = _fake_batch(N)
+    opts = make_options(0.05, precision="f32")
+    if change == "count0":
+        b.count = 0
+    elif change == "n_big":
+        keep["n"][1] = N.BATCH_MAX_SIDE + 1
+    elif change == "m0":
+        keep["m"][0] = 0
+    elif change == "s_neg":
+        keep["s"][0] = -1.0
+    elif change == "d0":
+        b.d = 0
+    elif change == "lam":
+        opts = make_options(0.05, lam=1.0, precision="f32")
+    elif change == "log":
+        opts = make_options(0.05, precision="f32_log")
+    elif change == "delta":
+        opts = make_options(0.05, precision="f32", stop_rule="delta")
+    elif change == "hist":
+        opts = make_options(0.05, precision="f32", err_hist=None)
+        opts.err_hist = 4096
+    elif change == "fail_policy":
+        opts = make_options(0.05, precision="f32", empty_policy="fail")
+    out = ctypes.c_size_t(0)
+    assert N.lib.ss_batch_workspace_size(ctypes.byref(b), ctypes.byref(opts),
+                                         ctypes.byref(out)) == N.SS_E_INVALID_ARG
+    res = (N.SsResult * 2)()
+    assert N.lib.spar_sink_batched(ctypes.byref(b), ctypes.byref(opts), None, ctypes.c_void_p(4096),
+                                   1 << 40, None, res) == N.SS_E_INVALID_ARG
+
+
+def test_batch_workspace_and_schedule_checks():
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd.api import make_options
+    b, keep = _fake_batch(N, ns=(4096, 300), ms=(4096, 17), ss=(8 * 4096 * 8.3, 500.0))
+    opts = make_options(0.05, precision="f32")
+    out = ctypes.c_size_t(0)
+    assert N.lib.ss_batch_workspace_size(ctypes.byref(b), ctypes.byref(opts), ctypes.byref(out)) == 0
+    # masks of both problems and their transposes at least
+    assert out.value >= 2 * (4096 * 64 + 300 * 1) * 8
+    res = (N.SsResult * 2)()
+    assert N.lib.spar_sink_batched(ctypes.byref(b), ctypes.byref(opts), None, ctypes.c_void_p(4096),
+                                   16, None, res) == N.SS_E_WORKSPACE
+    bad = N.SsSchedule(12, 256)
+    assert N.lib.spar_sink_batched(ctypes.byref(b), ctypes.byref(opts), ctypes.byref(bad),
+                                   ctypes.c_void_p(4096), 1 << 40, None, res) == N.SS_E_INVALID_ARG
+    bad = N.SsSchedule(8, 128)
+    assert N.lib.spar_sink_batched(ctypes.byref(b), ctypes.byref(opts), ctypes.byref(bad),
+                                   ctypes.c_void_p(4096), 1 << 40, None, res) == N.SS_E_INVALID_ARG
