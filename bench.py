@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched workload (profiling runs)")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--warmstart-train", type=int, default=100_000,
+                    help="training problems for the learned warm start (0: skip)")
+    ap.add_argument("--warmstart-only", action="store_true")
     return ap.parse_args()
 
 
@@ -161,6 +164,40 @@ def batched_bench(count: int, steps: int) -> dict:
             "max_marginal_err": float(max(r.marginal_err for r in res))}
 
 
+def warmstart_bench(ntrain: int, count: int) -> dict:
+    """The DeepSets warm start trained on the GPU with the library's own step:
+    ntrain problems of the batched workload's generator (seeds 1000 + k, one
+    chunk of 512 per seed), targets from spar_sink_batched (FP32, tol 1e-6),
+    one pass in minibatches of 64 with Adam (lr 1e-3); evaluated on the
+    batched workload itself (seed 0) against the plain start."""
+    import torch
+
+    from paper_2306_06581_amd import api as A
+    from paper_2306_06581_amd import warmstart as WS
+    from paper_2306_06581_amd import workloads as W
+
+    net = A.WarmStartNet(seed=0)
+    chunk = 512
+    t_gen = t_train = 0.0
+    losses = []
+    for c in range((ntrain + chunk - 1) // chunk):
+        probs = W.batch_ot(min(chunk, ntrain - c * chunk), seed=1000 + c)
+        t0 = time.perf_counter()
+        mbs = WS.solution_minibatches(probs, eps=0.05, seed=1000 + c)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        losses += WS.train(net, mbs, eps=0.05, lr=1e-3)
+        torch.cuda.synchronize()
+        t_gen += t1 - t0
+        t_train += time.perf_counter() - t1
+    ev = WS.evaluate(net, W.batch_ot(count, seed=0), eps=0.05, seed=0)
+    ev.update({"train_problems": ntrain, "train_steps": len(losses),
+               "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:])),
+               "data_s": t_gen, "train_s": t_train,
+               "train_ms_per_step": t_train * 1e3 / max(len(losses), 1)})
+    return ev
+
+
 def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
     """The FP64 oracle timed on a bounded sample of the same workload."""
     import numpy as np
@@ -222,6 +259,11 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"batched": batched_bench(args.batch_count, args.steps)}))
+        return
+    if args.warmstart_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"warmstart": warmstart_bench(args.warmstart_train, args.batch_count)}))
         return
     import torch
 
@@ -301,6 +343,8 @@ def main():
         out["speedup_vs_dense"] = dms / ms_step
     if not args.no_batched:
         out["batched"] = batched_bench(args.batch_count, args.steps)
+    if args.warmstart_train > 0:
+        out["warmstart"] = warmstart_bench(args.warmstart_train, args.batch_count)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, r.iters, args.precision == "f32_log")
     print(json.dumps(out))

@@ -255,6 +255,66 @@ int spar_sink_batched(const ss_batch *batch, const ss_options *opts, const ss_sc
 int ss_autotune_batched(const ss_batch *batch, const ss_options *opts, void *ws, size_t ws_bytes,
                         void *stream, ss_schedule *best, float *cand_ms, int32_t *ncand);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start: a DeepSets network (hidden width 256, d = 3) that
+ * predicts log u^0 and log v^0 for every problem of a batch.  Points enter in
+ * kernel units: centred on the mean of all points of their problem and
+ * divided by sqrt(eps C_s), C_s = max |x_i - y_j|^2 for SS_COST_SQEUCLID_MAXNORM
+ * and 1 for SS_COST_SQEUCLID (the Gibbs kernel of eq. (rot) becomes
+ * exp(-|x' - y'|^2)).  For the side predicting the scalings of points z_i
+ * with weights w_i given the opposite measure (o_j, q_j), j < m:
+ *   phi_j = ReLU(P [o_j, m q_j] + p),  e = mean_j phi_j,  g = U e + c1,
+ *   h1_i = ReLU(W1 z_i + g),  h2_i = ReLU(W2 h1_i + c2),  psi_i = w3 . h2_i + c3,
+ *   log y0_i = log w_i + psi_i;
+ * the u side uses (x, a) with opposite (y, b), the v side (y, b) with (x, a).
+ * Training minimises the mean over sides of the centred squared error
+ * mean_M (d - mean_M d)^2, d = psi - (log y* - log w), over the points with
+ * a finite target: Alg. 1 reads only v^0 and a constant shift of log v^0
+ * leaves its iterates' plans unchanged (eq. (rot-solu)).
+ *
+ * params   device FP32 [SS_MLP_PARAMS] master weights in the order
+ *          P (256x4), p (256), W1 (256x3), U (256x256), c1 (256),
+ *          W2 (256x256), c2 (256), w3 (256), c3 (1), matrices row-major.
+ * bf16     device BF16 copy [SS_MLP_PARAMS] used by the kernels.
+ * w2t      device BF16 [256 x 256]: W2 transposed.
+ * adam_m, adam_v  device FP32 [SS_MLP_PARAMS] Adam moments (zero at start).
+ * step     Adam steps taken (incremented by ss_warmstart_train_step).
+ * All buffers are owned by the caller. */
+#define SS_MLP_PARAMS 133889
+
+typedef struct ss_mlp {
+    float *params;
+    void *bf16;
+    void *w2t;
+    float *adam_m, *adam_v;
+    int32_t step;
+    int32_t reserved;
+} ss_mlp;
+
+/* Refreshes bf16 and w2t from params (after the caller changed params). */
+int ss_mlp_sync(ss_mlp *mlp, void *stream);
+
+/* Workspace bytes for ss_warmstart_predict / ss_warmstart_train_step on this
+ * batch (d must be 3; the problem sizes of ss_batch apply). */
+int ss_warmstart_workspace_size(const ss_batch *batch, size_t *bytes);
+
+/* log_u0 (device FP64, sum(n)) and log_v0 (device FP64, sum(m)) for every
+ * problem; pass them as init_log_u / init_log_v to spar_sink_batched (or to
+ * spar_sink_ot per problem).  eps and cost are those of the solve.  Either
+ * output may be NULL. */
+int ss_warmstart_predict(const ss_mlp *mlp, const ss_batch *batch, double eps, int32_t cost,
+                         double *log_u0, double *log_v0, void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (learning rate lr, betas 0.9 / 0.999, eps 1e-8) on the batch
+ * loss against the solutions tgt_log_u (device FP64, sum(n)) and tgt_log_v
+ * (sum(m)); entries that are not finite (empty lines) are left out.  *loss
+ * (host) receives the batch loss before the step; grad_out (device FP32
+ * [SS_MLP_PARAMS], may be NULL) receives its gradient.  lr = 0 computes the
+ * loss and gradient without changing the weights or the step count. */
+int ss_warmstart_train_step(ss_mlp *mlp, const ss_batch *batch, double eps, int32_t cost,
+                            const double *tgt_log_u, const double *tgt_log_v, float lr, void *ws,
+                            size_t ws_bytes, void *stream, float *loss, float *grad_out);
+
 const char *ss_status_string(int status);
 const char *ss_last_error(void);
 int ss_version(void);

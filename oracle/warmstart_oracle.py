@@ -11,8 +11,13 @@ an additive constant matters: the loss is a centred (shift-invariant) squared
 error of the predicted log-correction.  The same network is applied with the
 roles of the two measures swapped to predict log u^0.
 
-For the side that predicts the scalings of points z_i (weights w_i, count n)
-given the opposite measure (points o_j, weights q_j, count m):
+Inputs are the points of a problem centred on the mean of all its points
+(both measures, unweighted) and divided by the kernel length sqrt(eps C_s)
+with C_s = max_ij |x_i - y_j|^2 for the max-normalised cost (eq. (rot):
+K = exp(-|x - y|^2 / (eps C_s)) becomes exp(-|x' - y'|^2)), C_s = 1 for the
+plain cost.  For the side that predicts the scalings of points z_i (weights
+w_i, count n) given the opposite measure (points o_j, weights q_j, count m),
+all in these units:
 
     phi_j  = ReLU(P [o_j, m q_j] + p)            (4 -> H)
     e      = mean_j phi_j                        (H)
@@ -81,6 +86,20 @@ def init_params(H: int = 256, seed: int = 0) -> Params:
 
 def _relu(z):
     return np.maximum(z, 0.0)
+
+
+def normalise(x, y, eps: float, cost: str = "maxnorm"):
+    """x, y in kernel units: centred on the mean of all points, divided by
+    sqrt(eps C_s)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    center = np.concatenate([x, y]).mean(axis=0)
+    cs = 1.0
+    if cost == "maxnorm":
+        d2 = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+        cs = float(d2.max()) if d2.max() > 0 else 1.0
+    scale = 1.0 / np.sqrt(eps * cs)
+    return (x - center) * scale, (y - center) * scale
 
 
 def side_forward(par: Params, z, o, q):
@@ -158,13 +177,16 @@ def problem_sides(x, a, y, b, log_u, log_v):
     return out
 
 
-def batch_loss_and_grad(par: Params, problems):
+def batch_loss_and_grad(par: Params, problems, eps: float | None = None, cost="maxnorm"):
     """problems: list of (x, a, y, b, log_u*, log_v*).  Mean loss over
-    problems and sides, and its gradient."""
+    problems and sides, and its gradient.  With eps the points are first put
+    in kernel units (normalise); without, they are used as given."""
     total = 0.0
     grad = Params.zeros(par.H)
     nside = 2 * len(problems)
     for x, a, y, b, lu, lv in problems:
+        if eps is not None:
+            x, y = normalise(x, y, eps, cost)
         for z, w, o, q, t, mask in problem_sides(x, a, y, b, lu, lv):
             psi, cache = side_forward(par, z, o, q)
             loss, dpsi = side_loss(psi, t, mask)
@@ -173,10 +195,13 @@ def batch_loss_and_grad(par: Params, problems):
     return total, grad
 
 
-def predict(par: Params, x, a, y, b):
-    """Initial log u^0, log v^0 (log w + psi on each side)."""
+def predict(par: Params, x, a, y, b, eps: float | None = None, cost="maxnorm"):
+    """Initial log u^0, log v^0 (log w + psi on each side); with eps the
+    points are first put in kernel units."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
+    if eps is not None:
+        x, y = normalise(x, y, eps, cost)
     psi_u, _ = side_forward(par, x, y, b)
     psi_v, _ = side_forward(par, y, x, a)
     with np.errstate(divide="ignore"):

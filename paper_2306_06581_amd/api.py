@@ -306,3 +306,93 @@ def ss_autotune_batched(batch: Batch, *, eps, seed=0, precision="f32", cost="max
     cands = [(l, b) for l in (4, 8, 16, 32) for b in (256, 512, 1024)]
     return (best.lanes_per_line, best.block_threads), {c: float(ms[i]) for i, c in
                                                           enumerate(cands[: nc.value])}
+
+
+# ---------------------------------------------------------------- warm start
+_MLP_SHAPES = (("P", (256, 4)), ("p", (256,)), ("W1", (256, 3)), ("U", (256, 256)),
+               ("c1", (256,)), ("W2", (256, 256)), ("c2", (256,)), ("w3", (256,)), ("c3", (1,)))
+
+
+class WarmStartNet:
+    """Device weights and Adam state of the DeepSets warm-start network."""
+
+    def __init__(self, flat=None, seed: int = 0):
+        if flat is None:
+            flat = self.initial_weights(seed)
+        flat = np.asarray(flat, dtype=np.float32)
+        if flat.size != N.MLP_PARAMS:
+            raise ValueError(f"expected {N.MLP_PARAMS} weights")
+        self.params = torch.tensor(flat, device="cuda")
+        self.bf16 = torch.empty(N.MLP_PARAMS, dtype=torch.bfloat16, device="cuda")
+        self.w2t = torch.empty(256 * 256, dtype=torch.bfloat16, device="cuda")
+        self.adam_m = torch.zeros(N.MLP_PARAMS, dtype=torch.float32, device="cuda")
+        self.adam_v = torch.zeros(N.MLP_PARAMS, dtype=torch.float32, device="cuda")
+        self.c = N.SsMlp(_ptr(self.params), _ptr(self.bf16), _ptr(self.w2t), _ptr(self.adam_m),
+                         _ptr(self.adam_v), 0, 0)
+        rc = N.lib.ss_mlp_sync(ctypes.byref(self.c), _stream())
+        if rc < 0:
+            raise N.SparSinkError(rc, "ss_mlp_sync")
+
+    @staticmethod
+    def initial_weights(seed: int = 0) -> np.ndarray:
+        """He-scaled Gaussian matrices for the ReLU layers, small first bias."""
+        rng = np.random.default_rng(seed)
+        scale = {"P": np.sqrt(2 / 4), "W1": np.sqrt(2 / 3), "U": np.sqrt(1 / 256),
+                 "W2": np.sqrt(2 / 256), "w3": np.sqrt(1 / 256)}
+        parts = []
+        for name, shape in _MLP_SHAPES:
+            if name in scale:
+                parts.append(rng.standard_normal(shape).ravel() * scale[name])
+            else:
+                parts.append(np.full(int(np.prod(shape)), 0.01 if name == "c1" else 0.0))
+        return np.concatenate(parts).astype(np.float32)
+
+    @property
+    def step(self) -> int:
+        return int(self.c.step)
+
+    def weights(self) -> np.ndarray:
+        return self.params.cpu().numpy()
+
+    def bf16_weights(self) -> np.ndarray:
+        return self.bf16.float().cpu().numpy()
+
+    def predict(self, batch: "Batch", eps: float, cost="maxnorm", stream=None):
+        """(log u^0, log v^0) as FP64 device tensors of sum(n), sum(m) entries
+        for a solve with this eps and cost."""
+        out_u = torch.empty(int(batch.row_off[-1]), dtype=torch.float64, device="cuda")
+        out_v = torch.empty(int(batch.col_off[-1]), dtype=torch.float64, device="cuda")
+        nb = ctypes.c_size_t(0)
+        rc = N.lib.ss_warmstart_workspace_size(ctypes.byref(batch.c), ctypes.byref(nb))
+        if rc < 0:
+            raise N.SparSinkError(rc, "ss_warmstart_workspace_size")
+        ws = workspace(nb.value)
+        rc = N.lib.ss_warmstart_predict(ctypes.byref(self.c), ctypes.byref(batch.c), float(eps),
+                                        N.COST[cost], _ptr(out_u), _ptr(out_v),
+                                        ctypes.c_void_p(ws.data_ptr()),
+                                        ctypes.c_size_t(ws.numel()), _stream(stream))
+        if rc < 0:
+            raise N.SparSinkError(rc, "ss_warmstart_predict")
+        return out_u, out_v
+
+    def train_step(self, batch: "Batch", tgt_log_u, tgt_log_v, lr: float, eps: float,
+                   cost="maxnorm", want_grad=False, stream=None):
+        """One Adam step; returns the loss before it (and the gradient)."""
+        tu, tv = _dev(tgt_log_u), _dev(tgt_log_v)
+        if tu.numel() != int(batch.row_off[-1]) or tv.numel() != int(batch.col_off[-1]):
+            raise ValueError("targets need sum(n) and sum(m) entries")
+        grad = torch.empty(N.MLP_PARAMS, dtype=torch.float32, device="cuda") if want_grad else None
+        nb = ctypes.c_size_t(0)
+        rc = N.lib.ss_warmstart_workspace_size(ctypes.byref(batch.c), ctypes.byref(nb))
+        if rc < 0:
+            raise N.SparSinkError(rc, "ss_warmstart_workspace_size")
+        ws = workspace(nb.value)
+        loss = ctypes.c_float(0.0)
+        rc = N.lib.ss_warmstart_train_step(ctypes.byref(self.c), ctypes.byref(batch.c), float(eps),
+                                           N.COST[cost], _ptr(tu), _ptr(tv), float(lr),
+                                           ctypes.c_void_p(ws.data_ptr()),
+                                           ctypes.c_size_t(ws.numel()), _stream(stream),
+                                           ctypes.byref(loss), _ptr(grad))
+        if rc < 0:
+            raise N.SparSinkError(rc, "ss_warmstart_train_step")
+        return (float(loss.value), grad) if want_grad else float(loss.value)

@@ -1014,6 +1014,211 @@ int batch_start(BCtx& c, const ss_batch* B, const ss_options* O, void* ws, size_
     return batch_setup(c);
 }
 
+
+// ------------------------------------------------------------------ warm start
+struct WLayout {
+    size_t sides, xform, emb, gvec, psi, dpsi, h1g, dz2g, dgp, blkp, w2p, sidep, dgs, grad, loss;
+    size_t total;
+    int nsides, nblk, nchunk;
+    int64_t ntiles, npts;
+};
+
+int check_ws_batch(const ss_batch* B) {
+    if (!B) return fail(SS_E_INVALID_ARG, "batch must not be NULL");
+    if (B->count < 1) return fail(SS_E_INVALID_ARG, "count must be >= 1");
+    if (B->d != 3) return fail(SS_E_INVALID_ARG, "the warm-start network takes d = 3");
+    if (!B->n || !B->m) return fail(SS_E_INVALID_ARG, "n, m must not be NULL");
+    if (!B->x || !B->y || !B->a || !B->b)
+        return fail(SS_E_INVALID_ARG, "x, y, a, b must not be NULL");
+    for (int k = 0; k < B->count; ++k)
+        if (B->n[k] < 1 || B->n[k] > SS_BATCH_MAX_SIDE || B->m[k] < 1 || B->m[k] > SS_BATCH_MAX_SIDE)
+            return fail(SS_E_INVALID_ARG, "problem %d: n and m must be in [1, %d]", k, SS_BATCH_MAX_SIDE);
+    return SS_OK;
+}
+
+constexpr int kWsTile = 16, kWsChunk = 2048, kWsH = 256;
+
+void ws_sides(const ss_batch* B, std::vector<WSide>* out) {
+    out->clear();
+    int64_t ro = 0, co = 0, tile = 0, pt = 0;
+    for (int k = 0; k < B->count; ++k) {
+        for (int side = 0; side < 2; ++side) {
+            WSide S;
+            S.which = side;
+            S.prob = k;
+            S.npts = side == 0 ? B->n[k] : B->m[k];
+            S.pts_off = side == 0 ? ro : co;
+            S.nopp = side == 0 ? B->m[k] : B->n[k];
+            S.opp_off = side == 0 ? co : ro;
+            S.tile0 = tile;
+            S.ntiles = (S.npts + kWsTile - 1) / kWsTile;
+            S.pt0 = pt;
+            tile += S.ntiles;
+            pt += S.npts;
+            out->push_back(S);
+        }
+        ro += B->n[k];
+        co += B->m[k];
+    }
+}
+
+WLayout wplan(const ss_batch* B) {
+    WLayout L;
+    std::vector<WSide> sides;
+    ws_sides(B, &sides);
+    L.nsides = (int)sides.size();
+    L.ntiles = sides.back().tile0 + sides.back().ntiles;
+    L.npts = sides.back().pt0 + sides.back().npts;
+    L.nblk = kMaxLoopBlocks;  // bound; the launch uses the compute-unit count
+    L.nchunk = (int)((L.npts + kWsChunk - 1) / kWsChunk);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.sides = take(sides.size() * sizeof(WSide));
+    L.xform = take((size_t)B->count * 4 * 4);
+    L.emb = take((size_t)L.nsides * kWsH * 4);
+    L.gvec = take((size_t)L.nsides * kWsH * 4);
+    L.psi = take((size_t)L.npts * 4);
+    L.dpsi = take((size_t)L.npts * 4);
+    L.h1g = take((size_t)L.npts * kWsH * 2);
+    L.dz2g = take((size_t)L.npts * kWsH * 2);
+    L.dgp = take((size_t)L.ntiles * kWsH * 4);
+    L.blkp = take((size_t)L.nblk * (768 + 256 + 256 + 1) * 4);
+    L.w2p = take((size_t)L.nchunk * kWsH * kWsH * 4);
+    L.sidep = take((size_t)L.nsides * 1280 * 4);
+    L.dgs = take((size_t)L.nsides * kWsH * 4);
+    L.grad = take((size_t)SS_MLP_PARAMS * 4);
+    L.loss = take((size_t)L.nsides * 8);
+    L.total = off;
+    return L;
+}
+
+int ws_args(const ss_mlp* M, const ss_batch* B, double eps, int cost, void* ws, size_t ws_bytes,
+            hipStream_t st, WLayout* L, std::vector<WSide>* sides, MlpArgs* a) {
+    int rc = check_ws_batch(B);
+    if (rc != SS_OK) return rc;
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(SS_E_INVALID_ARG, "eps must be > 0");
+    if (cost != SS_COST_SQEUCLID_MAXNORM && cost != SS_COST_SQEUCLID)
+        return fail(SS_E_INVALID_ARG, "unknown cost %d", cost);
+    if (!M || !M->params || !M->bf16 || !M->w2t) return fail(SS_E_INVALID_ARG, "mlp buffers must not be NULL");
+    *L = wplan(B);
+    if (!ws) return fail(SS_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(SS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L->total)
+        return fail(SS_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L->total);
+    HIP_TRY(mlp_init());
+    ws_sides(B, sides);
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, L->sides), sides->data(), sides->size() * sizeof(WSide),
+                           hipMemcpyHostToDevice, st));
+    const int grid = mlp_head_grid();
+    if (grid <= 0) return fail(SS_E_HIP, "no device");
+    a->sides = at<WSide>(ws, L->sides);
+    a->nsides = L->nsides;
+    a->ntiles = L->ntiles;
+    a->npts = L->npts;
+    a->nblk = grid < L->nblk ? grid : L->nblk;
+    a->nchunk = L->nchunk;
+    a->x = B->x;
+    a->y = B->y;
+    a->a = B->a;
+    a->b = B->b;
+    a->tgt_u = a->tgt_v = nullptr;
+    a->out_u = a->out_v = nullptr;
+    a->xform = at<float>(ws, L->xform);
+    a->eps = eps;
+    a->cost = cost;
+    a->wbf = M->bf16;
+    a->w2t = M->w2t;
+    a->emb = at<float>(ws, L->emb);
+    a->gvec = at<float>(ws, L->gvec);
+    a->psi = at<float>(ws, L->psi);
+    a->dpsi = at<float>(ws, L->dpsi);
+    a->h1g = at<void>(ws, L->h1g);
+    a->dz2g = at<void>(ws, L->dz2g);
+    a->dgp = at<float>(ws, L->dgp);
+    a->blkp = at<float>(ws, L->blkp);
+    a->w2p = at<float>(ws, L->w2p);
+    a->sidep = at<float>(ws, L->sidep);
+    a->dgs = at<float>(ws, L->dgs);
+    a->grad = at<float>(ws, L->grad);
+    a->loss = at<double>(ws, L->loss);
+    return SS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_mlp_sync(ss_mlp* M, void* stream) {
+    if (!M || !M->params || !M->bf16 || !M->w2t) return fail(SS_E_INVALID_ARG, "mlp buffers must not be NULL");
+    HIP_TRY(launch_mlp_sync(M->params, (__bf16*)M->bf16, (__bf16*)M->w2t, (hipStream_t)stream));
+    return SS_OK;
+}
+
+int ss_warmstart_workspace_size(const ss_batch* batch, size_t* bytes) {
+    int rc = check_ws_batch(batch);
+    if (rc != SS_OK) return rc;
+    if (!bytes) return fail(SS_E_INVALID_ARG, "bytes must not be NULL");
+    *bytes = wplan(batch).total;
+    return SS_OK;
+}
+
+int ss_warmstart_predict(const ss_mlp* M, const ss_batch* B, double eps, int32_t cost,
+                         double* log_u0, double* log_v0, void* ws, size_t ws_bytes, void* stream) {
+    const hipStream_t st = (hipStream_t)stream;
+    WLayout L;
+    std::vector<WSide> sides;
+    MlpArgs a;
+    int rc = ws_args(M, B, eps, cost, ws, ws_bytes, st, &L, &sides, &a);
+    if (rc != SS_OK) return rc;
+    a.out_u = log_u0;
+    a.out_v = log_v0;
+    HIP_TRY(launch_mlp_predict(a, st));
+    HIP_TRY(hipStreamSynchronize(st));  // the side table's host copy goes out of scope
+    return SS_OK;
+}
+
+int ss_warmstart_train_step(ss_mlp* M, const ss_batch* B, double eps, int32_t cost,
+                            const double* tgt_log_u, const double* tgt_log_v, float lr, void* ws,
+                            size_t ws_bytes, void* stream, float* loss, float* grad_out) {
+    if (!tgt_log_u || !tgt_log_v) return fail(SS_E_INVALID_ARG, "targets must not be NULL");
+    if (!(lr >= 0.0f) || !isfinite(lr)) return fail(SS_E_INVALID_ARG, "lr must be >= 0");
+    if (lr > 0.0f && (!M || !M->adam_m || !M->adam_v))
+        return fail(SS_E_INVALID_ARG, "Adam moments must not be NULL");
+    const hipStream_t st = (hipStream_t)stream;
+    WLayout L;
+    std::vector<WSide> sides;
+    MlpArgs a;
+    int rc = ws_args(M, B, eps, cost, ws, ws_bytes, st, &L, &sides, &a);
+    if (rc != SS_OK) return rc;
+    a.tgt_u = tgt_log_u;
+    a.tgt_v = tgt_log_v;
+    HIP_TRY(launch_mlp_grad(a, st));
+    if (grad_out)
+        HIP_TRY(hipMemcpyAsync(grad_out, a.grad, (size_t)SS_MLP_PARAMS * 4, hipMemcpyDeviceToDevice, st));
+    if (lr > 0.0f) {
+        M->step += 1;
+        HIP_TRY(launch_mlp_adam(M->params, M->adam_m, M->adam_v, a.grad, (__bf16*)M->bf16,
+                                (__bf16*)M->w2t, lr, M->step, st));
+    }
+    std::vector<double> ls(L.nsides);
+    HIP_TRY(hipMemcpyAsync(ls.data(), a.loss, ls.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (loss) {
+        double tot = 0.0;
+        for (double v : ls) tot += v;
+        *loss = (float)(tot / (double)L.nsides);
+    }
+    return SS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
 }  // namespace
 
 extern "C" {

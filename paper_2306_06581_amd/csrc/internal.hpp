@@ -351,4 +351,51 @@ hipError_t launch_batch_iterate(int precision, int lanes, int block, int grid, c
                                 hipStream_t st);
 hipError_t launch_batch_objective(int precision, int count, const BObjArgs& a, hipStream_t st);
 
+// ---- mlp.hip (learned warm start)
+// One side of a problem: the points whose scalings are predicted and the
+// opposite measure.
+struct WSide {
+    int64_t npts, pts_off;   // points, first row in their concatenated array
+    int64_t nopp, opp_off;   // opposite measure
+    int64_t tile0, ntiles;   // head tiles of this side
+    int64_t pt0;             // first position in the list of all sides' points
+    int32_t which;           // 0: points from x / a (u side), 1: from y / b (v side)
+    int32_t prob;            // problem index
+};
+
+struct MlpArgs {
+    const WSide* sides;
+    int nsides;
+    int64_t ntiles, npts;
+    int nblk;                // head blocks (<= resident)
+    int nchunk;              // dW2 blocks
+    const double *x, *y, *a, *b;
+    const double *tgt_u, *tgt_v;
+    double *out_u, *out_v;
+    float* xform;            // [problem][4]: centre (3), 1 / sqrt(eps C_s)
+    double eps;
+    int cost;                // SS_COST_*
+    const void* wbf;         // BF16 weights
+    const void* w2t;         // BF16 W2 transposed
+    float *emb, *gvec;       // [side][256]
+    float *psi, *dpsi;       // [point]
+    void *h1g, *dz2g;        // BF16 [point][256]
+    float *dgp;              // [tile][256]
+    float *blkp;             // [block][1281]
+    float *w2p;              // [chunk][65536]
+    float *sidep;            // [side][1280]
+    float *dgs;              // [side][256]
+    float *grad;             // [SS_MLP_PARAMS]
+    double* loss;            // [side]
+};
+
+hipError_t mlp_init();
+int mlp_head_grid();
+int mlp_chunks(int64_t npts);
+hipError_t launch_mlp_sync(float* w, __bf16* wbf, __bf16* w2t, hipStream_t st);
+hipError_t launch_mlp_predict(const MlpArgs& a, hipStream_t st);
+hipError_t launch_mlp_grad(const MlpArgs& a, hipStream_t st);
+hipError_t launch_mlp_adam(float* w, float* m1, float* m2, const float* grad, __bf16* wbf,
+                           __bf16* w2t, float lr, int step, hipStream_t st);
+
 }  // namespace ss

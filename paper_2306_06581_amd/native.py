@@ -75,6 +75,12 @@ class SsSchedule(ctypes.Structure):
 
 
 BATCH_MAX_SIDE = 4096
+MLP_PARAMS = 133889
+
+
+class SsMlp(ctypes.Structure):
+    _fields_ = [("params", c_void_p), ("bf16", c_void_p), ("w2t", c_void_p), ("adam_m", c_void_p),
+                ("adam_v", c_void_p), ("step", c_int32), ("reserved", c_int32)]
 
 
 # Every symbol the header declares, with its signature.
@@ -96,6 +102,13 @@ SIGNATURES = {
     "ss_autotune_batched": (c_int, [POINTER(SsBatch), POINTER(SsOptions), c_void_p, c_size_t,
                                     c_void_p, POINTER(SsSchedule), POINTER(c_float),
                                     POINTER(c_int32)]),
+    "ss_mlp_sync": (c_int, [POINTER(SsMlp), c_void_p]),
+    "ss_warmstart_workspace_size": (c_int, [POINTER(SsBatch), POINTER(c_size_t)]),
+    "ss_warmstart_predict": (c_int, [POINTER(SsMlp), POINTER(SsBatch), c_double, c_int32,
+                                     c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ss_warmstart_train_step": (c_int, [POINTER(SsMlp), POINTER(SsBatch), c_double, c_int32,
+                                        c_void_p, c_void_p, c_float, c_void_p, c_size_t, c_void_p,
+                                        POINTER(c_float), c_void_p]),
     "ss_status_string": (c_char_p, [c_int]),
     "ss_last_error": (c_char_p, []),
     "ss_version": (c_int, []),

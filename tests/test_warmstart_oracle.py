@@ -116,3 +116,20 @@ def test_adam_first_step_moves_by_lr():
     np.testing.assert_allclose(par.W2, before.W2 - 1e-3, rtol=0, atol=1e-10)
     np.testing.assert_allclose(par.c3, before.c3 + 1e-3, rtol=0, atol=1e-10)
     np.testing.assert_allclose(par.U, before.U)  # zero gradient, zero step
+
+
+def test_normalisation_makes_the_kernel_unit_free():
+    # kernel units: exp(-|x' - y'|^2) is the Gibbs kernel of eq. (rot) with the
+    # max-normalised cost, and a common shift of both clouds changes nothing
+    rng = np.random.default_rng(7)
+    x, y = rng.standard_normal((9, 3)), rng.standard_normal((6, 3)) + 2.0
+    eps = 0.05
+    xs, ys = WO.normalise(x, y, eps)
+    d2 = ((x[:, None] - y[None]) ** 2).sum(-1)
+    K = np.exp(-d2 / d2.max() / eps)
+    Ks = np.exp(-((xs[:, None] - ys[None]) ** 2).sum(-1))
+    np.testing.assert_allclose(Ks, K, rtol=1e-12)
+    xs2, ys2 = WO.normalise(x + 5.0, y + 5.0, eps)
+    np.testing.assert_allclose(xs2, xs, atol=1e-12)
+    np.testing.assert_allclose(ys2, ys, atol=1e-12)
+    np.testing.assert_allclose(xs2.mean(0) * 9 + ys2.mean(0) * 6, 0.0, atol=1e-10)
