@@ -236,6 +236,27 @@ class Batch:
                            self.s.ctypes.data, self.pidx.ctypes.data, _ptr(self.x), _ptr(self.y),
                            _ptr(self.a), _ptr(self.b))
 
+    def subset(self, k0: int, k1: int) -> "Batch":
+        """Problems k0 .. k1 - 1 as a batch whose device arrays are views of
+        this one's (no copy)."""
+        sub = Batch.__new__(Batch)
+        sub.count = k1 - k0
+        sub.d = self.d
+        sub.n = np.ascontiguousarray(self.n[k0:k1])
+        sub.m = np.ascontiguousarray(self.m[k0:k1])
+        sub.s = np.ascontiguousarray(self.s[k0:k1])
+        sub.pidx = np.ascontiguousarray(self.pidx[k0:k1])
+        r0, r1 = int(self.row_off[k0]), int(self.row_off[k1])
+        c0, c1 = int(self.col_off[k0]), int(self.col_off[k1])
+        sub.x, sub.a = self.x[r0:r1], self.a[r0:r1]
+        sub.y, sub.b = self.y[c0:c1], self.b[c0:c1]
+        sub.row_off = self.row_off[k0:k1 + 1] - r0
+        sub.col_off = self.col_off[k0:k1 + 1] - c0
+        sub.c = N.SsBatch(sub.count, sub.d, sub.n.ctypes.data, sub.m.ctypes.data,
+                          sub.s.ctypes.data, sub.pidx.ctypes.data, _ptr(sub.x), _ptr(sub.y),
+                          _ptr(sub.a), _ptr(sub.b))
+        return sub
+
     @classmethod
     def from_problems(cls, probs):
         """From workload Problems (x, y, a, b, s, problem_index attributes)."""

@@ -1263,7 +1263,9 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
     if (schedule) {
         sc = *schedule;
     } else {
-        const auto key = std::make_tuple(O->precision, B->count, (int64_t)(c.L.rows / 256));
+        // size class: half octaves of the total number of rows
+        const auto key = std::make_tuple(O->precision, B->count,
+                                         (int64_t)floor(2.0 * log2((double)c.L.rows)));
         bool have = false;
         {
             std::lock_guard<std::mutex> g(g_tune_mu);

@@ -37,10 +37,10 @@ def solution_minibatches(problems, *, eps, seed, minibatch=64, precision="f32", 
         raise RuntimeError(f"spar_sink_batched failed: {rc}")
     out = []
     for i in range(0, len(problems), minibatch):
-        sub = problems[i:i + minibatch]
-        lu = torch.cat([torch.log(r.u) for r in res[i:i + minibatch]])
-        lv = torch.cat([torch.log(r.v) for r in res[i:i + minibatch]])
-        out.append(Minibatch(A.Batch.from_problems(sub), lu, lv))
+        j = min(i + minibatch, len(problems))
+        lu = torch.cat([torch.log(r.u) for r in res[i:j]])
+        lv = torch.cat([torch.log(r.v) for r in res[i:j]])
+        out.append(Minibatch(B.subset(i, j), lu, lv))
     return out
 
 
