@@ -47,11 +47,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Byte offsets of every region of the caller's workspace.
 struct Layout {
     size_t mask, maskT, row_cnt, col_cnt, row_ptr, col_ptr, scan, col_idx, row_idx, val, val_t;
-    size_t row_fac, col_fac, row_bnd, col_bnd, a_eff, b_eff, tmp, tree, u[2], v[2], ug[2], vg[2];
+    size_t row_fac, col_fac, row_bnd, col_bnd, a_eff, b_eff, la_eff, lb_eff, tmp, tree, u[2], v[2];
+    size_t ug[2], vg[2];
     size_t partials, loop_part[2], state, stats, hstage, dense_part, rowsum, colsum;
     // lane plans of the iteration kernel: [0] rows (u-update), [1] columns
     struct PlanOff {
-        size_t split, lanes, weight, lane_ptr, wptr, rstart, info, scan, lst, lseg, pval, poff;
+        size_t split, quads, weight, wptr, rstart, info, scan, qs, qe, steplanes, stepoff, lmeta;
+        size_t pval, poff;
     } po[2];
     IterPlan plan[2];
     int64_t loop_part_len;
@@ -126,6 +128,9 @@ Layout plan(const ss_problem* P, const ss_options* O) {
     L.col_bnd = take((size_t)m * 8);
     L.a_eff = take((size_t)n * 8);
     L.b_eff = take((size_t)m * 8);
+    // log domain: logs of the effective marginals, formed once per solve
+    L.la_eff = take(O->precision == SS_F32_LOG ? (size_t)n * 8 : 0);
+    L.lb_eff = take(O->precision == SS_F32_LOG ? (size_t)m * 8 : 0);
     L.tmp = take((size_t)2 * nm * 8);
     const int64_t cost_blocks = ((n + 255) / 256) * ((m + 2047) / 2048);
     const int64_t tree_len = (cost_blocks > nm ? cost_blocks : nm);
@@ -153,15 +158,17 @@ Layout plan(const ss_problem* P, const ss_options* O) {
         const int64_t kmax = p.kmax;
         const int64_t scan_len = nl > kmax ? nl : kmax;
         L.po[d].split = take((size_t)nl * (size_t)(p.ns + 1) * 4);
-        L.po[d].lanes = take((size_t)nl * 4);
+        L.po[d].quads = take((size_t)nl * 4);
         L.po[d].weight = take((size_t)nl * 4);
-        L.po[d].lane_ptr = take((size_t)(nl + 1) * 8);
         L.po[d].wptr = take((size_t)(nl + 1) * 8);
         L.po[d].rstart = take((size_t)(kmax + 1) * 4);
         L.po[d].info = take(sizeof(PlanInfo));
         L.po[d].scan = take((size_t)((scan_len + 1023) / 1024 + 1) * 8);
-        L.po[d].lst = take((size_t)(nl * p.ns + kmax + 1) * 4);
-        L.po[d].lseg = take((size_t)p.lanes_max * 4);
+        L.po[d].qs = take((size_t)nl * (size_t)p.ns * 4);
+        L.po[d].qe = take((size_t)nl * (size_t)p.ns * 4);
+        L.po[d].steplanes = take((size_t)kmax * 4);
+        L.po[d].stepoff = take((size_t)(kmax + 1) * 8);
+        L.po[d].lmeta = take((size_t)p.lanes_max * 4);
     }
 
     L.state = take(sizeof(IterState));
@@ -509,6 +516,10 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     float* vg[2] = {lg ? at<float>(ws, c.L.vg[0]) : nullptr, lg ? at<float>(ws, c.L.vg[1]) : nullptr};
     HIP_TRY(launch_init_scaling(prec, u[0], ug[0], O->init_log_u, n, c.st));
     HIP_TRY(launch_init_scaling(prec, v[0], vg[0], O->init_log_v, m, c.st));
+    if (lg) {
+        HIP_TRY(launch_log_vec(at<double>(ws, c.L.a_eff), at<double>(ws, c.L.la_eff), n, c.st));
+        HIP_TRY(launch_log_vec(at<double>(ws, c.L.b_eff), at<double>(ws, c.L.lb_eff), m, c.st));
+    }
     IterState* d_state = at<IterState>(ws, c.L.state);
     const double theta = uot ? O->lambda / (O->lambda + O->eps) : 1.0;
     HIP_TRY(iterate_init());
@@ -518,15 +529,17 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         const Layout::PlanOff& po = c.L.po[d];
         p.grid = iterate_grid(prec, p.block);
         p.split = at<int32_t>(ws, po.split);
-        p.lanes = at<int32_t>(ws, po.lanes);
+        p.quads = at<int32_t>(ws, po.quads);
         p.weight = at<int32_t>(ws, po.weight);
-        p.lane_ptr = at<int64_t>(ws, po.lane_ptr);
         p.wptr = at<int64_t>(ws, po.wptr);
         p.rstart = at<int32_t>(ws, po.rstart);
         p.info = at<PlanInfo>(ws, po.info);
         p.scan = at<int64_t>(ws, po.scan);
-        p.lst = at<int32_t>(ws, po.lst);
-        p.lseg = at<int32_t>(ws, po.lseg);
+        p.qs = at<int32_t>(ws, po.qs);
+        p.qe = at<int32_t>(ws, po.qe);
+        p.steplanes = at<int32_t>(ws, po.steplanes);
+        p.stepoff = at<int64_t>(ws, po.stepoff);
+        p.lmeta = at<int32_t>(ws, po.lmeta);
         p.pval = at<void>(ws, po.pval);
         p.poff = at<uint16_t>(ws, po.poff);
         pl[d] = p;
@@ -541,16 +554,17 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.ptr = at<int64_t>(ws, c.L.row_ptr);
         a.nlines = n;
         a.nx = m;
-        a.split = pl[0].split;
         a.nslices = pl[0].ns;
         a.rstart = pl[0].rstart;
-        a.lane_ptr = pl[0].lane_ptr;
-        a.lst = pl[0].lst;
-        a.lseg = pl[0].lseg;
+        a.stepoff = pl[0].stepoff;
+        a.qs = pl[0].qs;
+        a.qe = pl[0].qe;
+        a.lmeta = pl[0].lmeta;
         a.info = pl[0].info;
         a.pval = pl[0].pval;
         a.poff = pl[0].poff;
         a.marg = at<double>(ws, c.L.a_eff);
+        a.lmarg = lg ? at<double>(ws, c.L.la_eff) : nullptr;
         a.xin = lg ? (const void*)vg[k] : v[k];
         a.yout = u[(k + 1) & 1];
         a.yg = ug[(k + 1) & 1];
@@ -569,16 +583,17 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.ptr = at<int64_t>(ws, c.L.col_ptr);
         a.nlines = m;
         a.nx = n;
-        a.split = pl[1].split;
         a.nslices = pl[1].ns;
         a.rstart = pl[1].rstart;
-        a.lane_ptr = pl[1].lane_ptr;
-        a.lst = pl[1].lst;
-        a.lseg = pl[1].lseg;
+        a.stepoff = pl[1].stepoff;
+        a.qs = pl[1].qs;
+        a.qe = pl[1].qe;
+        a.lmeta = pl[1].lmeta;
         a.info = pl[1].info;
         a.pval = pl[1].pval;
         a.poff = pl[1].poff;
         a.marg = at<double>(ws, c.L.b_eff);
+        a.lmarg = lg ? at<double>(ws, c.L.lb_eff) : nullptr;
         a.xin = lg ? (const void*)ug[(k + 1) & 1] : u[(k + 1) & 1];
         a.yout = v[(k + 1) & 1];
         a.yg = vg[(k + 1) & 1];

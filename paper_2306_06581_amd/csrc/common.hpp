@@ -7,6 +7,8 @@
 namespace ss {
 
 constexpr int kWave = 64;
+constexpr double kLog2e = 1.4426950408889634;  // log2(e)
+constexpr double kLn2 = 0.6931471805599453;     // ln(2)
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
@@ -129,6 +131,39 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     double r = 0.0;
     for (int w = 0; w < nw; ++w) r += sh[w];
     return r;
+}
+
+// Block barrier that orders LDS only: waits for this wave's LDS (and scalar
+// memory) operations, not for its global stores (s_waitcnt lgkmcnt(0) with
+// vmcnt and expcnt at their maxima, then s_barrier; the empty asm statements
+// keep the compiler from moving memory operations across it).
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Two sums over a block in one pass, each in the tree of block_sum; results
+// valid in every thread.  sh: at least 32 doubles of LDS.  The barriers order
+// LDS only, so global stores still in flight do not delay the sums.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+    a = group_sum<kWave>(a);
+    b = group_sum<kWave>(b);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    lds_barrier();
+    if (lane == 0) {
+        sh[wv] = a;
+        sh[16 + wv] = b;
+    }
+    lds_barrier();
+    a = 0.0;
+    b = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        a += sh[w];
+        b += sh[16 + w];
+    }
 }
 
 __device__ __forceinline__ int block_max_int(int v, int* sh) {

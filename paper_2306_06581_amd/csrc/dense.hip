@@ -176,8 +176,11 @@ __global__ __launch_bounds__(256) void k_dense_finish(DensePartial P) {
         }
         const double yp = PREC == P_F32 ? (double)((const float*)A.yprev)[line]
                                         : ((const double*)A.yprev)[line];
-        res = line_update<PREC, UOT>(A.role, marginal, t, A.no > 0, A.marg[line], A.theta, yp,
-                                     A.yout, nullptr, line, w, A.st);
+        const double mg = A.marg[line];
+        const LineNew o = line_new<PREC, UOT>(A.role, marginal, t, A.no > 0, mg,
+                                              PREC == P_LOG ? log(mg) : 0.0, A.theta, yp, w);
+        line_store<PREC>(A.yout, nullptr, line, o.y, A.st);
+        res = o.res;
     }
     const double bsum = block_sum256(res, sh);
     if (threadIdx.x == 0) A.partials[blockIdx.x] = bsum;

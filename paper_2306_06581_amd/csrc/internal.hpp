@@ -115,15 +115,16 @@ hipError_t launch_reduce_stats(const ReduceSpec& r, double* stats, hipStream_t s
 // ---- iterate.hip
 // Device-side parameters of a lane plan (see build_plan).
 struct PlanInfo {
-    int64_t T;     // lane weight per step
+    int64_t T;     // quad weight per step
     int64_t K;     // number of steps
-    int32_t maxw;  // largest line weight
+    int32_t maxw;  // largest line weight (quads)
     int32_t pad;
 };
 
 // Lane plan of one sparse matrix for the iteration kernel: the lines are cut
-// into steps, each step's (slice, line) segments get lanes, and the entries
-// are repacked lane by lane.  Built once per solve, on the device.
+// into steps, each step's (slice, line) segments are laid out in quads of 4
+// entries and packed into lanes of J quads (at most two segments a lane), and
+// the entries are repacked lane by lane.  Built once per solve, on the device.
 struct IterPlan {
     int block = 0;          // threads per block
     int ns = 0;             // slices of the gathered vector
@@ -131,34 +132,37 @@ struct IterPlan {
     int grid = 0;           // blocks per launch (resident blocks, <= kMaxLoopBlocks)
     int64_t kmax = 0;       // bound on the number of steps
     int64_t lanes_max = 0;  // bound on the number of lanes
-    int32_t* split = nullptr;     // [nlines][ns + 1] entry offsets at the slice boundaries
-    int32_t* lanes = nullptr;     // [nlines] lanes of each line
-    int32_t* weight = nullptr;    // [nlines] step weight of each line
-    int64_t* lane_ptr = nullptr;  // [nlines + 1] exclusive scan of lanes
-    int64_t* wptr = nullptr;      // [nlines + 1] exclusive scan of weights
-    int32_t* rstart = nullptr;    // [kmax + 1] first line of each step
+    int32_t* split = nullptr;      // [nlines][ns + 1] entry offsets at the slice boundaries
+    int32_t* quads = nullptr;      // [nlines] quads of each line (sum over its segments)
+    int32_t* weight = nullptr;     // [nlines] step weight of each line
+    int64_t* wptr = nullptr;       // [nlines + 1] exclusive scan of weights
+    int32_t* rstart = nullptr;     // [kmax + 1] first line of each step
     PlanInfo* info = nullptr;
-    int64_t* scan = nullptr;      // scan scratch
-    int32_t* lst = nullptr;       // per step k: lane starts of its segments at r0 * ns + k
-    int32_t* lseg = nullptr;      // [lanes_max] segment of every lane inside its step
-    void* pval = nullptr;         // [lanes_max * E] packed values
-    uint16_t* poff = nullptr;     // [lanes_max * E] packed slice offsets
+    int64_t* scan = nullptr;       // scan scratch
+    int32_t* qs = nullptr;         // [nlines * ns] first packed quad of each segment in its step
+    int32_t* qe = nullptr;         // [nlines * ns] end of the segment's packed quads
+    int32_t* steplanes = nullptr;  // [kmax] lanes of each step
+    int64_t* stepoff = nullptr;    // [kmax + 1] exclusive scan of steplanes
+    int32_t* lmeta = nullptr;      // [lanes_max] slice << 8 | quad where the second segment starts
+    void* pval = nullptr;          // [lanes_max * E] packed values
+    uint16_t* poff = nullptr;      // [lanes_max * E] packed byte offsets inside the slice
 };
 
 struct IterArgs {
     const int64_t* ptr;   // line pointers (empty-line test)
     int64_t nlines;
     int64_t nx;           // length of the gathered vector
-    const int32_t* split;
     int nslices;
     const int32_t* rstart;
-    const int64_t* lane_ptr;
-    const int32_t* lst;
-    const int32_t* lseg;
+    const int64_t* stepoff;
+    const int32_t* qs;
+    const int32_t* qe;
+    const int32_t* lmeta;
     const PlanInfo* info;
     const void* pval;
     const uint16_t* poff;
     const double* marg;   // a_eff (u role) or b_eff (v role)
+    const double* lmarg;  // log of marg (log domain; else unused)
     const void* xin;      // gathered vector: v^(t-1) (u role), u^t (v role)
     void* yout;           // new scaling / potential
     float* yg;            // log domain: FP32 copy of yout for the next gather (else NULL)
@@ -188,6 +192,8 @@ int iterate_grid(int precision, int block);  // valid after iterate_init()
 hipError_t build_plan(int precision, const IterPlan& p, const int64_t* ptr, const int32_t* idx,
                       const void* val, int64_t nlines, hipStream_t st);
 hipError_t launch_iterate(int precision, int block, int grid, const IterArgs& a, hipStream_t st);
+// out[i] = log(in[i]) (log of a marginal; -inf for 0)
+hipError_t launch_log_vec(const double* in, double* out, int64_t n, hipStream_t st);
 hipError_t launch_init_scaling(int precision, void* y, float* yg, const double* init_log,
                                int64_t n, hipStream_t st);
 hipError_t launch_export_scaling(int precision, const void* y, double* out, int64_t n,
