@@ -131,7 +131,9 @@ Layout plan(const ss_problem* P, const ss_options* O) {
     // log domain: logs of the effective marginals, formed once per solve
     L.la_eff = take(O->precision == SS_F32_LOG ? (size_t)n * 8 : 0);
     L.lb_eff = take(O->precision == SS_F32_LOG ? (size_t)m * 8 : 0);
-    L.tmp = take((size_t)2 * nm * 8);
+    // sampling scratch; at the start it holds the pruned cost maximum's state
+    const size_t tmp_bytes = (size_t)2 * nm * 8;
+    L.tmp = take(tmp_bytes > cmax_scratch_bytes(n) ? tmp_bytes : cmax_scratch_bytes(n));
     const int64_t cost_blocks = ((n + 255) / 256) * ((m + 2047) / 2048);
     const int64_t tree_len = (cost_blocks > nm ? cost_blocks : nm);
     L.tree = take((size_t)(2 * ((tree_len + 1023) / 1024) + 2) * 8);
@@ -319,7 +321,7 @@ int stage_start(Ctx& c) {
     HIP_TRY(launch_fill_u32(at<uint32_t>(c.ws, c.L.state), sizeof(IterState) / 4, 0u, c.st));
     HIP_TRY(launch_validate(P->a, P->n, P->x, P->n * P->d, stats, c.st));
     HIP_TRY(launch_validate(P->b, P->m, P->y, P->m * P->d, stats, c.st));
-    HIP_TRY(launch_cmax(P->x, P->y, P->n, P->m, P->d, stats, c.st));
+    HIP_TRY(launch_cmax(P->x, P->y, P->n, P->m, P->d, stats, at<void>(c.ws, c.L.tmp), c.st));
     HIP_TRY(hipMemcpyAsync(c.stats, stats, sizeof(c.stats), hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     if (c.stats[ST_BAD_INPUT] != 0.0)

@@ -78,8 +78,11 @@ hipError_t launch_validate(const double* a, int64_t n, const double* x, int64_t 
                            hipStream_t st);
 hipError_t launch_tree_sum(const double* in, int64_t n, double* scratch, double* out,
                            hipStream_t st);
+// max_ij c_ij into stats[ST_CMAX] (which must start at 0); `scratch` holds
+// cmax_scratch_bytes(n) bytes.
 hipError_t launch_cmax(const double* x, const double* y, int64_t n, int64_t m, int d,
-                       double* stats, hipStream_t st);
+                       double* stats, void* scratch, hipStream_t st);
+size_t cmax_scratch_bytes(int64_t n);
 hipError_t launch_ot_prep(const double* a, const double* b, int64_t n, int64_t m, double s,
                           double* ra, double* rb, double* scratch, double* stats,
                           hipStream_t st);

@@ -214,13 +214,18 @@ __global__ void k_plan_bounds(const int64_t* __restrict__ wptr, int64_t nlines,
 // p = s * nl + i (line r0 + i, slice s) and the step's lane count.  Segments
 // of one slice follow each other; a slice starts on a new lane; a segment
 // starts on the next lane when the lane it would start in already holds two
-// segments.  One thread lays the step out (at most kMaxPairs segments).
+// segments.  A thread lays out one slice (from quad 0), a block scan over the
+// slices' lane counts gives each slice its first lane, and the ranges are
+// shifted there.
 __global__ __launch_bounds__(256) void k_layout(const int32_t* __restrict__ split, int ns, int J,
                                                 const int32_t* __restrict__ rstart,
                                                 const PlanInfo* __restrict__ info, int64_t kmax,
                                                 int32_t* __restrict__ qs, int32_t* __restrict__ qe,
                                                 int32_t* __restrict__ steplanes) {
-    __shared__ int nq[kMaxPairs];
+    __shared__ int nq[kMaxPairs];   // quads of each segment, then its start in its slice
+    __shared__ int qe_l[kMaxPairs];  // end of each segment in its slice
+    __shared__ int sl_lanes[kMaxPairs / 2 + 1];  // per slice: lanes, then first lane
+    __shared__ int wsum[256 / kWave];
     const int64_t k = blockIdx.x;
     if (k >= kmax) return;
     if (k >= info->K) {
@@ -230,18 +235,16 @@ __global__ __launch_bounds__(256) void k_layout(const int32_t* __restrict__ spli
     const int64_t r0 = rstart[k];
     const int nl = (int)(rstart[k + 1] - r0);
     const int P = ns * nl;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const int tid = threadIdx.x;
+    for (int p = tid; p < P; p += blockDim.x) {
         const int s = p / nl, i = p - s * nl;
         const int32_t* sp = split + (r0 + i) * (ns + 1);
         nq[p] = (sp[s + 1] - sp[s] + 3) / 4;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    int32_t* qs_k = qs + r0 * ns;
-    int32_t* qe_k = qe + r0 * ns;
-    int pos = 0;
-    for (int s = 0; s < ns; ++s) {
-        int prev = pos;  // start of the last segment placed in this slice
+    for (int s = tid; s < ns; s += blockDim.x) {
+        int pos = 0;
+        int prev = 0;  // start of the last segment placed in this slice
         for (int i = 0; i < nl; ++i) {
             const int p = s * nl + i;
             const int n = nq[p];
@@ -252,13 +255,44 @@ __global__ __launch_bounds__(256) void k_layout(const int32_t* __restrict__ spli
                 if (pos != lane0 * J && prev > lane0 * J) pos = (lane0 + 1) * J;
                 prev = pos;
             }
-            qs_k[p] = pos;
+            nq[p] = pos;
             pos += n;
-            qe_k[p] = pos;
+            qe_l[p] = pos;
         }
-        pos = (pos + J - 1) / J * J;
+        sl_lanes[s] = (pos + J - 1) / J;
     }
-    steplanes[k] = pos / J;
+    __syncthreads();
+    // exclusive scan of the slices' lane counts (ns <= kMaxPairs / 2)
+    const int per = (ns + 255) / 256;
+    int mine = 0;
+    for (int u = 0; u < per; ++u) {
+        const int s = tid * per + u;
+        if (s < ns) mine += sl_lanes[s];
+    }
+    const int incl = wave_inclusive_scan(mine);
+    if ((tid & (kWave - 1)) == kWave - 1) wsum[tid / kWave] = incl;
+    __syncthreads();
+    int run = incl - mine;
+    for (int w = 0; w < tid / kWave; ++w) run += wsum[w];
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();  // every thread has read its slices' counts
+    for (int u = 0; u < per; ++u) {
+        const int s = tid * per + u;
+        if (s < ns) {
+            const int c = sl_lanes[s];
+            sl_lanes[s] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    int32_t* qs_k = qs + r0 * ns;
+    int32_t* qe_k = qe + r0 * ns;
+    for (int p = tid; p < P; p += blockDim.x) {
+        const int shift = sl_lanes[p / nl] * J;
+        qs_k[p] = nq[p] + shift;
+        qe_k[p] = qe_l[p] + shift;
+    }
+    if (tid == 0) steplanes[k] = total;
 }
 
 // Last index p in [0, n) with a[p * stride] <= key (nondecreasing, a[0] <= key).

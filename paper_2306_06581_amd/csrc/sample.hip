@@ -111,25 +111,123 @@ hipError_t launch_tree_sum(const double* in, int64_t n, double* scratch, double*
 constexpr int kCostTileCols = 2048;
 
 // max_ij c_ij; non-negative doubles order like their bit patterns.
-template <int D>
-__global__ __launch_bounds__(256) void k_cmax(const double* __restrict__ x, const double* __restrict__ y,
-                                              int64_t n, int64_t m, int d, int64_t ncol_tiles,
-                                              double* stats) {
-    const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
-    const int64_t i = rt * 256 + threadIdx.x;
-    const int64_t j0 = ct * kCostTileCols;
-    const int64_t j1 = (j0 + kCostTileCols < m) ? j0 + kCostTileCols : m;
-    double mx = 0.0;
+//
+// Exact pruning: with a centre c and R = max_j |y_j - c|, the triangle
+// inequality bounds row i by ub_i = (|x_i - c| + R)^2 >= max_j c_ij (a
+// relative margin of 1e-9 covers the rounding of every term for d <= 64).
+// The full row of the x point farthest from c gives a lower bound L0 on the
+// maximum, so only rows with ub_i >= L0 can hold it; those rows are scanned
+// with the same distance code as the brute-force maximum, so the result is
+// that maximum, bit for bit.  Clouds without such structure leave every row
+// a survivor and cost one brute-force pass.
+constexpr int kCenterPoints = 16384;  // the centre is the mean of the first points of y
+
+struct CmaxScratch {
+    double center[64];
+    unsigned long long r2;   // max_j |y_j - c|^2 as bits
+    unsigned long long far;  // (float bits of |x_i - c|^2) << 32 | i, maximised
+    int count;               // survivor rows
+    int pad;
+};
+
+__device__ __forceinline__ double center_sqdist(const double* p, const double* c, int d) {
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double u = p[k] - c[k];
+        acc = acc + u * u;
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void k_cm_center(const double* __restrict__ y, int64_t m, int d,
+                                                   CmaxScratch* cs) {
+    __shared__ double sh[16];
+    const int64_t np = m < kCenterPoints ? m : kCenterPoints;
+    for (int k = 0; k < d; ++k) {
+        double acc = 0.0;
+        for (int64_t j = threadIdx.x; j < np; j += blockDim.x) acc += y[j * d + k];
+        acc = block_sum(acc, sh);
+        if (threadIdx.x == 0) cs->center[k] = acc / (double)np;
+    }
+    if (threadIdx.x == 0) {
+        cs->r2 = 0ull;
+        cs->far = 0ull;
+        cs->count = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cm_radius(const double* __restrict__ y, int64_t m, int d,
+                                                   CmaxScratch* cs) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r2 = j < m ? center_sqdist(y + j * d, cs->center, d) : 0.0;
+    r2 = group_max<kWave>(r2);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&cs->r2, (unsigned long long)__double_as_longlong(r2));
+}
+
+__global__ __launch_bounds__(256) void k_cm_far(const double* __restrict__ x, int64_t n, int d,
+                                                CmaxScratch* cs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long key = 0ull;
     if (i < n) {
-        double xi[D > 0 ? D : 1];
-        const double* xp = x + i * d;
-        if (D > 0) {
+        const float d2 = (float)center_sqdist(x + i * d, cs->center, d);
+        key = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned long long)i;
+    }
+    key = group_max<kWave>(key);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&cs->far, key);
+}
+
+// Lower bound: the full row of the farthest x point, into stats[ST_CMAX].
+template <int D>
+__global__ __launch_bounds__(256) void k_cm_row(const double* __restrict__ x, const double* __restrict__ y,
+                                                int64_t m, int d, const CmaxScratch* cs,
+                                                double* stats) {
+    const int64_t i = (int64_t)(cs->far & 0xffffffffull);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double mx = j < m ? sqdist<D>(x + i * d, y + j * d, d) : 0.0;
+    mx = group_max<kWave>(mx);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        atomicMax((unsigned long long*)&stats[ST_CMAX], (unsigned long long)__double_as_longlong(mx));
+}
+
+// Rows whose bound reaches the lower bound.
+__global__ __launch_bounds__(256) void k_cm_survivors(const double* __restrict__ x, int64_t n, int d,
+                                                      CmaxScratch* cs, const double* stats,
+                                                      int32_t* __restrict__ rows) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double R = sqrt(__longlong_as_double((long long)cs->r2));
+    const double di = sqrt(center_sqdist(x + i * d, cs->center, d));
+    const double ub = (di + R) * (di + R) * (1.0 + 1e-9);
+    if (ub >= stats[ST_CMAX] && i != (int64_t)(cs->far & 0xffffffffull))
+        rows[atomicAdd(&cs->count, 1)] = (int32_t)i;
+}
+
+// Maximum over the survivor rows: items (group of 256 rows, column tile),
+// grid-stride; thread = row, columns in order within the tile.
+template <int D>
+__global__ __launch_bounds__(256) void k_cmax_rows(const double* __restrict__ x, const double* __restrict__ y,
+                                                   int64_t m, int d, const int32_t* __restrict__ rows,
+                                                   const CmaxScratch* cs, double* stats) {
+    const int64_t nct = (m + kCostTileCols - 1) / kCostTileCols;
+    const int64_t count = cs->count;
+    const int64_t items = (count + 255) / 256 * nct;
+    double mx = 0.0;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t rg = it / nct, ct = it - rg * nct;
+        const int64_t s = rg * 256 + threadIdx.x;
+        const int64_t j0 = ct * kCostTileCols;
+        const int64_t j1 = (j0 + kCostTileCols < m) ? j0 + kCostTileCols : m;
+        if (s < count) {
+            const double* xp = x + (int64_t)rows[s] * d;
+            double xi[D > 0 ? D : 1];
+            if (D > 0) {
 #pragma unroll
-            for (int k = 0; k < (D > 0 ? D : 1); ++k) xi[k] = xp[k];
-        }
-        for (int64_t j = j0; j < j1; ++j) {
-            const double c = sqdist<D>(D > 0 ? xi : xp, y + j * d, d);
-            mx = c > mx ? c : mx;
+                for (int k = 0; k < (D > 0 ? D : 1); ++k) xi[k] = xp[k];
+            }
+            for (int64_t j = j0; j < j1; ++j) {
+                const double c = sqdist<D>(D > 0 ? xi : xp, y + j * d, d);
+                mx = c > mx ? c : mx;
+            }
         }
     }
     mx = group_max<kWave>(mx);
@@ -149,18 +247,25 @@ __global__ __launch_bounds__(256) void k_cmax(const double* __restrict__ x, cons
 
 template <int D>
 static void run_cmax(const double* x, const double* y, int64_t n, int64_t m, int d, double* stats,
-                     hipStream_t st) {
-    const int64_t nct = (m + kCostTileCols - 1) / kCostTileCols;
-    const int64_t nrt = (n + 255) / 256;
-    hipLaunchKernelGGL(k_cmax<D>, dim3((unsigned)(nct * nrt)), dim3(256), 0, st, x, y, n, m, d, nct,
-                       stats);
+                     CmaxScratch* cs, int32_t* rows, hipStream_t st) {
+    hipLaunchKernelGGL(k_cm_row<D>, dim3(grid_for(m)), dim3(256), 0, st, x, y, m, d, cs, stats);
+    hipLaunchKernelGGL(k_cm_survivors, dim3(grid_for(n)), dim3(256), 0, st, x, n, d, cs, stats,
+                       rows);
+    hipLaunchKernelGGL(k_cmax_rows<D>, dim3(1024), dim3(256), 0, st, x, y, m, d, rows, cs, stats);
 }
 
 hipError_t launch_cmax(const double* x, const double* y, int64_t n, int64_t m, int d,
-                       double* stats, hipStream_t st) {
-    SS_DISPATCH_D(d, run_cmax, x, y, n, m, d, stats, st);
+                       double* stats, void* scratch, hipStream_t st) {
+    CmaxScratch* cs = (CmaxScratch*)scratch;
+    int32_t* rows = (int32_t*)(cs + 1);
+    hipLaunchKernelGGL(k_cm_center, dim3(1), dim3(256), 0, st, y, m, d, cs);
+    hipLaunchKernelGGL(k_cm_radius, dim3(grid_for(m)), dim3(256), 0, st, y, m, d, cs);
+    hipLaunchKernelGGL(k_cm_far, dim3(grid_for(n)), dim3(256), 0, st, x, n, d, cs);
+    SS_DISPATCH_D(d, run_cmax, x, y, n, m, d, stats, cs, rows, st);
     return hipGetLastError();
 }
+
+size_t cmax_scratch_bytes(int64_t n) { return sizeof(CmaxScratch) + (size_t)n * 4; }
 
 // ------------------------------------------------------------------ OT prep
 __global__ void k_sqrt2(const double* a, const double* b, int64_t n, int64_t m, double* ra,
