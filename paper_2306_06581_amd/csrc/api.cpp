@@ -368,9 +368,11 @@ int stage_sample(Ctx& c) {
         HIP_TRY(launch_ot_prep(P->a, P->b, n, m, O->s, (double*)pp.row_fac, (double*)pp.col_fac,
                                tree, stats, st));
     } else {
+        // exp(col_fac) goes to col_bnd until the bounds below replace it
         HIP_TRY(launch_uot_prep(P->a, P->b, n, m, O->lambda, O->eps, (double*)pp.row_fac,
-                                (double*)pp.col_fac, (double*)pp.row_bnd, st));
-        HIP_TRY(launch_uot_z(pp, n, m, at<double>(ws, c.L.partials), tree, stats, st));
+                                (double*)pp.col_fac, (double*)pp.row_bnd, (double*)pp.col_bnd, st));
+        HIP_TRY(launch_uot_z(pp, n, m, pp.col_bnd, c.stats[ST_CMAX], at<double>(ws, c.L.partials),
+                             tree, stats, st));
         HIP_TRY(launch_uot_bounds(pp.col_fac, m, O->s, stats, (double*)pp.col_bnd, st));
     }
     int32_t* row_cnt = at<int32_t>(ws, c.L.row_cnt);

@@ -87,9 +87,12 @@ hipError_t launch_ot_prep(const double* a, const double* b, int64_t n, int64_t m
                           double* ra, double* rb, double* scratch, double* stats,
                           hipStream_t st);
 hipError_t launch_uot_prep(const double* a, const double* b, int64_t n, int64_t m, double lam,
-                           double eps, double* la, double* lb, double* ea, hipStream_t st);
-hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, double* partials,
-                        double* scratch, double* stats, hipStream_t st);
+                           double eps, double* la, double* lb, double* ea, double* eb,
+                           hipStream_t st);
+// Z (eq. (pij-uot) normaliser) into stats[ST_Z]; eb_j = exp(col_fac_j); cmax
+// is the cost maximum (chooses the short-range exponential when it applies).
+hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* eb, double cmax,
+                        double* partials, double* scratch, double* stats, hipStream_t st);
 hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, const double* stats,
                              double* fb, hipStream_t st);
 hipError_t launch_mask(const ProbParams& pp, int64_t n, int64_t m, uint64_t* mask,

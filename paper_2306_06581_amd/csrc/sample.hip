@@ -296,24 +296,30 @@ hipError_t launch_ot_prep(const double* a, const double* b, int64_t n, int64_t m
 }
 
 // ------------------------------------------------------------------ UOT prep
-// la_i = th_u log a_i, lb_j = th_u log b_j (th_u = lam/(2lam+eps)); ea_i = exp(la_i).
+// la_i = th_u log a_i, lb_j = th_u log b_j (th_u = lam/(2lam+eps)); ea_i = exp(la_i),
+// eb_j = exp(lb_j).
 __global__ void k_uot_logs(const double* a, const double* b, int64_t n, int64_t m, double thu,
-                           double* la, double* lb, double* ea) {
+                           double* la, double* lb, double* ea, double* eb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const double l = thu * log(a[i]);
         la[i] = l;
         ea[i] = exp(l);
     }
-    if (i < m) lb[i] = thu * log(b[i]);
+    if (i < m) {
+        const double l = thu * log(b[i]);
+        lb[i] = l;
+        eb[i] = exp(l);
+    }
 }
 
 hipError_t launch_uot_prep(const double* a, const double* b, int64_t n, int64_t m, double lam,
-                           double eps, double* la, double* lb, double* ea, hipStream_t st) {
+                           double eps, double* la, double* lb, double* ea, double* eb,
+                           hipStream_t st) {
     const double thu = lam / (2.0 * lam + eps);
     const int64_t t = n > m ? n : m;
     hipLaunchKernelGGL(k_uot_logs, dim3(grid_for(t)), dim3(kBlock), 0, st, a, b, n, m, thu, la, lb,
-                       ea);
+                       ea, eb);
     return hipGetLastError();
 }
 
@@ -328,9 +334,16 @@ __device__ __forceinline__ double uot_q(const ProbParams& pp, const double* xi, 
 
 // Z = sum_ij q_ij: per-thread sums over a column tile in column order, a fixed
 // block tree, then the tree sum of the block partials.
-template <int D>
+//
+// SHORT (g = inv_cmax inv_tau with g max c <= 1/2): q_ij = ea_i eb_j
+// exp(-g c_ij), and exp(-g c) = e^(-1/4) e^u with u = 1/4 - g c in
+// [-1/4, 1/4] is a degree-11 Taylor polynomial in u (truncation below
+// 1.6e-16 relative), so no range reduction is needed: 12 fused multiply-adds
+// a pair instead of a general exponential.
+template <int D, bool SHORT>
 __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t m, int64_t ncol_tiles,
-                                               double* partials) {
+                                               const double* __restrict__ eb, double g,
+                                               double e_quarter, double* partials) {
     __shared__ double sh[4];
     const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
     const int64_t i = rt * 256 + threadIdx.x;
@@ -344,11 +357,36 @@ __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t
 #pragma unroll
             for (int k = 0; k < (D > 0 ? D : 1); ++k) xi[k] = xp[k];
         }
-        const double la = pp.row_fac[i];
-        for (int64_t j = j0; j < j1; ++j) {
-            const double c = sqdist<D>(D > 0 ? xi : xp, pp.y + j * pp.d, pp.d);
-            const double C = c * pp.inv_cmax;
-            acc = acc + exp((la + pp.col_fac[j]) - C * pp.inv_tau);
+        if constexpr (SHORT) {
+            // 1/k!, k = 0..11
+            constexpr double f0 = 1.0, f1 = 1.0, f2 = 1.0 / 2, f3 = 1.0 / 6, f4 = 1.0 / 24,
+                             f5 = 1.0 / 120, f6 = 1.0 / 720, f7 = 1.0 / 5040, f8 = 1.0 / 40320,
+                             f9 = 1.0 / 362880, f10 = 1.0 / 3628800, f11 = 1.0 / 39916800;
+            for (int64_t j = j0; j < j1; ++j) {
+                const double c = sqdist<D>(D > 0 ? xi : xp, pp.y + j * pp.d, pp.d);
+                const double u = fma(-g, c, 0.25);
+                double p = f11;
+                p = fma(p, u, f10);
+                p = fma(p, u, f9);
+                p = fma(p, u, f8);
+                p = fma(p, u, f7);
+                p = fma(p, u, f6);
+                p = fma(p, u, f5);
+                p = fma(p, u, f4);
+                p = fma(p, u, f3);
+                p = fma(p, u, f2);
+                p = fma(p, u, f1);
+                p = fma(p, u, f0);
+                acc = fma(p, eb[j], acc);
+            }
+            acc = acc * (pp.row_bnd[i] * e_quarter);
+        } else {
+            const double la = pp.row_fac[i];
+            for (int64_t j = j0; j < j1; ++j) {
+                const double c = sqdist<D>(D > 0 ? xi : xp, pp.y + j * pp.d, pp.d);
+                const double C = c * pp.inv_cmax;
+                acc = acc + exp((la + pp.col_fac[j]) - C * pp.inv_tau);
+            }
         }
     }
     const double tot = block_sum256(acc, sh);
@@ -356,17 +394,25 @@ __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t
 }
 
 template <int D>
-static void run_uot_z(const ProbParams& pp, int64_t n, int64_t m, double* partials, int64_t nct,
-                      int64_t nrt, hipStream_t st) {
-    hipLaunchKernelGGL(k_uot_z<D>, dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n, m, nct,
-                       partials);
+static void run_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* eb, double g,
+                      bool short_range, double* partials, int64_t nct, int64_t nrt,
+                      hipStream_t st) {
+    const double eq = exp(-0.25);
+    if (short_range)
+        hipLaunchKernelGGL((k_uot_z<D, true>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n,
+                           m, nct, eb, g, eq, partials);
+    else
+        hipLaunchKernelGGL((k_uot_z<D, false>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n,
+                           m, nct, eb, g, eq, partials);
 }
 
-hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, double* partials,
-                        double* scratch, double* stats, hipStream_t st) {
+hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* eb, double cmax,
+                        double* partials, double* scratch, double* stats, hipStream_t st) {
     const int64_t nct = (m + kCostTileCols - 1) / kCostTileCols;
     const int64_t nrt = (n + 255) / 256;
-    SS_DISPATCH_D(pp.d, run_uot_z, pp, n, m, partials, nct, nrt, st);
+    const double g = pp.inv_cmax * pp.inv_tau;
+    const bool short_range = g * cmax <= 0.5;
+    SS_DISPATCH_D(pp.d, run_uot_z, pp, n, m, eb, g, short_range, partials, nct, nrt, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_tree_sum(partials, nct * nrt, scratch, stats + ST_Z, st);

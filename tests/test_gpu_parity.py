@@ -111,9 +111,11 @@ def _uot_mask_compare(g_mask, sk, p, rows):
     return len(rr)
 
 
-@pytest.mark.parametrize("n,eps", [(600, 0.05), (513, 0.01)])
-def test_sample_uot(api, n, eps):
-    p = W.uot_mix3(n, seed=7, eps=eps)
+# lam = 1: the normaliser's short-range exponential (1/(2 lam + eps) <= 1/2);
+# lam = 0.3: the general exponential
+@pytest.mark.parametrize("n,eps,lam", [(600, 0.05, 1.0), (513, 0.01, 1.0), (400, 0.05, 0.3)])
+def test_sample_uot(api, n, eps, lam):
+    p = W.uot_mix3(n, seed=7, eps=eps, lam=lam)
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
     g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
     assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
