@@ -202,30 +202,33 @@ __global__ __launch_bounds__(256) void k_cm_survivors(const double* __restrict__
         rows[atomicAdd(&cs->count, 1)] = (int32_t)i;
 }
 
-// Maximum over the survivor rows: items (group of 256 rows, column tile),
-// grid-stride; thread = row, columns in order within the tile.
+// Maximum over the survivor rows: items (64 survivor rows, 256 columns),
+// grid-stride; the item's rows go to LDS, thread = column, rows in order.  The
+// distance is the brute-force one, sqdist(x_i, y_j).
+constexpr int kCmaxRows = 64;
+
 template <int D>
 __global__ __launch_bounds__(256) void k_cmax_rows(const double* __restrict__ x, const double* __restrict__ y,
                                                    int64_t m, int d, const int32_t* __restrict__ rows,
                                                    const CmaxScratch* cs, double* stats) {
-    const int64_t nct = (m + kCostTileCols - 1) / kCostTileCols;
+    __shared__ double xr[kCmaxRows * 64];  // d <= 64
+    const int64_t ncc = (m + 255) / 256;
     const int64_t count = cs->count;
-    const int64_t items = (count + 255) / 256 * nct;
+    const int64_t items = (count + kCmaxRows - 1) / kCmaxRows * ncc;
     double mx = 0.0;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const int64_t rg = it / nct, ct = it - rg * nct;
-        const int64_t s = rg * 256 + threadIdx.x;
-        const int64_t j0 = ct * kCostTileCols;
-        const int64_t j1 = (j0 + kCostTileCols < m) ? j0 + kCostTileCols : m;
-        if (s < count) {
-            const double* xp = x + (int64_t)rows[s] * d;
-            double xi[D > 0 ? D : 1];
-            if (D > 0) {
-#pragma unroll
-                for (int k = 0; k < (D > 0 ? D : 1); ++k) xi[k] = xp[k];
-            }
-            for (int64_t j = j0; j < j1; ++j) {
-                const double c = sqdist<D>(D > 0 ? xi : xp, y + j * d, d);
+        const int64_t rg = it / ncc, cc = it - rg * ncc;
+        const int64_t s0 = rg * kCmaxRows;
+        const int nr = (int)(count - s0 < kCmaxRows ? count - s0 : kCmaxRows);
+        __syncthreads();  // the previous item's rows are no longer read
+        for (int t = threadIdx.x; t < nr * d; t += blockDim.x)
+            xr[t] = x[(int64_t)rows[s0 + t / d] * d + t % d];
+        __syncthreads();
+        const int64_t j = cc * 256 + threadIdx.x;
+        if (j < m) {
+            const double* yj = y + j * d;
+            for (int r = 0; r < nr; ++r) {
+                const double c = sqdist<D>(xr + r * d, yj, d);
                 mx = c > mx ? c : mx;
             }
         }
