@@ -166,6 +166,10 @@ class Options:
     empty_policy: str = "auto"     # auto | renormalize | zero | fail
     stop_rule: str = "marginal"    # marginal | delta
     log_domain: bool = False
+    # weight g of the uniform probability 1/(nm) mixed into the sampling
+    # probability (Sec. 4, shrinkage: p = (1 - g) p + g / (nm)); g = 1 is the
+    # equal-probability subsampling of Sec. 5 (Rand-Sink)
+    shrink: float = 0.0
 
 
 class EmptySupportError(RuntimeError):
@@ -189,22 +193,30 @@ def cost_scale(x, y, opt: Options) -> tuple[float, float]:
 # --------------------------------------------------------------------------
 @dataclass
 class ProbOT:
-    alpha: np.ndarray   # s * sqrt(a_i) / (S_a S_b)
+    alpha: np.ndarray   # (1 - g) s sqrt(a_i) / (S_a S_b)
     rb: np.ndarray      # sqrt(b_j)
     s_a: float
     s_b: float
+    c0: float = 0.0     # s g / (nm): the uniform part of s p
 
     def pstar(self, rows, cols):
-        return np.minimum(1.0, self.alpha[rows][:, None] * self.rb[cols][None, :])
+        return np.minimum(1.0, self.alpha[rows][:, None] * self.rb[cols][None, :] + self.c0)
 
 
-def ot_probabilities(a, b, s) -> ProbOT:
-    """eq. (pij-ot): p_ij = sqrt(a_i) sqrt(b_j) / (sum_i sqrt(a_i) sum_j sqrt(b_j))."""
+def shrink_terms(s, shrink, n, m) -> tuple[float, float]:
+    """(1 - g, s g / (nm)): s p = (1 - g) s p_ij + s g / (nm) (Sec. 4, shrinkage)."""
+    return 1.0 - shrink, s * shrink / (float(n) * float(m))
+
+
+def ot_probabilities(a, b, s, shrink: float = 0.0) -> ProbOT:
+    """eq. (pij-ot): p_ij = sqrt(a_i) sqrt(b_j) / (sum_i sqrt(a_i) sum_j sqrt(b_j)),
+    mixed with the uniform probability with weight `shrink`."""
     ra = np.sqrt(np.asarray(a, dtype=np.float64))
     rb = np.sqrt(np.asarray(b, dtype=np.float64))
     s_a, s_b = tree_sum(ra), tree_sum(rb)
     kappa = s / (s_a * s_b)
-    return ProbOT(alpha=kappa * ra, rb=rb, s_a=s_a, s_b=s_b)
+    w, c0 = shrink_terms(s, shrink, ra.size, rb.size)
+    return ProbOT(alpha=(kappa * ra) * w, rb=rb, s_a=s_a, s_b=s_b, c0=c0)
 
 
 @dataclass
@@ -214,9 +226,10 @@ class ProbUOT:
     inv_tau: float      # 1 / (2 lam + eps)
     inv_cmax: float
     z: float            # sum_ij q_ij
-    kappa: float        # s / z
+    kappa: float        # (1 - g) s / z
     x: np.ndarray
     y: np.ndarray
+    c0: float = 0.0     # s g / (nm)
 
     def q(self, rows, cols):
         cij = sq_dist(self.x[rows], self.y[cols]) * self.inv_cmax
@@ -225,11 +238,13 @@ class ProbUOT:
         return np.exp(e)
 
     def pstar(self, rows, cols):
-        return np.minimum(1.0, self.kappa * self.q(rows, cols))
+        return np.minimum(1.0, self.kappa * self.q(rows, cols) + self.c0)
 
 
-def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256) -> ProbUOT:
-    """eq. (pij-uot) with K^(eps/(2lam+eps)) written as exp(-C/(2lam+eps))."""
+def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256,
+                      shrink: float = 0.0) -> ProbUOT:
+    """eq. (pij-uot) with K^(eps/(2lam+eps)) written as exp(-C/(2lam+eps)),
+    mixed with the uniform probability with weight `shrink`."""
     tau = 2.0 * lam + eps
     th = lam / tau
     with np.errstate(divide="ignore"):
@@ -243,7 +258,8 @@ def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256) -> Pr
         rows = np.arange(r0, min(len(a), r0 + chunk))
         rowsums.append(pr.q(rows, cols).sum(axis=1))
     pr.z = float(np.sum(np.concatenate(rowsums)))
-    pr.kappa = s / pr.z
+    w, pr.c0 = shrink_terms(s, shrink, len(a), len(b))
+    pr.kappa = w * (s / pr.z)
     return pr
 
 
@@ -304,9 +320,10 @@ def build_sketch(x, y, a, b, opt: Options, chunk: int = 256) -> Sketch:
     n, m = x.shape[0], y.shape[0]
     cmax, inv_cmax = cost_scale(x, y, opt)
     if is_uot(opt):
-        prob = uot_probabilities(a, b, x, y, opt.s, opt.lam, opt.eps, inv_cmax)
+        prob = uot_probabilities(a, b, x, y, opt.s, opt.lam, opt.eps, inv_cmax,
+                                 shrink=opt.shrink)
     else:
-        prob = ot_probabilities(a, b, opt.s)
+        prob = ot_probabilities(a, b, opt.s, shrink=opt.shrink)
     masks, ri, ci, pvals = [], [], [], []
     for r0 in range(0, n, chunk):
         rows = np.arange(r0, min(n, r0 + chunk))
@@ -352,7 +369,7 @@ def expected_nnz_ot(prob: ProbOT) -> tuple[float, float]:
     """E[nnz] = sum p*, Var[nnz] = sum p*(1-p*) (eq. (pois) and its remark)."""
     e, v = 0.0, 0.0
     for i in range(prob.alpha.size):
-        p = np.minimum(1.0, prob.alpha[i] * prob.rb)
+        p = np.minimum(1.0, prob.alpha[i] * prob.rb + prob.c0)
         e += p.sum()
         v += (p * (1 - p)).sum()
     return e, v
