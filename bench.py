@@ -341,6 +341,21 @@ def main():
         out["dense_precision"] = dp
         out["dense_estimate"] = d.estimate
         out["speedup_vs_dense"] = dms / ms_step
+        # Sec. 5's comparison at the same budget s: the relative error of the
+        # estimate against the dense one, for Spar-Sink and for Rand-Sink
+        # (uniform probabilities, shrink = 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = A.spar_sink_uot(prob, **kw, shrink=1.0, raise_on_error=False)
+        torch.cuda.synchronize()
+        rel = lambda e: abs(e - d.estimate) / abs(d.estimate)
+        out["rand_sink"] = {"s": (time.perf_counter() - t0), "iters": rs.iters,
+                            "status": rs.status, "nnz": rs.nnz, "estimate": rs.estimate,
+                            "rel_err_vs_dense": rel(rs.estimate),
+                            "sparse_objective_rel_err_vs_dense": rel(rs.sparse_objective),
+                            "spar_sink_rel_err_vs_dense": rel(r.estimate),
+                            "spar_sink_sparse_objective_rel_err_vs_dense":
+                                rel(r.sparse_objective)}
     if not args.no_batched:
         out["batched"] = batched_bench(args.batch_count, args.steps)
     if args.warmstart_train > 0:

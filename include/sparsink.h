@@ -98,7 +98,12 @@ typedef struct ss_problem {
  * init_log_u, init_log_v  optional device FP64 warm start (log u^0, log v^0).
  * u_out, v_out optional device FP64 outputs: the returned scalings u^t, v^t.
  * err_hist     optional device FP64 array of max_iter entries: err(t) for
- *              t = 1..iters (entries past iters untouched). */
+ *              t = 1..iters (entries past iters untouched).
+ * shrink       g in [0, 1]: shrinkage toward uniform sampling (Sec. 4),
+ *              p_ij = (1 - g) p_ij + g / (nm) in place of eq. (pij-ot) /
+ *              eq. (pij-uot); 0 is Spar-Sink, 1 is Rand-Sink (Sec. 5, uniform
+ *              probabilities s / (nm)).  Only the sampling changes: the
+ *              sketch's values stay K_ij / p*_ij.  Batches need 0. */
 typedef struct ss_options {
     double eps, lambda, s, tol;
     uint64_t seed;
@@ -106,6 +111,7 @@ typedef struct ss_options {
     int32_t block_threads, graph_iters, reserved0;
     const double *init_log_u, *init_log_v;
     double *u_out, *v_out, *err_hist;
+    double shrink;
 } ss_options;
 
 /* Result of a solve (host struct).

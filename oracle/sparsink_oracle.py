@@ -133,11 +133,23 @@ def sq_dist(x, y):
     return acc
 
 
-def max_sq_dist(x, y, chunk: int = 512) -> float:
-    out = 0.0
-    for r0 in range(0, x.shape[0], chunk):
-        out = max(out, float(sq_dist(x[r0:r0 + chunk], y).max()))
-    return out
+def _map_chunks(fn, starts, workers: int) -> list:
+    """[fn(r0) for r0 in starts], optionally on a thread pool (numpy releases
+    the interpreter lock in its array loops); the results keep the order of
+    `starts`, so every caller's arithmetic is the same for any `workers`."""
+    starts = list(starts)
+    if workers <= 1:
+        return [fn(r0) for r0 in starts]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, starts))
+
+
+def max_sq_dist(x, y, chunk: int = 512, workers: int = 1) -> float:
+    """max_ij c_ij (the maximum does not depend on the order of the scan)."""
+    maxima = _map_chunks(lambda r0: float(sq_dist(x[r0:r0 + chunk], y).max()),
+                         range(0, x.shape[0], chunk), workers)
+    return max([0.0] + maxima)
 
 
 def kl_div(x, y) -> float:
@@ -242,7 +254,7 @@ class ProbUOT:
 
 
 def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256,
-                      shrink: float = 0.0) -> ProbUOT:
+                      shrink: float = 0.0, workers: int = 1) -> ProbUOT:
     """eq. (pij-uot) with K^(eps/(2lam+eps)) written as exp(-C/(2lam+eps)),
     mixed with the uniform probability with weight `shrink`."""
     tau = 2.0 * lam + eps
@@ -253,10 +265,9 @@ def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256,
     pr = ProbUOT(la=la, lb=lb, inv_tau=1.0 / tau, inv_cmax=inv_cmax, z=0.0, kappa=0.0,
                  x=np.asarray(x, np.float64), y=np.asarray(y, np.float64))
     cols = np.arange(len(b))
-    rowsums = []
-    for r0 in range(0, len(a), chunk):
-        rows = np.arange(r0, min(len(a), r0 + chunk))
-        rowsums.append(pr.q(rows, cols).sum(axis=1))
+    rowsums = _map_chunks(
+        lambda r0: pr.q(np.arange(r0, min(len(a), r0 + chunk)), cols).sum(axis=1),
+        range(0, len(a), chunk), workers)
     pr.z = float(np.sum(np.concatenate(rowsums)))
     w, pr.c0 = shrink_terms(s, shrink, len(a), len(b))
     pr.kappa = w * (s / pr.z)

@@ -214,6 +214,8 @@ int check_args(const ss_problem* P, const ss_options* O, bool dense) {
     if (!(bt == 0 || bt == 256 || bt == 1024))
         return fail(SS_E_INVALID_ARG, "block_threads must be 0, 256 or 1024");
     if (!(O->lambda > 0.0)) return fail(SS_E_INVALID_ARG, "lambda must be > 0 (or +INFINITY)");
+    if (!(O->shrink >= 0.0 && O->shrink <= 1.0))
+        return fail(SS_E_INVALID_ARG, "shrink must be in [0, 1]");
     if (!dense) {
         // the sparse iteration cuts the gathered vector into at most a fixed
         // number of LDS slices
@@ -340,6 +342,9 @@ ProbParams make_params(const Ctx& c) {
     pp.inv_cmax = c.inv_cmax;
     pp.inv_tau = c.uot ? 1.0 / (2.0 * O->lambda + O->eps) : 0.0;
     pp.kappa = 0.0;
+    // Sec. 4 shrinkage: s p = (1 - g) s p_ij + s g / (nm)
+    pp.shrink_w = 1.0 - O->shrink;
+    pp.shrink_c = O->s * O->shrink / ((double)c.P->n * (double)c.P->m);
     pp.row_fac = at<double>(c.ws, c.L.row_fac);
     pp.col_fac = at<double>(c.ws, c.L.col_fac);
     pp.row_bnd = at<double>(c.ws, c.L.row_bnd);
@@ -365,15 +370,16 @@ int stage_sample(Ctx& c) {
     double* tree = at<double>(ws, c.L.tree);
     ProbParams pp = make_params(c);
     if (!c.uot) {
-        HIP_TRY(launch_ot_prep(P->a, P->b, n, m, O->s, (double*)pp.row_fac, (double*)pp.col_fac,
-                               tree, stats, st));
+        HIP_TRY(launch_ot_prep(P->a, P->b, n, m, O->s, pp.shrink_w, (double*)pp.row_fac,
+                               (double*)pp.col_fac, tree, stats, st));
     } else {
         // exp(col_fac) goes to col_bnd until the bounds below replace it
         HIP_TRY(launch_uot_prep(P->a, P->b, n, m, O->lambda, O->eps, (double*)pp.row_fac,
                                 (double*)pp.col_fac, (double*)pp.row_bnd, (double*)pp.col_bnd, st));
         HIP_TRY(launch_uot_z(pp, n, m, pp.col_bnd, c.stats[ST_CMAX], at<double>(ws, c.L.partials),
                              tree, stats, st));
-        HIP_TRY(launch_uot_bounds(pp.col_fac, m, O->s, stats, (double*)pp.col_bnd, st));
+        HIP_TRY(launch_uot_bounds(pp.col_fac, m, O->s, pp.shrink_w, stats, (double*)pp.col_bnd,
+                                  st));
     }
     int32_t* row_cnt = at<int32_t>(ws, c.L.row_cnt);
     int32_t* col_cnt = at<int32_t>(ws, c.L.col_cnt);
@@ -705,6 +711,7 @@ int check_batch(const ss_batch* B, const ss_options* O) {
     if (!(O->tol >= 0.0)) return fail(SS_E_INVALID_ARG, "tol must be >= 0");
     if (O->max_iter < 1) return fail(SS_E_INVALID_ARG, "max_iter must be >= 1");
     if (isfinite(O->lambda)) return fail(SS_E_INVALID_ARG, "batches solve OT: lambda must be +INFINITY");
+    if (O->shrink != 0.0) return fail(SS_E_INVALID_ARG, "batches sample with shrink = 0 only");
     if (O->precision != SS_F64 && O->precision != SS_F32)
         return fail(SS_E_INVALID_ARG, "batches support precision SS_F64 or SS_F32");
     if (O->cost != SS_COST_SQEUCLID_MAXNORM && O->cost != SS_COST_SQEUCLID)

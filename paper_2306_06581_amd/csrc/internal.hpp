@@ -57,6 +57,8 @@ struct ProbParams {
     double inv_cmax;    // C = c * inv_cmax
     double inv_tau;     // 1 / (2 lam + eps)            (UOT)
     double kappa;       // s / Z                        (UOT; device value in stats)
+    double shrink_w;    // 1 - g: weight of eq. (pij-ot)/(pij-uot) in the shrunk p
+    double shrink_c;    // s g / (nm): the uniform part of s p (0 without shrinkage)
     const double* row_fac;  // OT: alpha_i;  UOT: th_u log a_i
     const double* col_fac;  // OT: sqrt b_j; UOT: th_u log b_j
     const double* row_bnd;  // UOT: exp(row_fac_i)
@@ -84,8 +86,8 @@ hipError_t launch_cmax(const double* x, const double* y, int64_t n, int64_t m, i
                        double* stats, void* scratch, hipStream_t st);
 size_t cmax_scratch_bytes(int64_t n);
 hipError_t launch_ot_prep(const double* a, const double* b, int64_t n, int64_t m, double s,
-                          double* ra, double* rb, double* scratch, double* stats,
-                          hipStream_t st);
+                          double shrink_w, double* ra, double* rb, double* scratch,
+                          double* stats, hipStream_t st);
 hipError_t launch_uot_prep(const double* a, const double* b, int64_t n, int64_t m, double lam,
                            double eps, double* la, double* lb, double* ea, double* eb,
                            hipStream_t st);
@@ -93,8 +95,8 @@ hipError_t launch_uot_prep(const double* a, const double* b, int64_t n, int64_t 
 // is the cost maximum (chooses the short-range exponential when it applies).
 hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* eb, double cmax,
                         double* partials, double* scratch, double* stats, hipStream_t st);
-hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, const double* stats,
-                             double* fb, hipStream_t st);
+hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrink_w,
+                             const double* stats, double* fb, hipStream_t st);
 hipError_t launch_mask(const ProbParams& pp, int64_t n, int64_t m, uint64_t* mask,
                        int32_t* row_cnt, const double* stats, hipStream_t st);
 hipError_t launch_transpose(const uint64_t* mask, int64_t n, int64_t m, uint64_t* maskT,

@@ -279,22 +279,23 @@ __global__ void k_sqrt2(const double* a, const double* b, int64_t n, int64_t m, 
 }
 
 // alpha_i = kappa sqrt(a_i), kappa = s / (S_a S_b)   (eq. (pij-ot) times s).
-__global__ void k_alpha(double* ra, int64_t n, double s, const double* stats) {
+// With shrinkage (Sec. 4) the factor carries the weight 1 - g of eq. (pij-ot).
+__global__ void k_alpha(double* ra, int64_t n, double s, double w, const double* stats) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double kappa = s / (stats[ST_SA] * stats[ST_SB]);
-    if (i < n) ra[i] = kappa * ra[i];
+    if (i < n) ra[i] = (kappa * ra[i]) * w;
 }
 
 hipError_t launch_ot_prep(const double* a, const double* b, int64_t n, int64_t m, double s,
-                          double* ra, double* rb, double* scratch, double* stats,
-                          hipStream_t st) {
+                          double shrink_w, double* ra, double* rb, double* scratch,
+                          double* stats, hipStream_t st) {
     const int64_t t = n > m ? n : m;
     hipLaunchKernelGGL(k_sqrt2, dim3(grid_for(t)), dim3(kBlock), 0, st, a, b, n, m, ra, rb);
     hipError_t e = launch_tree_sum(ra, n, scratch, stats + ST_SA, st);
     if (e != hipSuccess) return e;
     e = launch_tree_sum(rb, m, scratch, stats + ST_SB, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_alpha, dim3(grid_for(n)), dim3(kBlock), 0, st, ra, n, s, stats);
+    hipLaunchKernelGGL(k_alpha, dim3(grid_for(n)), dim3(kBlock), 0, st, ra, n, s, shrink_w, stats);
     return hipGetLastError();
 }
 
@@ -422,19 +423,21 @@ hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double
 }
 
 // Column factor of a rigorous upper bound on p*: for every (i, j),
-// p*_ij <= ea_i * fb_j with fb_j = (s/Z) exp(lb_j) (1 + 2^-30); the margin
-// covers the rounding of the sum, exponential and products (all < 1e-12).
-__global__ void k_uot_bounds(const double* lb, int64_t m, double s, const double* stats,
-                             double* fb) {
+// p*_ij <= ea_i * fb_j + c (1 + 2^-30) with fb_j = (1 - g)(s/Z) exp(lb_j)
+// (1 + 2^-30) and c the uniform part of shrinkage; the margins cover the
+// rounding of the sum, exponential and products (all < 1e-12).
+__global__ void k_uot_bounds(const double* lb, int64_t m, double s, double w,
+                             const double* stats, double* fb) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
-    const double kappa = s / stats[ST_Z];
+    const double kappa = w * (s / stats[ST_Z]);
     fb[j] = kappa * exp(lb[j]) * (1.0 + 0x1p-30);
 }
 
-hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, const double* stats,
-                             double* fb, hipStream_t st) {
-    hipLaunchKernelGGL(k_uot_bounds, dim3(grid_for(m)), dim3(kBlock), 0, st, lb, m, s, stats, fb);
+hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrink_w,
+                             const double* stats, double* fb, hipStream_t st) {
+    hipLaunchKernelGGL(k_uot_bounds, dim3(grid_for(m)), dim3(kBlock), 0, st, lb, m, s, shrink_w,
+                       stats, fb);
     return hipGetLastError();
 }
 
@@ -467,6 +470,9 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
         const int64_t i = row0 + r;
         if (i >= n) break;
         const double rowf = UOT ? pp.row_bnd[i] : pp.row_fac[i];
+        // the uniform part of shrinkage (0 without it); for the UOT bound with
+        // the bound's margin
+        const double pc = UOT ? pp.shrink_c * (1.0 + 0x1p-30) : pp.shrink_c;
         uint64_t mine = 0;
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
@@ -479,14 +485,14 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
                 const int64_t j = 256 * g + 64 * s + lane;
                 bool keep = false;
                 if (j < m) {
-                    const double P = rowf * cf[gg * 4 + s];
+                    const double P = rowf * cf[gg * 4 + s] + pc;
                     if (!UOT) {
                         keep = keep_decision(h.w[s], P, q, (uint32_t)i, pp.problem_index, pp.k0,
                                              pp.k1, s);
                     } else if ((double)h.w[s] * 0x1p-32 < P) {
                         // P is an upper bound; only candidates pay for the exact p*.
                         const double q_ij = uot_q<D>(pp, pp.x + i * pp.d, i, j);
-                        const double pst = fmin(1.0, kappa * q_ij);
+                        const double pst = fmin(1.0, kappa * q_ij + pp.shrink_c);
                         keep = keep_decision(h.w[s], pst, q, (uint32_t)i, pp.problem_index, pp.k0,
                                              pp.k1, s);
                     }
@@ -519,7 +525,7 @@ __global__ __launch_bounds__(256) void k_mask(ProbParams pp, int64_t n, int64_t 
                                               const double* __restrict__ stats) {
     __shared__ uint64_t tile[kMaskRows][64];
     const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
-    const double kappa = UOT ? pp.s / stats[ST_Z] : 0.0;
+    const double kappa = UOT ? pp.shrink_w * (pp.s / stats[ST_Z]) : 0.0;
     mask_tile<UOT, D>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile);
 }
 
@@ -735,9 +741,9 @@ __device__ __forceinline__ double entry_value(const ProbParams& pp, double kappa
     const double K = exp(-Ce);
     double P;
     if (UOT)
-        P = fmin(1.0, kappa * exp((pp.row_fac[i] + pp.col_fac[j]) - C * pp.inv_tau));
+        P = fmin(1.0, kappa * exp((pp.row_fac[i] + pp.col_fac[j]) - C * pp.inv_tau) + pp.shrink_c);
     else
-        P = fmin(1.0, pp.row_fac[i] * pp.col_fac[j]);
+        P = fmin(1.0, pp.row_fac[i] * pp.col_fac[j] + pp.shrink_c);
     *logv = -Ce - log(P);
     return K / P;
 }
@@ -815,7 +821,7 @@ __global__ __launch_bounds__(256) void k_fill(ProbParams pp, const double* __res
     const int wv = threadIdx.x >> 6;
     const int64_t line = (int64_t)blockIdx.x * 4 + wv;
     const bool active = line < nlines;
-    const double kappa = UOT ? pp.s / stats[ST_Z] : 0.0;
+    const double kappa = UOT ? pp.shrink_w * (pp.s / stats[ST_Z]) : 0.0;
     fill_line<ROLE, UOT, PREC, D, int32_t>(pp, kappa, active, bits + (active ? line : 0) * words,
                                           line, words, active ? ptr[line] : 0, idx, val, cap,
                                           queue[wv]);
@@ -991,6 +997,8 @@ __global__ __launch_bounds__(256) void k_b_mask(BatchArgs A) {
     const int64_t nct = (P.W + 63) / 64;
     ProbParams pp;
     pp.uot = 0;
+    pp.shrink_w = 1.0;
+    pp.shrink_c = 0.0;
     pp.row_fac = A.row_fac + P.xo;
     pp.col_fac = A.col_fac + P.yo;
     pp.problem_index = P.pidx;
@@ -1023,6 +1031,8 @@ __global__ __launch_bounds__(256) void k_b_fill(BatchArgs A) {
     const int64_t local = (active ? L : lines - 1) - off[k];
     ProbParams pp;
     pp.uot = 0;
+    pp.shrink_w = 1.0;
+    pp.shrink_c = 0.0;
     pp.s = P.s;
     pp.eps = A.eps;
     pp.inv_cmax = A.stat[k].inv_cmax;

@@ -42,7 +42,7 @@ class SsOptions(ctypes.Structure):
                 ("cost", c_int32), ("stop_rule", c_int32), ("empty_policy", c_int32),
                 ("block_threads", c_int32), ("graph_iters", c_int32), ("reserved0", c_int32),
                 ("init_log_u", c_void_p), ("init_log_v", c_void_p), ("u_out", c_void_p),
-                ("v_out", c_void_p), ("err_hist", c_void_p)]
+                ("v_out", c_void_p), ("err_hist", c_void_p), ("shrink", c_double)]
 
 
 class SsResult(ctypes.Structure):

@@ -51,7 +51,7 @@ int main(void) {
          sizeof(ss_problem), sizeof(ss_options), sizeof(ss_result), sizeof(ss_sparse));
   printf("ss_batch %zu\nss_schedule %zu\n", sizeof(ss_batch), sizeof(ss_schedule));
   P(ss_batch, s) P(ss_batch, x) P(ss_batch, b) P(ss_schedule, block_threads)
-  P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist)
+  P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist) P(ss_options, shrink)
   P(ss_result, nnz) P(ss_result, iters) P(ss_result, t_obj_ms) P(ss_sparse, capacity)
   P(ss_sparse, z_norm)
   return 0;
@@ -77,6 +77,7 @@ def test_struct_layout_matches_header():
     assert N.SsOptions.seed.offset == lay["ss_options.seed"]
     assert N.SsOptions.init_log_u.offset == lay["ss_options.init_log_u"]
     assert N.SsOptions.err_hist.offset == lay["ss_options.err_hist"]
+    assert N.SsOptions.shrink.offset == lay["ss_options.shrink"]
     assert N.SsResult.nnz.offset == lay["ss_result.nnz"]
     assert N.SsResult.iters.offset == lay["ss_result.iters"]
     assert N.SsResult.t_obj_ms.offset == lay["ss_result.t_obj_ms"]

@@ -376,3 +376,15 @@ def test_estimate_error_shrinks_with_budget():
             e.append(abs(r.estimate.sparse_objective - dense.estimate.estimate))
         errs.append(np.mean(e))
     assert errs[1] < errs[0]
+
+
+def test_thread_pool_scans_match_the_serial_scans():
+    # the thread-pool option of the full scans changes no bit of cmax or Z
+    p = W.uot_mix3(700, seed=31, eps=0.05)
+    c1 = O.max_sq_dist(p.x, p.y)
+    c4 = O.max_sq_dist(p.x, p.y, chunk=64, workers=4)
+    assert c1 == c4 == float(O.sq_dist(p.x, p.y).max())
+    z1 = O.uot_probabilities(p.a, p.b, p.x, p.y, p.s, p.lam, p.eps, 1.0 / c1).z
+    z4 = O.uot_probabilities(p.a, p.b, p.x, p.y, p.s, p.lam, p.eps, 1.0 / c1, chunk=37,
+                             workers=4).z
+    assert z1 == z4
