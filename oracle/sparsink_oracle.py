@@ -324,13 +324,16 @@ def sample_rows(x, y, a, b, opt: Options, rows, prob=None, inv_cmax=None):
     return keep, pst, u01
 
 
-def build_sketch(x, y, a, b, opt: Options, chunk: int = 256) -> Sketch:
-    """Alg. 3/4 step 1: construct K~ by eq. (pois) with eq. (pij-ot)/(pij-uot)."""
+def build_sketch(x, y, a, b, opt: Options, chunk: int = 256, prob=None) -> Sketch:
+    """Alg. 3/4 step 1: construct K~ by eq. (pois) with eq. (pij-ot)/(pij-uot),
+    or with the given probabilities `prob` (an object with pstar(rows, cols))."""
     x = np.asarray(x, np.float64)
     y = np.asarray(y, np.float64)
     n, m = x.shape[0], y.shape[0]
     cmax, inv_cmax = cost_scale(x, y, opt)
-    if is_uot(opt):
+    if prob is not None:
+        pass
+    elif is_uot(opt):
         prob = uot_probabilities(a, b, x, y, opt.s, opt.lam, opt.eps, inv_cmax,
                                  shrink=opt.shrink)
     else:

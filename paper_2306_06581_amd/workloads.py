@@ -23,6 +23,12 @@ takes an explicit ``n`` so tests can use small or ragged shapes):
 * ``batch_ot``    -- many independent OT problems, n_k ~ U{256..4096}, d=3,
   x ~ N(mu_x, I), y ~ N(mu_y, I), mu ~ U[-1,1]^3, a,b ~ Dirichlet(1),
   eps=0.05, s_k = 8 n_k ln n_k.
+* ``ibp_synthetic`` -- fixed-support barycenter of three measures on n points
+  x ~ U(0,1)^d (the paper's barycenter simulation): b_1 a Gaussian
+  N(1/5, 1/50), b_2 the mixture N(1/2, 1/60)/2 + N(4/5, 1/80)/2, b_3 a t_5
+  with location 3/5 and scale^2 1/100, each a density evaluated on the index
+  grid i/n, raised by 1e-2 of its maximum and normalised; equal weights;
+  s = factor * s0(n), s0(n) = 1e-3 n ln^4 n.
 """
 from __future__ import annotations
 
@@ -31,7 +37,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Problem", "ot_gauss2d", "ot_t5_d10", "uot_mix3", "batch_ot", "s_budget"]
+__all__ = ["Problem", "ot_gauss2d", "ot_t5_d10", "uot_mix3", "batch_ot", "s_budget",
+           "IBPProblem", "ibp_synthetic", "s0_budget"]
 
 
 @dataclass
@@ -126,3 +133,52 @@ def batch_ot(count: int = 512, seed: int = 0, n_lo: int = 256, n_hi: int = 4096,
         out.append(Problem(x, y, a, b, eps=eps, s=s_budget(nk, s_factor), seed=seed,
                            problem_index=k, name=f"batch_ot_{k}_n{nk}"))
     return out
+
+
+@dataclass
+class IBPProblem:
+    """A fixed-support barycenter problem: support x, measures b[k], weights w."""
+
+    x: np.ndarray            # (n, d) float64
+    b: np.ndarray            # (m, n) float64, each row sums to 1
+    w: np.ndarray            # (m,) float64, sums to 1
+    eps: float
+    s: float
+    seed: int = 0
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def count(self) -> int:
+        return int(self.b.shape[0])
+
+
+def s0_budget(n: int) -> float:
+    """The barycenter experiments' unit budget 1e-3 n ln^4 n (natural log)."""
+    return 1e-3 * n * math.log(n) ** 4
+
+
+def ibp_synthetic(n: int = 1000, d: int = 5, seed: int = 0, eps: float = 0.01,
+                  s_factor: float = 20.0) -> IBPProblem:
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 1.0, size=(n, d))
+    t = np.arange(n) / n
+
+    def gauss(mu, var):
+        return np.exp(-0.5 * (t - mu) ** 2 / var)
+
+    def student5(mu, scale2):
+        return (1.0 + (t - mu) ** 2 / scale2 / 5.0) ** -3.0
+
+    dens = [gauss(0.2, 1 / 50), 0.5 * gauss(0.5, 1 / 60) + 0.5 * gauss(0.8, 1 / 80),
+            student5(0.6, 1 / 100)]
+    b = []
+    for g in dens:
+        g = g / g.sum()
+        g = g + 1e-2 * g.max()
+        b.append(g / g.sum())
+    return IBPProblem(x=x, b=np.array(b), w=np.full(3, 1.0 / 3.0), eps=eps,
+                      s=s_factor * s0_budget(n), seed=seed, name=f"ibp_synthetic_n{n}_d{d}")
