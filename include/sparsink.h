@@ -321,6 +321,68 @@ int ss_warmstart_train_step(ss_mlp *mlp, const ss_batch *batch, double eps, int3
                             const double *tgt_log_u, const double *tgt_log_v, float lr, void *ws,
                             size_t ws_bytes, void *stream, float *loss, float *grad_out);
 
+/* ------------------------------------------------------------------------
+ * Spar-IBP: fixed-support Wasserstein barycenters (the paper's barycenter
+ * section: eq. (wb), eq. (rwb), Alg. IBP, eq. (pois-k), Alg. Spar-IBP).
+ *
+ * `count` probability measures b_k on one support {x_i} (n points in R^d)
+ * and weights w_k >= 0 summing to 1.  Every measure gets its own sketch
+ * K~_k of K = exp(-C/eps) (C as selected by opts->cost, shared by all
+ * measures), sampled with p*_{k,ij} = min(1, s sqrt(b_kj) / (n sum_j
+ * sqrt(b_kj))) (the Spar-Sink probability with the barycenter replaced by its
+ * uniform start), mixed with the uniform s/n^2 by opts->shrink (Sec. 4;
+ * shrink = 1 is Rand-IBP), from hash stream k (problem index k of the
+ * Spar-Sink mask).  The loop is Alg. IBP in the order of the Bregman
+ * projections: for every k, v_k = b_k / K~_k' u_k; q = prod_k (K~_k v_k)^(w_k);
+ * for every k, u_k = q / K~_k v_k; q^0 = 1/n, u_k^0 = 1; a quotient with a
+ * zero denominator is 0.  It stops at the first t with |q^t - q^(t-1)|_1 <=
+ * opts->tol, or at opts->max_iter.
+ *
+ * x: device FP64 n*d row-major; b: device FP64 count*n (measure k at b + k n);
+ * w: host FP64 count entries.  1 <= count <= SS_IBP_MAX_MEASURES. */
+#define SS_IBP_MAX_MEASURES 64
+
+typedef struct ss_ibp_problem {
+    int64_t n;
+    int32_t d, count;
+    const double *x, *b;
+    const double *w;
+} ss_ibp_problem;
+
+/* Result of spar_ibp (host struct).
+ * err         |q^t - q^(t-1)|_1 at the returned t.   iters  that t.
+ * cmax        max_ij |x_i - x_j|^2.   nnz  entries over all sketches.
+ * empty_rows, empty_cols  lines of the sketches with no entry (summed over k).
+ * status      same as the return value.   t_*_ms  stage times on `stream`. */
+typedef struct ss_ibp_result {
+    double err, cmax;
+    int64_t nnz, empty_rows, empty_cols;
+    int32_t iters, status;
+    float t_sample_ms, t_iter_ms;
+} ss_ibp_result;
+
+/* Workspace bytes for spar_ibp and ss_ibp_sample.  Host-only. */
+int ss_ibp_workspace_size(const ss_ibp_problem *problem, const ss_options *opts, size_t *bytes);
+
+/* Alg. Spar-IBP.  Options used: eps, s, tol, seed, max_iter, precision
+ * (SS_F64, or SS_F32: FP32 stored K~ values, FP64 products, scalings and
+ * barycenter), cost, shrink, graph_iters, err_hist (max_iter FP64 entries:
+ * |q^t - q^(t-1)|_1), u_out and v_out (count*n FP64 each, measure-major: the
+ * returned u_k, v_k).  lambda must be +INFINITY; init_log_u/v must be NULL.
+ * q_out: device FP64, n entries, receives the returned q^t.
+ * Returns SS_OK, SS_NOT_CONVERGED (max_iter reached; result valid),
+ * SS_E_INVALID_ARG, SS_E_CAPACITY, SS_E_NONFINITE (q became NaN or Inf) or
+ * SS_E_HIP. */
+int spar_ibp(const ss_ibp_problem *problem, const ss_options *opts, double *q_out, void *ws,
+             size_t ws_bytes, void *stream, ss_ibp_result *result);
+
+/* The sketch of measure k alone (parity surface of eq. (pois-k)): mask,
+ * CSR, CSC and factors as in ss_sample, with row_fac_i = c and col_fac_j =
+ * sqrt(b_kj) such that p*_{k,ij} = min(1, c col_fac_j + s shrink / n^2).
+ * Synchronises `stream`. */
+int ss_ibp_sample(const ss_ibp_problem *problem, const ss_options *opts, int32_t k,
+                  ss_sparse *out, void *ws, size_t ws_bytes, void *stream);
+
 const char *ss_status_string(int status);
 const char *ss_last_error(void);
 int ss_version(void);

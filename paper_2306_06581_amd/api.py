@@ -419,3 +419,125 @@ class WarmStartNet:
         if rc < 0:
             raise N.SparSinkError(rc, "ss_warmstart_train_step")
         return (float(loss.value), grad) if want_grad else float(loss.value)
+
+
+# ---------------------------------------------------------------- Spar-IBP
+class IBPProblem:
+    """Device-resident inputs of one barycenter problem: support x (n, d),
+    measures b (count, n) and host weights w (count)."""
+
+    def __init__(self, x, b, w):
+        self.x = _dev(x)
+        self.b = _dev(b)
+        if self.x.dim() != 2:
+            raise ValueError("x must be (n, d)")
+        if self.b.dim() == 1:
+            self.b = self.b.reshape(1, -1)
+        if self.b.dim() != 2 or self.b.shape[1] != self.x.shape[0]:
+            raise ValueError("b must be (count, n)")
+        self.b = self.b.contiguous()
+        self.w = np.ascontiguousarray(w, dtype=np.float64)
+        if self.w.size != self.b.shape[0]:
+            raise ValueError("w must have one entry per measure")
+        self.c = N.SsIbpProblem(self.x.shape[0], self.x.shape[1], self.b.shape[0], _ptr(self.x),
+                                _ptr(self.b), self.w.ctypes.data)
+
+    @property
+    def n(self):
+        return int(self.x.shape[0])
+
+    @property
+    def count(self):
+        return int(self.b.shape[0])
+
+
+@dataclass
+class IBPResult:
+    status: int
+    q: torch.Tensor
+    err: float
+    cmax: float
+    nnz: int
+    empty_rows: int
+    empty_cols: int
+    iters: int
+    t_sample_ms: float
+    t_iter_ms: float
+    u: Optional[torch.Tensor] = None
+    v: Optional[torch.Tensor] = None
+    err_hist: Optional[torch.Tensor] = None
+
+
+def _ibp_options(eps, s, tol, max_iter, seed, precision, cost, shrink, graph_iters,
+                 u_out=None, v_out=None, err_hist=None) -> N.SsOptions:
+    return make_options(eps, s, math.inf, tol, max_iter, seed, precision, cost, "marginal",
+                        "auto", 0, graph_iters, None, None, u_out, v_out, err_hist, shrink)
+
+
+def ibp_workspace_size(prob: IBPProblem, opts: N.SsOptions) -> int:
+    out = ctypes.c_size_t(0)
+    rc = N.lib.ss_ibp_workspace_size(ctypes.byref(prob.c), ctypes.byref(opts), ctypes.byref(out))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_ibp_workspace_size")
+    return int(out.value)
+
+
+def spar_ibp(prob: IBPProblem, *, eps, s, tol=1e-6, max_iter=1000, seed=0, precision="f64",
+             cost="maxnorm", shrink=0.0, graph_iters=0, return_scalings=False, return_hist=False,
+             stream=None, raise_on_error=True) -> IBPResult:
+    """Alg. Spar-IBP: the barycenter q of the measures on the shared support."""
+    n, K = prob.n, prob.count
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    u_out = torch.empty((K, n), dtype=torch.float64, device="cuda") if return_scalings else None
+    v_out = torch.empty((K, n), dtype=torch.float64, device="cuda") if return_scalings else None
+    hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device="cuda") \
+        if return_hist else None
+    opts = _ibp_options(eps, s, tol, max_iter, seed, precision, cost, shrink, graph_iters, u_out,
+                        v_out, hist)
+    ws = workspace(ibp_workspace_size(prob, opts))
+    res = N.SsIbpResult()
+    rc = N.lib.spar_ibp(ctypes.byref(prob.c), ctypes.byref(opts), _ptr(q),
+                        ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                        _stream(stream), ctypes.byref(res))
+    if rc < 0 and raise_on_error:
+        raise N.SparSinkError(rc, "spar_ibp")
+    out = IBPResult(status=rc, q=q, **{k: getattr(res, k) for k, _ in N.SsIbpResult._fields_
+                                       if k != "status"})
+    out.u, out.v = u_out, v_out
+    if hist is not None:
+        out.err_hist = hist[: max(res.iters, 0)]
+    return out
+
+
+def ss_ibp_sample(prob: IBPProblem, k: int, *, eps, s, seed=0, precision="f64", cost="maxnorm",
+                  shrink=0.0, capacity: Optional[int] = None, stream=None) -> dict:
+    """eq. (pois-k): the sketch of measure k (mask, CSR, CSC, factors)."""
+    opts = _ibp_options(eps, s, 1e-6, 1, seed, precision, cost, shrink, 0)
+    ws = workspace(ibp_workspace_size(prob, opts))
+    n = prob.n
+    cap = capacity if capacity is not None else int(min(n * n, math.floor(s + 8 * math.sqrt(s) + 64)))
+    vdt = torch.float64 if precision == "f64" else torch.float32
+    out = {
+        "mask": torch.empty((n, (n + 63) // 64), dtype=torch.int64, device="cuda"),
+        "row_ptr": torch.empty(n + 1, dtype=torch.int64, device="cuda"),
+        "col_idx": torch.empty(cap, dtype=torch.int32, device="cuda"),
+        "val": torch.empty(cap, dtype=vdt, device="cuda"),
+        "col_ptr": torch.empty(n + 1, dtype=torch.int64, device="cuda"),
+        "row_idx": torch.empty(cap, dtype=torch.int32, device="cuda"),
+        "val_t": torch.empty(cap, dtype=vdt, device="cuda"),
+        "row_fac": torch.empty(n, dtype=torch.float64, device="cuda"),
+        "col_fac": torch.empty(n, dtype=torch.float64, device="cuda"),
+    }
+    sp = N.SsSparse(*[_ptr(out[key]) for key in ("mask", "row_ptr", "col_idx", "val", "col_ptr",
+                                                 "row_idx", "val_t", "row_fac", "col_fac")],
+                    cap, 0, 0.0, 0.0)
+    rc = N.lib.ss_ibp_sample(ctypes.byref(prob.c), ctypes.byref(opts), int(k), ctypes.byref(sp),
+                             ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                             _stream(stream))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_ibp_sample")
+    nnz = int(sp.nnz)
+    for key in ("col_idx", "val", "row_idx", "val_t"):
+        out[key] = out[key][:nnz]
+    out["nnz"], out["cmax"] = nnz, sp.cmax
+    return out

@@ -22,7 +22,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsparsink.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["sample.hip", "iterate.hip", "objective.hip", "dense.hip", "batch.hip", "mlp.hip", "api.cpp"]
+SOURCES = ["sample.hip", "iterate.hip", "objective.hip", "dense.hip", "batch.hip", "mlp.hip",
+           "ibp.hip", "api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1582,3 +1582,313 @@ int dense_sinkhorn(const ss_problem* P, const ss_options* O, void* ws, size_t ws
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- Spar-IBP
+namespace {
+
+struct IbpLayout {
+    size_t mask, maskT, row_cnt, col_cnt, scan, tmp, tree, stats, row_fac, col_fac;
+    size_t row_ptr, col_ptr, col_idx, row_idx, val, val_t;
+    size_t u, v[2], q[2], partials, state, empty;
+    int64_t cap;   // entries per measure (and the stride between measures)
+    int nb_rows;
+    size_t total;
+};
+
+IbpLayout ibp_plan(const ss_ibp_problem* P, const ss_options* O) {
+    IbpLayout L;
+    const int64_t n = P->n, K = P->count;
+    const int64_t W = (n + 63) / 64;
+    L.cap = entry_capacity(O->s, n, n);
+    L.nb_rows = ibp_row_blocks(n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t es = esize(O->precision);
+    L.mask = take((size_t)n * W * 8);
+    L.maskT = take((size_t)n * W * 8);
+    L.row_cnt = take((size_t)n * 4);
+    L.col_cnt = take((size_t)n * 4);
+    L.scan = take((size_t)((n + 1023) / 1024 + 1) * 8);
+    L.tmp = take(cmax_scratch_bytes(n) > (size_t)16 * n ? cmax_scratch_bytes(n) : (size_t)16 * n);
+    L.tree = take((size_t)(2 * ((n + 1023) / 1024) + 2) * 8);
+    L.stats = take(ST_COUNT * 8);
+    L.row_fac = take((size_t)n * 8);
+    L.col_fac = take((size_t)n * 8);
+    L.row_ptr = take((size_t)K * (n + 1) * 8);
+    L.col_ptr = take((size_t)K * (n + 1) * 8);
+    L.col_idx = take((size_t)K * L.cap * 4);
+    L.row_idx = take((size_t)K * L.cap * 4);
+    L.val = take((size_t)K * L.cap * es);
+    L.val_t = take((size_t)K * L.cap * es);
+    L.u = take((size_t)K * n * 8);
+    L.v[0] = take((size_t)K * n * 8);
+    L.v[1] = take((size_t)K * n * 8);
+    L.q[0] = take((size_t)n * 8);
+    L.q[1] = take((size_t)n * 8);
+    L.partials = take((size_t)L.nb_rows * 8);
+    L.state = take(sizeof(IterState));
+    L.empty = take(2 * sizeof(unsigned long long));
+    L.total = off;
+    return L;
+}
+
+int check_ibp(const ss_ibp_problem* P, const ss_options* O) {
+    if (!P || !O) return fail(SS_E_INVALID_ARG, "problem and options must not be NULL");
+    if (P->n <= 0 || P->n >= ((int64_t)1 << 31)) return fail(SS_E_INVALID_ARG, "n must be in [1, 2^31)");
+    if (P->d <= 0 || P->d > 64) return fail(SS_E_INVALID_ARG, "d must be in [1, 64]");
+    if (P->count < 1 || P->count > SS_IBP_MAX_MEASURES)
+        return fail(SS_E_INVALID_ARG, "count must be in [1, %d]", SS_IBP_MAX_MEASURES);
+    if (!P->x || !P->b || !P->w) return fail(SS_E_INVALID_ARG, "x, b, w must not be NULL");
+    double sw = 0.0;
+    for (int k = 0; k < P->count; ++k) {
+        if (!(P->w[k] >= 0.0) || !isfinite(P->w[k]))
+            return fail(SS_E_INVALID_ARG, "weight %d must be finite and >= 0", k);
+        sw += P->w[k];
+    }
+    if (fabs(sw - 1.0) > 1e-12) return fail(SS_E_INVALID_ARG, "weights must sum to 1 (%.17g)", sw);
+    if (!(O->eps > 0.0) || !isfinite(O->eps)) return fail(SS_E_INVALID_ARG, "eps must be > 0");
+    if (!(O->s > 0.0) || !isfinite(O->s))
+        return fail(SS_E_INVALID_ARG, "s must be a positive finite number");
+    if (!(O->tol >= 0.0)) return fail(SS_E_INVALID_ARG, "tol must be >= 0");
+    if (O->max_iter < 1) return fail(SS_E_INVALID_ARG, "max_iter must be >= 1");
+    if (O->precision != SS_F64 && O->precision != SS_F32)
+        return fail(SS_E_INVALID_ARG, "spar_ibp supports precision SS_F64 or SS_F32");
+    if (O->cost != SS_COST_SQEUCLID_MAXNORM && O->cost != SS_COST_SQEUCLID)
+        return fail(SS_E_INVALID_ARG, "unknown cost %d", O->cost);
+    if (isfinite(O->lambda)) return fail(SS_E_INVALID_ARG, "spar_ibp needs lambda = +INFINITY");
+    if (!(O->shrink >= 0.0 && O->shrink <= 1.0))
+        return fail(SS_E_INVALID_ARG, "shrink must be in [0, 1]");
+    if (O->init_log_u || O->init_log_v)
+        return fail(SS_E_INVALID_ARG, "spar_ibp takes no warm start");
+    return SS_OK;
+}
+
+struct IbpCtx {
+    const ss_ibp_problem* P;
+    const ss_options* O;
+    IbpLayout L;
+    void* ws;
+    hipStream_t st;
+    double stats[ST_COUNT];
+    double inv_cmax;
+    int64_t nnz;
+};
+
+int ibp_start(IbpCtx& c, const ss_ibp_problem* P, const ss_options* O, void* ws, size_t ws_bytes,
+              void* stream) {
+    int rc = check_ibp(P, O);
+    if (rc != SS_OK) return rc;
+    c.P = P;
+    c.O = O;
+    c.ws = ws;
+    c.st = (hipStream_t)stream;
+    c.L = ibp_plan(P, O);
+    c.nnz = 0;
+    if (!ws) return fail(SS_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(SS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < c.L.total)
+        return fail(SS_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, c.L.total);
+    double* stats = at<double>(ws, c.L.stats);
+    HIP_TRY(launch_fill_f64(stats, ST_COUNT, 0.0, c.st));
+    HIP_TRY(launch_fill_u32(at<uint32_t>(ws, c.L.state), sizeof(IterState) / 4, 0u, c.st));
+    HIP_TRY(launch_fill_u32(at<uint32_t>(ws, c.L.empty), 4, 0u, c.st));
+    HIP_TRY(launch_validate(P->b, (int64_t)P->count * P->n, P->x, P->n * P->d, stats, c.st));
+    HIP_TRY(launch_cmax(P->x, P->x, P->n, P->n, P->d, stats, at<void>(ws, c.L.tmp), c.st));
+    HIP_TRY(hipMemcpyAsync(c.stats, stats, sizeof(c.stats), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    if (c.stats[ST_BAD_INPUT] != 0.0)
+        return fail(SS_E_INVALID_ARG, "b must be finite and >= 0 and x finite");
+    const double cmax = c.stats[ST_CMAX];
+    c.inv_cmax = (O->cost == SS_COST_SQEUCLID_MAXNORM && cmax > 0.0) ? 1.0 / cmax : 1.0;
+    return SS_OK;
+}
+
+// eq. (pois-k): the sketch of measure k into its CSR / CSC region.
+int ibp_sample_one(IbpCtx& c, int k) {
+    const ss_ibp_problem* P = c.P;
+    const ss_options* O = c.O;
+    const int64_t n = P->n, W = (n + 63) / 64;
+    void* ws = c.ws;
+    hipStream_t st = c.st;
+    double* stats = at<double>(ws, c.L.stats);
+    ProbParams pp;
+    memset(&pp, 0, sizeof pp);
+    pp.uot = 0;
+    pp.s = O->s;
+    pp.eps = O->eps;
+    pp.inv_cmax = c.inv_cmax;
+    pp.shrink_w = 1.0 - O->shrink;
+    pp.shrink_c = O->s * O->shrink / ((double)n * (double)n);
+    pp.row_fac = at<double>(ws, c.L.row_fac);
+    pp.col_fac = at<double>(ws, c.L.col_fac);
+    pp.x = P->x;
+    pp.y = P->x;
+    pp.d = P->d;
+    pp.problem_index = (uint32_t)k;
+    pp.k0 = (uint32_t)(O->seed & 0xFFFFFFFFull);
+    pp.k1 = (uint32_t)(O->seed >> 32);
+    HIP_TRY(launch_ibp_prep(P->b + (int64_t)k * n, n, O->s, pp.shrink_w, (double*)pp.row_fac,
+                            (double*)pp.col_fac, at<double>(ws, c.L.tree), stats, st));
+    int32_t* row_cnt = at<int32_t>(ws, c.L.row_cnt);
+    int32_t* col_cnt = at<int32_t>(ws, c.L.col_cnt);
+    HIP_TRY(launch_fill_i32(row_cnt, n, 0, st));
+    HIP_TRY(launch_fill_i32(col_cnt, n, 0, st));
+    uint64_t* mask = at<uint64_t>(ws, c.L.mask);
+    uint64_t* maskT = at<uint64_t>(ws, c.L.maskT);
+    HIP_TRY(launch_mask(pp, n, n, mask, row_cnt, stats, st));
+    HIP_TRY(launch_transpose(mask, n, n, maskT, col_cnt, st));
+    int64_t* row_ptr = at<int64_t>(ws, c.L.row_ptr) + (int64_t)k * (n + 1);
+    int64_t* col_ptr = at<int64_t>(ws, c.L.col_ptr) + (int64_t)k * (n + 1);
+    HIP_TRY(launch_scan(row_cnt, n, row_ptr, at<int64_t>(ws, c.L.scan), st));
+    HIP_TRY(launch_scan(col_cnt, n, col_ptr, at<int64_t>(ws, c.L.scan), st));
+    int64_t tot[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&tot[0], row_ptr + n, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&tot[1], col_ptr + n, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (tot[0] != tot[1])
+        return fail(SS_E_HIP, "measure %d: CSR and CSC sizes differ (%lld vs %lld)", k,
+                    (long long)tot[0], (long long)tot[1]);
+    if (tot[0] > c.L.cap)
+        return fail(SS_E_CAPACITY, "measure %d: sampled %lld entries exceed the capacity %lld", k,
+                    (long long)tot[0], (long long)c.L.cap);
+    c.nnz += tot[0];
+    const size_t es = esize(O->precision);
+    const int64_t base = (int64_t)k * c.L.cap;
+    HIP_TRY(launch_fill_entries(0, O->precision, pp, stats, mask, n, W, row_ptr,
+                                at<int32_t>(ws, c.L.col_idx) + base,
+                                at<char>(ws, c.L.val) + (size_t)base * es, c.L.cap, st));
+    HIP_TRY(launch_fill_entries(1, O->precision, pp, stats, maskT, n, W, col_ptr,
+                                at<int32_t>(ws, c.L.row_idx) + base,
+                                at<char>(ws, c.L.val_t) + (size_t)base * es, c.L.cap, st));
+    unsigned long long* empty = at<unsigned long long>(ws, c.L.empty);
+    HIP_TRY(launch_ibp_empty(row_cnt, n, empty, st));
+    HIP_TRY(launch_ibp_empty(col_cnt, n, empty + 1, st));
+    return SS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_ibp_workspace_size(const ss_ibp_problem* problem, const ss_options* opts, size_t* bytes) {
+    int rc = check_ibp(problem, opts);
+    if (rc != SS_OK) return rc;
+    if (!bytes) return fail(SS_E_INVALID_ARG, "bytes must not be NULL");
+    *bytes = ibp_plan(problem, opts).total;
+    return SS_OK;
+}
+
+int ss_ibp_sample(const ss_ibp_problem* P, const ss_options* O, int32_t k, ss_sparse* out,
+                  void* ws, size_t ws_bytes, void* stream) {
+    if (!out) return fail(SS_E_INVALID_ARG, "out must not be NULL");
+    IbpCtx c;
+    int rc = ibp_start(c, P, O, ws, ws_bytes, stream);
+    if (rc != SS_OK) return rc;
+    if (k < 0 || k >= P->count) return fail(SS_E_INVALID_ARG, "k must be in [0, count)");
+    rc = ibp_sample_one(c, k);
+    if (rc != SS_OK) return rc;
+    const int64_t n = P->n, W = (n + 63) / 64;
+    const bool wants_entries = out->col_idx || out->val || out->row_idx || out->val_t;
+    if (wants_entries && out->capacity < c.nnz)
+        return fail(SS_E_CAPACITY, "out->capacity %lld < nnz %lld", (long long)out->capacity,
+                    (long long)c.nnz);
+    const size_t es = esize(O->precision);
+    const int64_t base = (int64_t)k * c.L.cap;
+    auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        if (!dst || bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.st);
+    };
+    HIP_TRY(cp(out->mask, at<char>(ws, c.L.mask), (size_t)n * W * 8));
+    HIP_TRY(cp(out->row_ptr, at<int64_t>(ws, c.L.row_ptr) + (int64_t)k * (n + 1), (size_t)(n + 1) * 8));
+    HIP_TRY(cp(out->col_idx, at<int32_t>(ws, c.L.col_idx) + base, (size_t)c.nnz * 4));
+    HIP_TRY(cp(out->val, at<char>(ws, c.L.val) + (size_t)base * es, (size_t)c.nnz * es));
+    HIP_TRY(cp(out->col_ptr, at<int64_t>(ws, c.L.col_ptr) + (int64_t)k * (n + 1), (size_t)(n + 1) * 8));
+    HIP_TRY(cp(out->row_idx, at<int32_t>(ws, c.L.row_idx) + base, (size_t)c.nnz * 4));
+    HIP_TRY(cp(out->val_t, at<char>(ws, c.L.val_t) + (size_t)base * es, (size_t)c.nnz * es));
+    HIP_TRY(cp(out->row_fac, at<double>(ws, c.L.row_fac), (size_t)n * 8));
+    HIP_TRY(cp(out->col_fac, at<double>(ws, c.L.col_fac), (size_t)n * 8));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    out->nnz = c.nnz;
+    out->cmax = c.stats[ST_CMAX];
+    out->z_norm = 0.0;
+    return SS_OK;
+}
+
+int spar_ibp(const ss_ibp_problem* P, const ss_options* O, double* q_out, void* ws,
+             size_t ws_bytes, void* stream, ss_ibp_result* R) {
+    if (!R) return fail(SS_E_INVALID_ARG, "result must not be NULL");
+    if (!q_out) return fail(SS_E_INVALID_ARG, "q_out must not be NULL");
+    IbpCtx c;
+    int rc = ibp_start(c, P, O, ws, ws_bytes, stream);
+    if (rc != SS_OK) return rc;
+    memset(R, 0, sizeof *R);
+    Timer tm;
+    tm.mark(0, c.st);
+    for (int k = 0; k < P->count; ++k) {
+        rc = ibp_sample_one(c, k);
+        if (rc != SS_OK) return rc;
+    }
+    tm.mark(1, c.st);
+    const int64_t n = P->n, K = P->count;
+    IbpArgs A;
+    memset(&A, 0, sizeof A);
+    A.n = n;
+    A.count = P->count;
+    A.nb_rows = c.L.nb_rows;
+    A.cap = c.L.cap;
+    A.row_ptr = at<int64_t>(ws, c.L.row_ptr);
+    A.col_idx = at<int32_t>(ws, c.L.col_idx);
+    A.val = at<void>(ws, c.L.val);
+    A.col_ptr = at<int64_t>(ws, c.L.col_ptr);
+    A.row_idx = at<int32_t>(ws, c.L.row_idx);
+    A.val_t = at<void>(ws, c.L.val_t);
+    A.b = P->b;
+    A.u = at<double>(ws, c.L.u);
+    A.v[0] = at<double>(ws, c.L.v[0]);
+    A.v[1] = at<double>(ws, c.L.v[1]);
+    A.q[0] = at<double>(ws, c.L.q[0]);
+    A.q[1] = at<double>(ws, c.L.q[1]);
+    A.partials = at<double>(ws, c.L.partials);
+    A.st = at<IterState>(ws, c.L.state);
+    A.err_hist = O->err_hist;
+    A.max_iter = O->max_iter;
+    A.tol = O->tol;
+    for (int k = 0; k < P->count; ++k) A.w[k] = P->w[k];
+    HIP_TRY(launch_ibp_init(A.u, K * n, A.q[0], n, c.st));
+    const int prec = O->precision == SS_F64 ? P_F64 : P_F32;
+    auto iter = [&](int, hipStream_t s) -> hipError_t { return launch_ibp_iteration(prec, A, s); };
+    const int G = O->graph_iters == 0 ? 16 : O->graph_iters;
+    IterState hs;
+    memset(&hs, 0, sizeof hs);
+    rc = run_loop(iter, G, O->max_iter, A.st, &hs, c.st);
+    if (rc != SS_OK) return rc;
+    tm.mark(2, c.st);
+    if (hs.nonfinite) return fail(SS_E_NONFINITE, "the barycenter became NaN or Inf");
+    if (hs.stop_iter <= 0) return fail(SS_E_HIP, "loop ended without a result");
+    const int p = hs.stop_iter & 1;
+    HIP_TRY(hipMemcpyAsync(q_out, A.q[p], (size_t)n * 8, hipMemcpyDeviceToDevice, c.st));
+    if (O->u_out)
+        HIP_TRY(hipMemcpyAsync(O->u_out, A.u, (size_t)K * n * 8, hipMemcpyDeviceToDevice, c.st));
+    if (O->v_out)
+        HIP_TRY(hipMemcpyAsync(O->v_out, A.v[p], (size_t)K * n * 8, hipMemcpyDeviceToDevice, c.st));
+    unsigned long long empty[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(empty, at<unsigned long long>(ws, c.L.empty), sizeof empty,
+                           hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    R->err = hs.err_final;
+    R->cmax = c.stats[ST_CMAX];
+    R->nnz = c.nnz;
+    R->empty_rows = (int64_t)empty[0];
+    R->empty_cols = (int64_t)empty[1];
+    R->iters = hs.stop_iter;
+    R->t_sample_ms = tm.ms(0, 1);
+    R->t_iter_ms = tm.ms(1, 2);
+    R->status = hs.err_final <= O->tol ? SS_OK : SS_NOT_CONVERGED;
+    return R->status;
+}
+
+}  // extern "C"

@@ -72,6 +72,49 @@ struct ProbParams {
 
 struct Workspace;
 
+// ---- ibp.hip (Spar-IBP)
+constexpr int kIbpMaxMeasures = 64;
+
+// Arguments of the two launches of one Spar-IBP step.  Measure k's sketch
+// holds its entries at [k * cap, k * cap + nnz_k) of the entry arrays, its
+// row (column) offsets at row_ptr + k (n + 1) (col_ptr + k (n + 1)), relative
+// to k * cap.  Vectors of all measures are laid out measure-major (k * n + i).
+// Protocol (IterState fields reused): a column launch runs step
+// t = cnt_u + 1, its block 0 first closes step t - 1 (error, history, stop)
+// and sets cnt_v = t; a row launch runs step cnt_v and its block 0 sets
+// cnt_u.  No launch reads a field its own grid writes, except stop_iter and
+// nonfinite, whose early sight only skips work that is no longer needed.
+struct IbpArgs {
+    int64_t n;
+    int32_t count;
+    int32_t nb_rows;          // grid of the row launch = number of partials
+    int64_t cap;              // entry stride between measures
+    const int64_t* row_ptr;   // count x (n + 1)
+    const int32_t* col_idx;
+    const void* val;          // FP64 or FP32
+    const int64_t* col_ptr;
+    const int32_t* row_idx;
+    const void* val_t;
+    const double* b;          // count x n
+    double* u;                // count x n
+    double* v[2];             // count x n, by step parity
+    double* q[2];             // n, by step parity (q[0] starts as 1/n)
+    double* partials;         // nb_rows
+    IterState* st;
+    double* err_hist;
+    int32_t max_iter;
+    double tol;
+    double w[kIbpMaxMeasures];
+};
+
+hipError_t launch_ibp_prep(const double* b, int64_t n, double s, double shrink_w, double* row_fac,
+                           double* col_fac, double* scratch, double* stats, hipStream_t st);
+hipError_t launch_ibp_empty(const int32_t* cnt, int64_t n, unsigned long long* out,
+                            hipStream_t st);
+hipError_t launch_ibp_init(double* u, int64_t nu, double* q0, int64_t n, hipStream_t st);
+int ibp_row_blocks(int64_t n);
+hipError_t launch_ibp_iteration(int precision, const IbpArgs& A, hipStream_t st);
+
 // ---- sample.hip
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);

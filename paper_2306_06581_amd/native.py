@@ -83,6 +83,20 @@ class SsMlp(ctypes.Structure):
                 ("adam_v", c_void_p), ("step", c_int32), ("reserved", c_int32)]
 
 
+class SsIbpProblem(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("d", c_int32), ("count", c_int32), ("x", c_void_p),
+                ("b", c_void_p), ("w", c_void_p)]
+
+
+class SsIbpResult(ctypes.Structure):
+    _fields_ = [("err", c_double), ("cmax", c_double), ("nnz", c_int64),
+                ("empty_rows", c_int64), ("empty_cols", c_int64), ("iters", c_int32),
+                ("status", c_int32), ("t_sample_ms", c_float), ("t_iter_ms", c_float)]
+
+
+IBP_MAX_MEASURES = 64
+
+
 # Every symbol the header declares, with its signature.
 SIGNATURES = {
     "ss_workspace_size": (c_int, [POINTER(SsProblem), POINTER(SsOptions), POINTER(c_size_t)]),
@@ -109,6 +123,12 @@ SIGNATURES = {
     "ss_warmstart_train_step": (c_int, [POINTER(SsMlp), POINTER(SsBatch), c_double, c_int32,
                                         c_void_p, c_void_p, c_float, c_void_p, c_size_t, c_void_p,
                                         POINTER(c_float), c_void_p]),
+    "ss_ibp_workspace_size": (c_int, [POINTER(SsIbpProblem), POINTER(SsOptions),
+                                      POINTER(c_size_t)]),
+    "spar_ibp": (c_int, [POINTER(SsIbpProblem), POINTER(SsOptions), c_void_p, c_void_p, c_size_t,
+                         c_void_p, POINTER(SsIbpResult)]),
+    "ss_ibp_sample": (c_int, [POINTER(SsIbpProblem), POINTER(SsOptions), c_int32,
+                              POINTER(SsSparse), c_void_p, c_size_t, c_void_p]),
     "ss_status_string": (c_char_p, [c_int]),
     "ss_last_error": (c_char_p, []),
     "ss_version": (c_int, []),

@@ -53,7 +53,9 @@ int main(void) {
   P(ss_batch, s) P(ss_batch, x) P(ss_batch, b) P(ss_schedule, block_threads)
   P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist) P(ss_options, shrink)
   P(ss_result, nnz) P(ss_result, iters) P(ss_result, t_obj_ms) P(ss_sparse, capacity)
-  P(ss_sparse, z_norm)
+  P(ss_sparse, z_norm) P(ss_ibp_problem, x) P(ss_ibp_problem, w) P(ss_ibp_result, nnz)
+  P(ss_ibp_result, t_iter_ms)
+  printf("ss_ibp_problem %zu\nss_ibp_result %zu\n", sizeof(ss_ibp_problem), sizeof(ss_ibp_result));
   return 0;
 }
 """
@@ -89,6 +91,12 @@ def test_struct_layout_matches_header():
     assert N.SsBatch.x.offset == lay["ss_batch.x"]
     assert N.SsBatch.b.offset == lay["ss_batch.b"]
     assert N.SsSchedule.block_threads.offset == lay["ss_schedule.block_threads"]
+    assert ctypes.sizeof(N.SsIbpProblem) == lay["ss_ibp_problem"]
+    assert ctypes.sizeof(N.SsIbpResult) == lay["ss_ibp_result"]
+    assert N.SsIbpProblem.x.offset == lay["ss_ibp_problem.x"]
+    assert N.SsIbpProblem.w.offset == lay["ss_ibp_problem.w"]
+    assert N.SsIbpResult.nnz.offset == lay["ss_ibp_result.nnz"]
+    assert N.SsIbpResult.t_iter_ms.offset == lay["ss_ibp_result.t_iter_ms"]
 
 
 def _fake_problem(N, n=8, m=8, d=2):
@@ -238,3 +246,54 @@ def test_batch_workspace_and_schedule_checks():
     bad = N.SsSchedule(8, 128)
     assert N.lib.spar_sink_batched(ctypes.byref(b), ctypes.byref(opts), ctypes.byref(bad),
                                    ctypes.c_void_p(4096), 1 << 40, None, res) == N.SS_E_INVALID_ARG
+
+
+def _ibp_problem(N, n=8, d=2, count=2, w=(0.5, 0.5)):
+    warr = (ctypes.c_double * len(w))(*w)
+    prob = N.SsIbpProblem(n, d, count, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                          ctypes.cast(warr, ctypes.c_void_p))
+    return prob, warr
+
+
+@pytest.mark.parametrize("change", ["count0", "count65", "wsum", "wneg", "lam", "log", "shrink",
+                                    "n0", "d0", "warm"])
+def test_ibp_arguments_rejected(change):
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd import api as A
+    kw = dict(n=8, d=2, count=2, w=(0.5, 0.5))
+    opt = dict(eps=0.1, s=10.0)
+    if change == "count0":
+        kw.update(count=0, w=(1.0,))
+    elif change == "count65":
+        kw.update(count=65, w=(1.0 / 65,) * 65)
+    elif change == "wsum":
+        kw.update(w=(0.5, 0.6))
+    elif change == "wneg":
+        kw.update(w=(1.5, -0.5))
+    elif change == "n0":
+        kw.update(n=0)
+    elif change == "d0":
+        kw.update(d=0)
+    prob, keep = _ibp_problem(N, **kw)
+    o = A.make_options(lam=1.0 if change == "lam" else math.inf,
+                       precision="f32_log" if change == "log" else "f64",
+                       shrink=1.5 if change == "shrink" else 0.0, **opt)
+    if change == "warm":
+        o.init_log_u = ctypes.c_void_p(16)
+    out = ctypes.c_size_t(0)
+    rc = N.lib.ss_ibp_workspace_size(ctypes.byref(prob), ctypes.byref(o), ctypes.byref(out))
+    assert rc == -1, change
+
+
+def test_ibp_workspace_grows_with_measures():
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd import api as A
+    sizes = []
+    for count in (1, 2, 4):
+        prob, keep = _ibp_problem(N, n=1000, count=count, w=(1.0 / count,) * count)
+        out = ctypes.c_size_t(0)
+        rc = N.lib.ss_ibp_workspace_size(ctypes.byref(prob), ctypes.byref(A.make_options(eps=0.1, s=5e4)),
+                                         ctypes.byref(out))
+        assert rc == 0
+        sizes.append(out.value)
+    assert sizes[0] < sizes[1] < sizes[2]
