@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--warmstart-train", type=int, default=100_000,
                     help="training problems for the learned warm start (0: skip)")
     ap.add_argument("--warmstart-only", action="store_true")
+    ap.add_argument("--no-ibp", action="store_true")
+    ap.add_argument("--ibp-only", action="store_true", help="only the Spar-IBP workload")
+    ap.add_argument("--ibp-n", type=int, default=16384)
     return ap.parse_args()
 
 
@@ -198,6 +201,60 @@ def warmstart_bench(ntrain: int, count: int) -> dict:
     return ev
 
 
+def ibp_step_bytes(nnz: int, n: int, count: int, precision: str) -> float:
+    """Algorithmic HBM bytes of one Spar-IBP step (column launch + row launch).
+
+    Per stored entry, in both directions: its value and a 4-byte index.  Per
+    measure and line: the two int64 offsets (CSR and CSC), b_k read, v_k and u_k
+    written, and the gathered u_k and v_k counted once (they stay in cache).
+    Per step: the barycenter read and written."""
+    ev = 8 if precision == "f64" else 4
+    return 2.0 * nnz * (ev + 4) + count * (2 * 8 * (n + 1) + 3 * 8 * n + 2 * 8 * n) + 2 * 8 * n
+
+
+def ibp_bench(n: int, steps: int, cpu: bool) -> dict:
+    """Spar-IBP (barycenter of three measures, the paper's barycenter
+    simulation scaled up): n support points in (0,1)^5, eps = 0.05 on the
+    normalised cost, s = 20 s0(n) per measure, FP32 stored values, stop at
+    |q^t - q^(t-1)|_1 <= 1e-8.  Also the paper's own size n = 1000."""
+    import torch
+
+    from paper_2306_06581_amd import api as A
+    from paper_2306_06581_amd import workloads as W
+
+    out = {}
+    for nn in (n, 1000):
+        p = W.ibp_synthetic(nn, d=5, seed=0, eps=0.05, s_factor=20.0)
+        prob = A.IBPProblem(p.x, p.b, p.w)
+        kw = dict(eps=p.eps, s=p.s, seed=p.seed, tol=1e-8, max_iter=5000, precision="f32")
+        A.spar_ibp(prob, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [A.spar_ibp(prob, **kw) for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        r = res[-1]
+        ms_it, nnz = A.ss_ibp_time_iterations(prob, 64, eps=p.eps, s=p.s, seed=p.seed,
+                                              precision="f32")
+        by = ibp_step_bytes(nnz, nn, p.count, "f32")
+        gbps = by / (ms_it * 1e-3) / 1e9
+        out[f"n{nn}"] = {
+            "workload": f"ibp_synthetic n={nn} d=5 3 measures eps=0.05 s=20 s0(n) f32 tol=1e-8",
+            "ms_per_solve": ms, "iters": r.iters, "status": r.status, "err": r.err,
+            "nnz": r.nnz, "stage_ms": {"sample": r.t_sample_ms, "iterate": r.t_iter_ms},
+            "ms_per_step": ms_it, "bytes_per_step": by, "step_GBps": gbps,
+            "step_frac_of_8TBps": gbps / HBM_PEAK_GBPS}
+        if cpu and nn == 1000:
+            from oracle import ibp_oracle as I
+            t0 = time.perf_counter()
+            o = I.spar_ibp(p.x, p.b, p.w, p.eps, p.s, seed=p.seed, tol=1e-8, max_iter=5000)
+            out[f"n{nn}"]["cpu_oracle"] = {"s": time.perf_counter() - t0, "iters": o.ibp.iters,
+                                           "cores": 1, "kind": "oracle",
+                                           "l1_vs_gpu": float(np.abs(o.ibp.q -
+                                                                     r.q.cpu().numpy()).sum())}
+    return out
+
+
 def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
     """The FP64 oracle timed on a bounded sample of the same workload."""
     import numpy as np
@@ -259,6 +316,11 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"batched": batched_bench(args.batch_count, args.steps)}))
+        return
+    if args.ibp_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"ibp": ibp_bench(args.ibp_n, args.steps, not args.no_cpu)}))
         return
     if args.warmstart_only:
         import torch
@@ -360,6 +422,8 @@ def main():
         out["batched"] = batched_bench(args.batch_count, args.steps)
     if args.warmstart_train > 0:
         out["warmstart"] = warmstart_bench(args.warmstart_train, args.batch_count)
+    if not args.no_ibp:
+        out["ibp"] = ibp_bench(args.ibp_n, args.steps, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, r.iters, args.precision == "f32_log")
     print(json.dumps(out))

@@ -383,6 +383,16 @@ int spar_ibp(const ss_ibp_problem *problem, const ss_options *opts, double *q_ou
 int ss_ibp_sample(const ss_ibp_problem *problem, const ss_options *opts, int32_t k,
                   ss_sparse *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Measurement hook for the Spar-IBP loop: samples the sketches like
+ * spar_ibp, then runs exactly `iters` (>= 1) steps with tol ignored as one
+ * captured HIP graph: one warm-up replay, one replay between two HIP events on
+ * `stream`.  *ms_per_iter (host) receives the mean duration of one step (its
+ * column launch and its row launch); *nnz (host, may be NULL) the entries
+ * over all sketches. */
+int ss_ibp_time_iterations(const ss_ibp_problem *problem, const ss_options *opts, void *ws,
+                           size_t ws_bytes, void *stream, int32_t iters, double *ms_per_iter,
+                           int64_t *nnz);
+
 const char *ss_status_string(int status);
 const char *ss_last_error(void);
 int ss_version(void);

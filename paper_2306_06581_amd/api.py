@@ -541,3 +541,19 @@ def ss_ibp_sample(prob: IBPProblem, k: int, *, eps, s, seed=0, precision="f64", 
         out[key] = out[key][:nnz]
     out["nnz"], out["cmax"] = nnz, sp.cmax
     return out
+
+
+def ss_ibp_time_iterations(prob: IBPProblem, iters: int = 64, *, eps, s, seed=0, precision="f64",
+                           cost="maxnorm", shrink=0.0, stream=None) -> tuple:
+    """(mean ms of one Spar-IBP step over `iters` graph-replayed steps, nnz)."""
+    opts = _ibp_options(eps, s, 0.0, iters, seed, precision, cost, shrink, 0)
+    ws = workspace(ibp_workspace_size(prob, opts))
+    ms = ctypes.c_double(0.0)
+    nnz = ctypes.c_int64(0)
+    rc = N.lib.ss_ibp_time_iterations(ctypes.byref(prob.c), ctypes.byref(opts),
+                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                      _stream(stream), int(iters), ctypes.byref(ms),
+                                      ctypes.byref(nnz))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_ibp_time_iterations")
+    return float(ms.value), int(nnz.value)

@@ -1770,6 +1770,35 @@ int ibp_sample_one(IbpCtx& c, int k) {
     return SS_OK;
 }
 
+IbpArgs ibp_args(const IbpCtx& c) {
+    IbpArgs A;
+    memset(&A, 0, sizeof A);
+    void* ws = c.ws;
+    A.n = c.P->n;
+    A.count = c.P->count;
+    A.nb_rows = c.L.nb_rows;
+    A.cap = c.L.cap;
+    A.row_ptr = at<int64_t>(ws, c.L.row_ptr);
+    A.col_idx = at<int32_t>(ws, c.L.col_idx);
+    A.val = at<void>(ws, c.L.val);
+    A.col_ptr = at<int64_t>(ws, c.L.col_ptr);
+    A.row_idx = at<int32_t>(ws, c.L.row_idx);
+    A.val_t = at<void>(ws, c.L.val_t);
+    A.b = c.P->b;
+    A.u = at<double>(ws, c.L.u);
+    A.v[0] = at<double>(ws, c.L.v[0]);
+    A.v[1] = at<double>(ws, c.L.v[1]);
+    A.q[0] = at<double>(ws, c.L.q[0]);
+    A.q[1] = at<double>(ws, c.L.q[1]);
+    A.partials = at<double>(ws, c.L.partials);
+    A.st = at<IterState>(ws, c.L.state);
+    A.err_hist = c.O->err_hist;
+    A.max_iter = c.O->max_iter;
+    A.tol = c.O->tol;
+    for (int k = 0; k < c.P->count; ++k) A.w[k] = c.P->w[k];
+    return A;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1834,30 +1863,7 @@ int spar_ibp(const ss_ibp_problem* P, const ss_options* O, double* q_out, void* 
     }
     tm.mark(1, c.st);
     const int64_t n = P->n, K = P->count;
-    IbpArgs A;
-    memset(&A, 0, sizeof A);
-    A.n = n;
-    A.count = P->count;
-    A.nb_rows = c.L.nb_rows;
-    A.cap = c.L.cap;
-    A.row_ptr = at<int64_t>(ws, c.L.row_ptr);
-    A.col_idx = at<int32_t>(ws, c.L.col_idx);
-    A.val = at<void>(ws, c.L.val);
-    A.col_ptr = at<int64_t>(ws, c.L.col_ptr);
-    A.row_idx = at<int32_t>(ws, c.L.row_idx);
-    A.val_t = at<void>(ws, c.L.val_t);
-    A.b = P->b;
-    A.u = at<double>(ws, c.L.u);
-    A.v[0] = at<double>(ws, c.L.v[0]);
-    A.v[1] = at<double>(ws, c.L.v[1]);
-    A.q[0] = at<double>(ws, c.L.q[0]);
-    A.q[1] = at<double>(ws, c.L.q[1]);
-    A.partials = at<double>(ws, c.L.partials);
-    A.st = at<IterState>(ws, c.L.state);
-    A.err_hist = O->err_hist;
-    A.max_iter = O->max_iter;
-    A.tol = O->tol;
-    for (int k = 0; k < P->count; ++k) A.w[k] = P->w[k];
+    IbpArgs A = ibp_args(c);
     HIP_TRY(launch_ibp_init(A.u, K * n, A.q[0], n, c.st));
     const int prec = O->precision == SS_F64 ? P_F64 : P_F32;
     auto iter = [&](int, hipStream_t s) -> hipError_t { return launch_ibp_iteration(prec, A, s); };
@@ -1889,6 +1895,59 @@ int spar_ibp(const ss_ibp_problem* P, const ss_options* O, double* q_out, void* 
     R->t_iter_ms = tm.ms(1, 2);
     R->status = hs.err_final <= O->tol ? SS_OK : SS_NOT_CONVERGED;
     return R->status;
+}
+
+int ss_ibp_time_iterations(const ss_ibp_problem* P, const ss_options* O, void* ws,
+                           size_t ws_bytes, void* stream, int32_t iters, double* ms_per_iter,
+                           int64_t* nnz) {
+    if (iters < 1) return fail(SS_E_INVALID_ARG, "iters must be >= 1");
+    if (!ms_per_iter) return fail(SS_E_INVALID_ARG, "ms_per_iter must not be NULL");
+    IbpCtx c;
+    int rc = ibp_start(c, P, O, ws, ws_bytes, stream);
+    if (rc != SS_OK) return rc;
+    for (int k = 0; k < P->count; ++k) {
+        rc = ibp_sample_one(c, k);
+        if (rc != SS_OK) return rc;
+    }
+    if (nnz) *nnz = c.nnz;
+    IbpArgs A = ibp_args(c);
+    A.tol = 0.0;
+    A.max_iter = iters;
+    A.err_hist = nullptr;
+    const int prec = O->precision == SS_F64 ? P_F64 : P_F32;
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < iters && e == hipSuccess; ++k) e = launch_ibp_iteration(prec, A, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        e = launch_fill_u32((uint32_t*)A.st, sizeof(IterState) / 4, 0u, c.st);
+        if (e == hipSuccess) e = launch_ibp_init(A.u, (int64_t)P->count * P->n, A.q[0], P->n, c.st);
+        if (e == hipSuccess && rep == 1) e = hipEventRecord(a, c.st);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, c.st);
+        if (e == hipSuccess && rep == 1) e = hipEventRecord(b, c.st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+    }
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(SS_E_HIP, "timing graph failed: %s", hipGetErrorString(e));
+    IterState hs;
+    HIP_TRY(hipMemcpy(&hs, A.st, sizeof hs, hipMemcpyDeviceToHost));
+    if (hs.nonfinite) return fail(SS_E_NONFINITE, "the barycenter became NaN or Inf");
+    *ms_per_iter = (double)ms / (double)iters;
+    return SS_OK;
 }
 
 }  // extern "C"

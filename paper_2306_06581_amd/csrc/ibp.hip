@@ -94,15 +94,28 @@ hipError_t launch_ibp_init(double* u, int64_t nu, double* q0, int64_t n, hipStre
     return hipGetLastError();
 }
 
-// Sum of line `line` of a CSR/CSC held at entries [lo, hi) + base: the 16
-// lanes of a group stride the entries; every lane returns the group's total.
+// Dot product of one CSR/CSC line (entries [lo, hi) + base) with the
+// gathered vector x: the 16 lanes of a group stride the entries, four
+// independent loads per lane in flight, four partial sums per lane added in a
+// fixed order, then the xor tree over the lanes; every lane returns the total.
 template <typename V>
 __device__ __forceinline__ double line_dot(const V* __restrict__ val, const int32_t* __restrict__ idx,
                                            int64_t base, int64_t lo, int64_t hi,
                                            const double* __restrict__ x, int lane16) {
-    double acc = 0.0;
-    for (int64_t e = lo + lane16; e < hi; e += 16) acc += (double)val[base + e] * x[idx[base + e]];
-    return group_sum<16>(acc);
+    const V* __restrict__ pv = val + base;
+    const int32_t* __restrict__ pi = idx + base;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t e = lo + lane16;
+    for (; e + 48 < hi; e += 64) {
+        const int32_t i0 = pi[e], i1 = pi[e + 16], i2 = pi[e + 32], i3 = pi[e + 48];
+        const V v0 = pv[e], v1 = pv[e + 16], v2 = pv[e + 32], v3 = pv[e + 48];
+        a0 += (double)v0 * x[i0];
+        a1 += (double)v1 * x[i1];
+        a2 += (double)v2 * x[i2];
+        a3 += (double)v3 * x[i3];
+    }
+    for (; e < hi; e += 16) a0 += (double)pv[e] * x[pi[e]];
+    return group_sum<16>((a0 + a1) + (a2 + a3));
 }
 
 // Block 0 of a column launch closes the previous step: err(t-1) from the row

@@ -129,6 +129,9 @@ SIGNATURES = {
                          c_void_p, POINTER(SsIbpResult)]),
     "ss_ibp_sample": (c_int, [POINTER(SsIbpProblem), POINTER(SsOptions), c_int32,
                               POINTER(SsSparse), c_void_p, c_size_t, c_void_p]),
+    "ss_ibp_time_iterations": (c_int, [POINTER(SsIbpProblem), POINTER(SsOptions), c_void_p,
+                                       c_size_t, c_void_p, c_int32, POINTER(c_double),
+                                       POINTER(c_int64)]),
     "ss_status_string": (c_char_p, [c_int]),
     "ss_last_error": (c_char_p, []),
     "ss_version": (c_int, []),
