@@ -182,6 +182,8 @@ class Options:
     # probability (Sec. 4, shrinkage: p = (1 - g) p + g / (nm)); g = 1 is the
     # equal-probability subsampling of Sec. 5 (Rand-Sink)
     shrink: float = 0.0
+    # eta of the Wasserstein-Fisher-Rao cost (cost="wfr")
+    eta: float = 1.0
 
 
 class EmptySupportError(RuntimeError):
@@ -193,11 +195,31 @@ def is_uot(opt: Options) -> bool:
 
 
 def cost_scale(x, y, opt: Options) -> tuple[float, float]:
-    """(cmax, inv_cmax) -- C_ij = c_ij * inv_cmax."""
+    """(cmax, inv_cmax) -- C_ij = c_ij * inv_cmax for the squared Euclidean
+    costs (cmax is reported for every cost)."""
     cmax = max_sq_dist(x, y)
     if opt.cost == "maxnorm":
         return cmax, (1.0 / cmax if cmax > 0 else 1.0)
     return cmax, 1.0
+
+
+HALF_PI = math.pi / 2
+
+
+def cost_from_sq(c, kind: str, inv_cmax: float, eta: float):
+    """C from squared Euclidean distances c.  "maxnorm" / "plain": c * inv_cmax.
+    "wfr": the Wasserstein-Fisher-Rao cost of the UOT background section,
+    C = -log cos_+^2(d / (2 eta)) with the Euclidean distance d = sqrt(c) and
+    cos_+(z) = cos(min(z, pi/2)); written -2 log cos(z) with
+    z = sqrt(c) * (0.5 / eta), and +inf (K = 0) where z >= pi/2, which the
+    section states for d >= pi eta."""
+    if kind != "wfr":
+        return c * inv_cmax
+    z = np.sqrt(c) * (0.5 / eta)
+    inside = z < HALF_PI
+    out = np.full(np.shape(z), np.inf)
+    out[inside] = -2.0 * np.log(np.cos(z[inside]))
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -242,9 +264,12 @@ class ProbUOT:
     x: np.ndarray
     y: np.ndarray
     c0: float = 0.0     # s g / (nm)
+    cost: str = "maxnorm"
+    eta: float = 1.0
 
     def q(self, rows, cols):
-        cij = sq_dist(self.x[rows], self.y[cols]) * self.inv_cmax
+        cij = cost_from_sq(sq_dist(self.x[rows], self.y[cols]), self.cost, self.inv_cmax,
+                           self.eta)
         with np.errstate(invalid="ignore"):
             e = (self.la[rows][:, None] + self.lb[cols][None, :]) - cij * self.inv_tau
         return np.exp(e)
@@ -254,7 +279,8 @@ class ProbUOT:
 
 
 def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256,
-                      shrink: float = 0.0, workers: int = 1) -> ProbUOT:
+                      shrink: float = 0.0, workers: int = 1, cost: str = "maxnorm",
+                      eta: float = 1.0) -> ProbUOT:
     """eq. (pij-uot) with K^(eps/(2lam+eps)) written as exp(-C/(2lam+eps)),
     mixed with the uniform probability with weight `shrink`."""
     tau = 2.0 * lam + eps
@@ -263,7 +289,7 @@ def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256,
         la = th * np.log(np.asarray(a, dtype=np.float64))
         lb = th * np.log(np.asarray(b, dtype=np.float64))
     pr = ProbUOT(la=la, lb=lb, inv_tau=1.0 / tau, inv_cmax=inv_cmax, z=0.0, kappa=0.0,
-                 x=np.asarray(x, np.float64), y=np.asarray(y, np.float64))
+                 x=np.asarray(x, np.float64), y=np.asarray(y, np.float64), cost=cost, eta=eta)
     cols = np.arange(len(b))
     rowsums = _map_chunks(
         lambda r0: pr.q(np.arange(r0, min(len(a), r0 + chunk)), cols).sum(axis=1),
@@ -335,7 +361,7 @@ def build_sketch(x, y, a, b, opt: Options, chunk: int = 256, prob=None) -> Sketc
         pass
     elif is_uot(opt):
         prob = uot_probabilities(a, b, x, y, opt.s, opt.lam, opt.eps, inv_cmax,
-                                 shrink=opt.shrink)
+                                 shrink=opt.shrink, cost=opt.cost, eta=opt.eta)
     else:
         prob = ot_probabilities(a, b, opt.s, shrink=opt.shrink)
     masks, ri, ci, pvals = [], [], [], []
@@ -354,7 +380,7 @@ def build_sketch(x, y, a, b, opt: Options, chunk: int = 256, prob=None) -> Sketc
     # Entry values: C recomputed from the coordinates, K = exp(-C/eps).
     cvals = np.array([sq_dist(x[i:i + 1], y[j:j + 1])[0, 0] for i, j in zip(ri, ci)]) \
         if ri.size < 4096 else _pair_sq_dist(x, y, ri, ci)
-    cost = cvals * inv_cmax
+    cost = cost_from_sq(cvals, opt.cost, inv_cmax, opt.eta)
     kval = np.exp(-(cost / opt.eps))
     val = kval / ps
     logval = -(cost / opt.eps) - np.log(ps)
@@ -542,7 +568,8 @@ class Estimate:
 
 def estimate_from_entries(rows, cols, t, cost, u, v, a, b, opt: Options) -> Estimate:
     pos = t > 0
-    transport = float(np.sum(t * cost))
+    # entries with t = 0 carry no transport, also where C = +inf (WFR)
+    transport = float(np.sum(t[pos] * cost[pos]))
     neg_ent = float(np.sum(t[pos] * (np.log(t[pos]) - 1.0)))
     row_sum = np.bincount(rows, weights=t, minlength=len(a))
     col_sum = np.bincount(cols, weights=t, minlength=len(b))
@@ -603,7 +630,7 @@ def dense_sinkhorn(x, y, a, b, opt: Options) -> SolveResult:
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     cmax, inv_cmax = cost_scale(x, y, opt)
-    cost = sq_dist(x, y) * inv_cmax
+    cost = cost_from_sq(sq_dist(x, y), opt.cost, inv_cmax, opt.eta)
     K = np.exp(-(cost / opt.eps))
     n, m = K.shape
     if opt.log_domain:

@@ -29,6 +29,15 @@ takes an explicit ``n`` so tests can use small or ragged shapes):
   with location 3/5 and scale^2 1/100, each a density evaluated on the index
   grid i/n, raised by 1e-2 of its maximum and normalised; equal weights;
   s = factor * s0(n), s0(n) = 1e-3 n ln^4 n.
+* ``wfr_synthetic`` -- UOT with the Wasserstein-Fisher-Rao cost (the paper's
+  UOT simulation): one support of n points shared by a and b (C1: x ~
+  U(0,1)^d; C2: x ~ N(0, Sigma), Sigma_jk = 0.5^|j-k|; C3: as C1), a and b
+  densities on the index grid i/n (C1, C2: Gaussians N(1/3, 1/20) and
+  N(1/2, 1/20); C3: t_5 with the same locations and scales^2) scaled to total
+  masses 5 and 3; eps = 0.1, lambda = 0.1; eta set so that a given share of
+  the pairs has d_ij < pi eta (K > 0): 0.7, 0.5, 0.3 for R1, R2, R3, taken
+  as a quantile of the distances of 20000 random pairs (a workload parameter,
+  not part of the method).
 """
 from __future__ import annotations
 
@@ -38,7 +47,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["Problem", "ot_gauss2d", "ot_t5_d10", "uot_mix3", "batch_ot", "s_budget",
-           "IBPProblem", "ibp_synthetic", "s0_budget"]
+           "IBPProblem", "ibp_synthetic", "s0_budget", "wfr_synthetic"]
 
 
 @dataclass
@@ -182,3 +191,31 @@ def ibp_synthetic(n: int = 1000, d: int = 5, seed: int = 0, eps: float = 0.01,
         b.append(g / g.sum())
     return IBPProblem(x=x, b=np.array(b), w=np.full(3, 1.0 / 3.0), eps=eps,
                       s=s_factor * s0_budget(n), seed=seed, name=f"ibp_synthetic_n{n}_d{d}")
+
+
+def wfr_synthetic(n: int = 1000, d: int = 5, seed: int = 0, pattern: str = "C1",
+                  nnz_ratio: float = 0.5, eps: float = 0.1, lam: float = 0.1,
+                  s_factor: float = 8.0) -> Problem:
+    rng = np.random.default_rng(seed)
+    if pattern == "C2":
+        idx = np.arange(d)
+        cov = 0.5 ** np.abs(idx[:, None] - idx[None, :])
+        x = rng.multivariate_normal(np.zeros(d), cov, size=n)
+    else:
+        x = rng.uniform(0.0, 1.0, size=(n, d))
+    t = np.arange(n) / n
+    if pattern == "C3":
+        a = (1.0 + (t - 1 / 3) ** 2 / (1 / 20) / 5.0) ** -3.0
+        b = (1.0 + (t - 1 / 2) ** 2 / (1 / 20) / 5.0) ** -3.0
+    else:
+        a = np.exp(-0.5 * (t - 1 / 3) ** 2 / (1 / 20))
+        b = np.exp(-0.5 * (t - 1 / 2) ** 2 / (1 / 20))
+    a = a * (5.0 / a.sum())
+    b = b * (3.0 / b.sum())
+    i = rng.integers(0, n, size=20000)
+    j = rng.integers(0, n, size=20000)
+    dist = np.sqrt(((x[i] - x[j]) ** 2).sum(axis=1))
+    eta = float(np.quantile(dist, nnz_ratio)) / math.pi
+    return Problem(x, x.copy(), a, b, eps=eps, s=s_factor * s0_budget(max(n, 2)), lam=lam,
+                   seed=seed, name=f"wfr_{pattern}_n{n}_d{d}_r{nnz_ratio:g}",
+                   meta={"eta": eta, "pattern": pattern, "nnz_ratio": nnz_ratio})
