@@ -49,7 +49,7 @@ enum {
 };
 
 enum { SS_F64 = 0, SS_F32 = 1, SS_F32_LOG = 2 };                 /* ss_options.precision */
-enum { SS_COST_SQEUCLID_MAXNORM = 0, SS_COST_SQEUCLID = 1 };      /* ss_options.cost      */
+enum { SS_COST_SQEUCLID_MAXNORM = 0, SS_COST_SQEUCLID = 1, SS_COST_WFR = 2 }; /* ss_options.cost */
 enum { SS_STOP_MARGINAL_L1 = 0, SS_STOP_SCALING_DELTA_L1 = 1 };   /* ss_options.stop_rule */
 enum { SS_EMPTY_AUTO = 0, SS_EMPTY_RENORMALIZE = 1, SS_EMPTY_ZERO = 2, SS_EMPTY_FAIL = 3 };
 
@@ -82,6 +82,13 @@ typedef struct ss_problem {
  *                      log-sum-exp with FP32 exponentials.
  * cost         SS_COST_SQEUCLID_MAXNORM: C = |x-y|^2 / max |x-y|^2.
  *              SS_COST_SQEUCLID:         C = |x-y|^2.
+ *              SS_COST_WFR: the Wasserstein-Fisher-Rao cost of the UOT
+ *                      background section, C = -log cos_+^2(|x-y| / (2 eta)),
+ *                      evaluated as -2 log cos(|x-y| * (1 / (2 eta))) and
+ *                      +infinity (K = 0, never sampled) where that argument
+ *                      is >= pi/2.  Sparse solvers need finite lambda (the
+ *                      UOT probability vanishes with K) and shrink = 0;
+ *                      batches and spar_ibp reject it.
  * stop_rule    SS_STOP_MARGINAL_L1: err(t) = L1 marginal error of (u^t, v^t) on
  *              the iterated kernel (for UOT the fixed-point residual
  *              sum|u^(1/th) K~v - a| + sum|v^(1/th) K~'u - b|, th = lam/(lam+eps)).
@@ -99,6 +106,7 @@ typedef struct ss_problem {
  * u_out, v_out optional device FP64 outputs: the returned scalings u^t, v^t.
  * err_hist     optional device FP64 array of max_iter entries: err(t) for
  *              t = 1..iters (entries past iters untouched).
+ * eta          > 0, the WFR cost's length scale (ignored by the other costs).
  * shrink       g in [0, 1]: shrinkage toward uniform sampling (Sec. 4),
  *              p_ij = (1 - g) p_ij + g / (nm) in place of eq. (pij-ot) /
  *              eq. (pij-uot); 0 is Spar-Sink, 1 is Rand-Sink (Sec. 5, uniform
@@ -111,7 +119,7 @@ typedef struct ss_options {
     int32_t block_threads, graph_iters, reserved0;
     const double *init_log_u, *init_log_v;
     double *u_out, *v_out, *err_hist;
-    double shrink;
+    double shrink, eta;
 } ss_options;
 
 /* Result of a solve (host struct).

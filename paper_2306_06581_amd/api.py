@@ -104,12 +104,12 @@ class Problem:
 def make_options(eps, s=1.0, lam=math.inf, tol=1e-6, max_iter=1000, seed=0, precision="f64",
                  cost="maxnorm", stop_rule="marginal", empty_policy="auto", block_threads=0,
                  graph_iters=0, init_log_u=None, init_log_v=None, u_out=None, v_out=None,
-                 err_hist=None, shrink=0.0) -> N.SsOptions:
+                 err_hist=None, shrink=0.0, eta=1.0) -> N.SsOptions:
     return N.SsOptions(float(eps), float(lam), float(s), float(tol), int(seed) & (2 ** 64 - 1),
                        int(max_iter), N.PRECISION[precision], N.COST[cost], N.STOP[stop_rule],
                        N.EMPTY[empty_policy], int(block_threads), int(graph_iters), 0,
                        _ptr(init_log_u), _ptr(init_log_v), _ptr(u_out), _ptr(v_out),
-                       _ptr(err_hist), float(shrink))
+                       _ptr(err_hist), float(shrink), float(eta))
 
 
 def workspace_size(prob: Problem, opts: N.SsOptions) -> int:
@@ -123,7 +123,8 @@ def workspace_size(prob: Problem, opts: N.SsOptions) -> int:
 def _solve(fn_name: str, prob: Problem, *, eps, s=1.0, lam=math.inf, tol=1e-6, max_iter=1000,
            seed=0, precision="f64", cost="maxnorm", stop_rule="marginal", empty_policy="auto",
            block_threads=0, graph_iters=0, init_log_u=None, init_log_v=None, shrink=0.0,
-           return_scalings=False, return_hist=False, stream=None, raise_on_error=True) -> Result:
+           eta=1.0, return_scalings=False, return_hist=False, stream=None,
+           raise_on_error=True) -> Result:
     u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda") if return_scalings else None
     v_out = torch.empty(prob.m, dtype=torch.float64, device="cuda") if return_scalings else None
     hist = torch.full((max_iter,), float("nan"), dtype=torch.float64, device="cuda") \
@@ -132,7 +133,7 @@ def _solve(fn_name: str, prob: Problem, *, eps, s=1.0, lam=math.inf, tol=1e-6, m
     ilv = _dev(init_log_v) if init_log_v is not None else None
     opts = make_options(eps, s, lam, tol, max_iter, seed, precision, cost, stop_rule,
                         empty_policy, block_threads, graph_iters, ilu, ilv, u_out, v_out, hist,
-                        shrink)
+                        shrink, eta)
     nbytes = workspace_size(prob, opts)
     ws = workspace(nbytes)
     res = N.SsResult()
@@ -166,10 +167,10 @@ def dense_sinkhorn(prob: Problem, **kw) -> Result:
 
 def ss_time_iterations(prob: Problem, iters: int = 64, *, eps, s=1.0, lam=math.inf, seed=0,
                        precision="f64", cost="maxnorm", block_threads=0, shrink=0.0,
-                       stream=None) -> float:
+                       eta=1.0, stream=None) -> float:
     """Mean duration (ms) of one iteration-kernel launch over `iters` iterations."""
     opts = make_options(eps, s, lam, seed=seed, precision=precision, cost=cost,
-                        block_threads=block_threads, shrink=shrink)
+                        block_threads=block_threads, shrink=shrink, eta=eta)
     ws = workspace(workspace_size(prob, opts))
     ms = ctypes.c_double(0.0)
     rc = N.lib.ss_time_iterations(ctypes.byref(prob.c), ctypes.byref(opts),
@@ -181,9 +182,11 @@ def ss_time_iterations(prob: Problem, iters: int = 64, *, eps, s=1.0, lam=math.i
 
 
 def ss_sample(prob: Problem, *, eps, s, lam=math.inf, seed=0, precision="f64", cost="maxnorm",
-              shrink=0.0, capacity: Optional[int] = None, want_mask=True, stream=None) -> dict:
+              shrink=0.0, eta=1.0, capacity: Optional[int] = None, want_mask=True,
+              stream=None) -> dict:
     """Step 1 of Alg. 3/4: returns the mask words, CSR, CSC and p* factors."""
-    opts = make_options(eps, s, lam, seed=seed, precision=precision, cost=cost, shrink=shrink)
+    opts = make_options(eps, s, lam, seed=seed, precision=precision, cost=cost, shrink=shrink,
+                        eta=eta)
     nbytes = workspace_size(prob, opts)
     ws = workspace(nbytes)
     n, m = prob.n, prob.m

@@ -204,8 +204,19 @@ int check_args(const ss_problem* P, const ss_options* O, bool dense) {
     if (O->max_iter < 1) return fail(SS_E_INVALID_ARG, "max_iter must be >= 1");
     if (O->precision < SS_F64 || O->precision > SS_F32_LOG)
         return fail(SS_E_INVALID_ARG, "unknown precision %d", O->precision);
-    if (O->cost != SS_COST_SQEUCLID_MAXNORM && O->cost != SS_COST_SQEUCLID)
+    if (O->cost != SS_COST_SQEUCLID_MAXNORM && O->cost != SS_COST_SQEUCLID &&
+        O->cost != SS_COST_WFR)
         return fail(SS_E_INVALID_ARG, "unknown cost %d", O->cost);
+    if (O->cost == SS_COST_WFR) {
+        if (!(O->eta > 0.0) || !isfinite(O->eta))
+            return fail(SS_E_INVALID_ARG, "the WFR cost needs a finite eta > 0");
+        // the OT probability ignores K, and shrinkage would sample the
+        // structural zeros of K: the sparse solvers need the UOT probability
+        if (!dense && !isfinite(O->lambda))
+            return fail(SS_E_INVALID_ARG, "the WFR cost needs finite lambda (UOT sampling)");
+        if (!dense && O->shrink != 0.0)
+            return fail(SS_E_INVALID_ARG, "the WFR cost takes shrink = 0");
+    }
     if (O->stop_rule != SS_STOP_MARGINAL_L1 && O->stop_rule != SS_STOP_SCALING_DELTA_L1)
         return fail(SS_E_INVALID_ARG, "unknown stop rule %d", O->stop_rule);
     if (O->empty_policy < SS_EMPTY_AUTO || O->empty_policy > SS_EMPTY_FAIL)
@@ -345,6 +356,8 @@ ProbParams make_params(const Ctx& c) {
     // Sec. 4 shrinkage: s p = (1 - g) s p_ij + s g / (nm)
     pp.shrink_w = 1.0 - O->shrink;
     pp.shrink_c = O->s * O->shrink / ((double)c.P->n * (double)c.P->m);
+    pp.cost = O->cost;
+    pp.wfr_w = 0.5 / O->eta;
     pp.row_fac = at<double>(c.ws, c.L.row_fac);
     pp.col_fac = at<double>(c.ws, c.L.col_fac);
     pp.row_bnd = at<double>(c.ws, c.L.row_bnd);
@@ -650,6 +663,8 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     oa.y = P->y;
     oa.d = P->d;
     oa.inv_cmax = c.inv_cmax;
+    oa.cost = O->cost;
+    oa.wfr_w = 0.5 / O->eta;
     oa.eps = O->eps;
     oa.uot = uot ? 1 : 0;
     oa.role = 0;
@@ -1499,6 +1514,8 @@ int dense_sinkhorn(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.d = P->d;
         a.scale = c.inv_cmax / O->eps;
         a.inv_cmax = c.inv_cmax;
+        a.cost = O->cost;
+        a.wfr_w = 0.5 / O->eta;
         a.eps = O->eps;
         a.marg = P->a;
         a.xin = v[k];
@@ -1552,6 +1569,8 @@ int dense_sinkhorn(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     oa.m = m;
     oa.d = P->d;
     oa.inv_cmax = c.inv_cmax;
+    oa.cost = O->cost;
+    oa.wfr_w = 0.5 / O->eta;
     oa.eps = O->eps;
     oa.u = u[p];
     oa.v = v[p];

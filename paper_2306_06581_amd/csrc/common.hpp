@@ -86,6 +86,20 @@ __device__ __forceinline__ double sqdist(const double* __restrict__ xi, const do
     return acc;
 }
 
+// C_ij from the squared Euclidean distance c.  Squared Euclidean costs:
+// c * scale (scale = 1 / cmax or 1).  Wasserstein-Fisher-Rao (UOT background
+// section): C = -log cos_+^2(d / (2 eta)) with d = sqrt(c), evaluated as
+// -2 log cos(z), z = sqrt(c) * w, w = 1 / (2 eta), and +inf (K = 0) where
+// z >= pi/2.
+constexpr int kCostWfr = 2;
+constexpr double kHalfPi = 1.5707963267948966;
+
+__device__ __forceinline__ double cost_value(double c, int kind, double scale, double w) {
+    if (kind != kCostWfr) return c * scale;
+    const double z = sqrt(c) * w;
+    return z >= kHalfPi ? INFINITY : -2.0 * log(cos(z));
+}
+
 // ---------------------------------------------------------------------------
 // Wave and block reductions.  xor-butterflies give every lane the same value
 // (IEEE addition is commutative), so the results are deterministic.

@@ -47,7 +47,7 @@ struct DensePartial {
     float* part_s;   // [nseg][nl]: LOG sums
 };
 
-template <int PREC, int D>
+template <int PREC, int D, bool WFR>
 __global__ __launch_bounds__(256) void k_dense_partial(DensePartial P) {
     typedef typename DenseT<PREC>::C Cf;
     constexpr int R = DenseT<PREC>::R;
@@ -82,6 +82,10 @@ __global__ __launch_bounds__(256) void k_dense_partial(DensePartial P) {
     }
     const double scale = A.scale;                       // inv_cmax / eps
     const float scale2 = (float)(A.scale * 1.4426950408889634);  // times log2(e)
+    // WFR: log2 K = (2/eps) log2 cos(sqrt(c) w), K = 0 from sqrt(c) w = pi/2 on
+    const float wf = (float)A.wfr_w;
+    const float two_eps = (float)(2.0 / A.eps);
+    const float two_eps_ln = (float)(2.0 / A.eps * 0.6931471805599453);
 
     for (int64_t jt = j0; jt < j1; jt += kDenseTile) {
         __syncthreads();
@@ -114,11 +118,34 @@ __global__ __launch_bounds__(256) void k_dense_partial(DensePartial P) {
                     }
                 }
                 if (PREC == P_F64) {
-                    const double C = (double)c * A.inv_cmax;
+                    const double C = WFR ? cost_value((double)c, kCostWfr, 1.0, A.wfr_w)
+                                         : (double)c * A.inv_cmax;
                     acc64[r] = acc64[r] + exp(-(C / A.eps)) * vj;
                 } else if (PREC == P_F32) {
-                    acc32[r] = fmaf(__builtin_amdgcn_exp2f(-(float)c * scale2), vjf, acc32[r]);
+                    if (WFR) {
+                        const float z = __fsqrt_rn((float)c) * wf;
+                        const float k2 = z < (float)kHalfPi
+                                             ? two_eps * __log2f(__cosf(z)) : -INFINITY;
+                        acc32[r] = fmaf(__builtin_amdgcn_exp2f(k2), vjf, acc32[r]);
+                    } else {
+                        acc32[r] = fmaf(__builtin_amdgcn_exp2f(-(float)c * scale2), vjf, acc32[r]);
+                    }
                 } else {
+                    if (WFR) {
+                        const float zc = __fsqrt_rn((float)c) * wf;
+                        if (!(zc < (float)kHalfPi)) continue;   // K = 0: no term
+                        const double lk = (double)(two_eps_ln * __log2f(__cosf(zc)));
+                        const double z = vj + lk;
+                        const double dz = z - mx[r];
+                        const float e = __expf(-(float)fabs(dz));
+                        if (dz > 0.0) {
+                            acc32[r] = acc32[r] * e + 1.0f;
+                            mx[r] = z;
+                        } else {
+                            acc32[r] += e;
+                        }
+                        continue;
+                    }
                     const double z = vj - (double)c * scale;
                     const double dz = z - mx[r];
                     const float e = __expf(-(float)fabs(dz));
@@ -220,8 +247,12 @@ static void run_dense(const DenseArgs& a, void* part, hipStream_t st) {
     dense_shape(DenseT<PREC>::R, a.nl, a.no, &P.row_tiles, &P.nseg, &P.seg_len);
     P.part = part;
     P.part_s = (float*)((char*)part + (size_t)P.nseg * a.nl * 8);
-    hipLaunchKernelGGL((k_dense_partial<PREC, D>), dim3((unsigned)(P.row_tiles * P.nseg)),
-                       dim3(kBlock), 0, st, P);
+    if (a.cost == kCostWfr)
+        hipLaunchKernelGGL((k_dense_partial<PREC, D, true>), dim3((unsigned)(P.row_tiles * P.nseg)),
+                           dim3(kBlock), 0, st, P);
+    else
+        hipLaunchKernelGGL((k_dense_partial<PREC, D, false>), dim3((unsigned)(P.row_tiles * P.nseg)),
+                           dim3(kBlock), 0, st, P);
     if (a.theta != 1.0)
         hipLaunchKernelGGL((k_dense_finish<PREC, true>), dim3(dense_blocks(a.nl)), dim3(kBlock), 0,
                            st, P);
@@ -298,7 +329,7 @@ __global__ __launch_bounds__(256) void k_dense_obj_partial(DenseObj O) {
             // entry (i, j) with i the row: distances always as |x_i - y_j|^2
             const double c = O.role == 0 ? sqdist<D>(xi, O.xo + j * d, d)
                                          : sqdist<D>(O.xo + j * d, xi, d);
-            const double C = c * A.inv_cmax;
+            const double C = cost_value(c, A.cost, A.inv_cmax, A.wfr_w);
             const double lk = -(C / A.eps);
             double t;
             if (PREC == P_LOG)

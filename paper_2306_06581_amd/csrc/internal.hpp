@@ -59,6 +59,8 @@ struct ProbParams {
     double kappa;       // s / Z                        (UOT; device value in stats)
     double shrink_w;    // 1 - g: weight of eq. (pij-ot)/(pij-uot) in the shrunk p
     double shrink_c;    // s g / (nm): the uniform part of s p (0 without shrinkage)
+    int cost;           // SS_COST_*; kCostWfr: C from cost_value with wfr_w
+    double wfr_w;       // 1 / (2 eta)
     const double* row_fac;  // OT: alpha_i;  UOT: th_u log a_i
     const double* col_fac;  // OT: sqrt b_j; UOT: th_u log b_j
     const double* row_bnd;  // UOT: exp(row_fac_i)
@@ -264,6 +266,8 @@ struct ObjArgs {
     int d;
     double inv_cmax;
     double eps;
+    int cost;             // SS_COST_*
+    double wfr_w;         // 1 / (2 eta) (WFR)
     int uot;
     int role;             // 0 rows (transport, entropy, KL_a), 1 columns (KL_b)
     double* partials;     // 4 * nblocks
@@ -280,6 +284,8 @@ struct DenseArgs {
     int d;
     double scale;         // inv_cmax / eps: K = exp(-c * scale)
     double inv_cmax, eps; // FP64 mode: K = exp(-((c * inv_cmax) / eps))
+    int cost;             // SS_COST_*; WFR: K = cos(sqrt(c) w)^(2/eps), 0 past pi/2
+    double wfr_w;         // 1 / (2 eta)
     const double* marg;
     const void* xin;      // other side's scaling
     void* yout;
@@ -303,6 +309,8 @@ struct DenseObjArgs {
     int64_t n, m;
     int d;
     double inv_cmax, eps;
+    int cost;
+    double wfr_w;
     const void* u;
     const void* v;
     const double* a;

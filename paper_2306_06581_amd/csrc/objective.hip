@@ -53,7 +53,8 @@ __global__ __launch_bounds__(256) void k_objective(ObjArgs A) {
             const double t = plan_entry<PREC>(yl, ylog, A.val, k, A.zs, o);
             s_line += t;
             if (A.role == 0 && t > 0.0) {
-                const double c = sqdist<D>(xl, A.y + o * A.d, A.d) * A.inv_cmax;
+                const double c = cost_value(sqdist<D>(xl, A.y + o * A.d, A.d), A.cost, A.inv_cmax,
+                                            A.wfr_w);
                 s_tc += t * c;
                 const double lt = log(t);
                 s_ent += t * (lt - 1.0);

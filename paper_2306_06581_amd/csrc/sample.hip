@@ -332,7 +332,7 @@ template <int D>
 __device__ __forceinline__ double uot_q(const ProbParams& pp, const double* xi, int64_t i,
                                         int64_t j) {
     const double c = sqdist<D>(xi, pp.y + j * pp.d, pp.d);
-    const double C = c * pp.inv_cmax;
+    const double C = cost_value(c, pp.cost, pp.inv_cmax, pp.wfr_w);
     return exp((pp.row_fac[i] + pp.col_fac[j]) - C * pp.inv_tau);
 }
 
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t
             const double la = pp.row_fac[i];
             for (int64_t j = j0; j < j1; ++j) {
                 const double c = sqdist<D>(D > 0 ? xi : xp, pp.y + j * pp.d, pp.d);
-                const double C = c * pp.inv_cmax;
+                const double C = cost_value(c, pp.cost, pp.inv_cmax, pp.wfr_w);
                 acc = acc + exp((la + pp.col_fac[j]) - C * pp.inv_tau);
             }
         }
@@ -415,7 +415,8 @@ hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double
     const int64_t nct = (m + kCostTileCols - 1) / kCostTileCols;
     const int64_t nrt = (n + 255) / 256;
     const double g = pp.inv_cmax * pp.inv_tau;
-    const bool short_range = g * cmax <= 0.5;
+    // the short-range exponential needs the squared Euclidean cost
+    const bool short_range = pp.cost != kCostWfr && g * cmax <= 0.5;
     SS_DISPATCH_D(pp.d, run_uot_z, pp, n, m, eb, g, short_range, partials, nct, nrt, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -736,7 +737,7 @@ template <bool UOT, int D>
 __device__ __forceinline__ double entry_value(const ProbParams& pp, double kappa, int64_t i,
                                               int64_t j, double* logv) {
     const double c = sqdist<D>(pp.x + i * pp.d, pp.y + j * pp.d, pp.d);
-    const double C = c * pp.inv_cmax;
+    const double C = cost_value(c, pp.cost, pp.inv_cmax, pp.wfr_w);
     const double Ce = C / pp.eps;
     const double K = exp(-Ce);
     double P;
@@ -999,6 +1000,8 @@ __global__ __launch_bounds__(256) void k_b_mask(BatchArgs A) {
     pp.uot = 0;
     pp.shrink_w = 1.0;
     pp.shrink_c = 0.0;
+    pp.cost = SS_COST_SQEUCLID_MAXNORM;   // C = c * inv_cmax (inv_cmax = 1 for the plain cost)
+    pp.wfr_w = 0.0;
     pp.row_fac = A.row_fac + P.xo;
     pp.col_fac = A.col_fac + P.yo;
     pp.problem_index = P.pidx;
@@ -1033,6 +1036,8 @@ __global__ __launch_bounds__(256) void k_b_fill(BatchArgs A) {
     pp.uot = 0;
     pp.shrink_w = 1.0;
     pp.shrink_c = 0.0;
+    pp.cost = SS_COST_SQEUCLID_MAXNORM;   // C = c * inv_cmax (inv_cmax = 1 for the plain cost)
+    pp.wfr_w = 0.0;
     pp.s = P.s;
     pp.eps = A.eps;
     pp.inv_cmax = A.stat[k].inv_cmax;

@@ -26,7 +26,7 @@ SS_E_EMPTY = -5
 SS_E_CAPACITY = -6
 
 PRECISION = {"f64": 0, "f32": 1, "f32_log": 2}
-COST = {"maxnorm": 0, "plain": 1}
+COST = {"maxnorm": 0, "plain": 1, "wfr": 2}
 STOP = {"marginal": 0, "delta": 1}
 EMPTY = {"auto": 0, "renormalize": 1, "zero": 2, "fail": 3}
 
@@ -42,7 +42,8 @@ class SsOptions(ctypes.Structure):
                 ("cost", c_int32), ("stop_rule", c_int32), ("empty_policy", c_int32),
                 ("block_threads", c_int32), ("graph_iters", c_int32), ("reserved0", c_int32),
                 ("init_log_u", c_void_p), ("init_log_v", c_void_p), ("u_out", c_void_p),
-                ("v_out", c_void_p), ("err_hist", c_void_p), ("shrink", c_double)]
+                ("v_out", c_void_p), ("err_hist", c_void_p), ("shrink", c_double),
+                ("eta", c_double)]
 
 
 class SsResult(ctypes.Structure):

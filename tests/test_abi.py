@@ -51,7 +51,7 @@ int main(void) {
          sizeof(ss_problem), sizeof(ss_options), sizeof(ss_result), sizeof(ss_sparse));
   printf("ss_batch %zu\nss_schedule %zu\n", sizeof(ss_batch), sizeof(ss_schedule));
   P(ss_batch, s) P(ss_batch, x) P(ss_batch, b) P(ss_schedule, block_threads)
-  P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist) P(ss_options, shrink)
+  P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist) P(ss_options, shrink) P(ss_options, eta)
   P(ss_result, nnz) P(ss_result, iters) P(ss_result, t_obj_ms) P(ss_sparse, capacity)
   P(ss_sparse, z_norm) P(ss_ibp_problem, x) P(ss_ibp_problem, w) P(ss_ibp_result, nnz)
   P(ss_ibp_result, t_iter_ms)
@@ -80,6 +80,7 @@ def test_struct_layout_matches_header():
     assert N.SsOptions.init_log_u.offset == lay["ss_options.init_log_u"]
     assert N.SsOptions.err_hist.offset == lay["ss_options.err_hist"]
     assert N.SsOptions.shrink.offset == lay["ss_options.shrink"]
+    assert N.SsOptions.eta.offset == lay["ss_options.eta"]
     assert N.SsResult.nnz.offset == lay["ss_result.nnz"]
     assert N.SsResult.iters.offset == lay["ss_result.iters"]
     assert N.SsResult.t_obj_ms.offset == lay["ss_result.t_obj_ms"]
@@ -297,3 +298,16 @@ def test_ibp_workspace_grows_with_measures():
         assert rc == 0
         sizes.append(out.value)
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+@pytest.mark.parametrize("case", ["ot_sparse", "shrink", "eta0", "etainf"])
+def test_wfr_arguments_rejected(case):
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd import api as A
+    prob = N.SsProblem(8, 8, 2, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                       ctypes.c_void_p(16))
+    o = A.make_options(eps=0.1, s=10.0, lam=math.inf if case == "ot_sparse" else 0.1, cost="wfr",
+                       shrink=0.5 if case == "shrink" else 0.0,
+                       eta={"eta0": 0.0, "etainf": math.inf}.get(case, 0.3))
+    out = ctypes.c_size_t(0)
+    assert N.lib.ss_workspace_size(ctypes.byref(prob), ctypes.byref(o), ctypes.byref(out)) == -1

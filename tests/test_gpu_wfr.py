@@ -1,0 +1,114 @@
+"""Parity of the Wasserstein-Fisher-Rao cost (UOT background section; the
+paper's UOT simulation) between the HIP path, through the C ABI, and the CPU
+FP64 oracle: sampling (UOT bars: mask bits equal except on the decision
+boundary, no structural zero ever kept), the sparse and dense FP64 iterates
+within 1e-10, and the reduced-precision estimates within 1e-4."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sparsink_oracle as O
+from paper_2306_06581_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_06581_amd import api as A
+    return A
+
+
+def _oopt(p, **kw):
+    base = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, problem_index=p.problem_index,
+                cost="wfr", eta=p.meta["eta"])
+    base.update(kw)
+    return O.Options(**base)
+
+
+def _kw(p, **kw):
+    base = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, cost="wfr", eta=p.meta["eta"])
+    base.update(kw)
+    return base
+
+
+def _prob(api, p):
+    return api.Problem(p.x, p.y, p.a, p.b, problem_index=p.problem_index)
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("pattern,ratio", [("C1", 0.7), ("C2", 0.5), ("C3", 0.3)])
+def test_sample_wfr(api, pattern, ratio):
+    p = W.wfr_synthetic(450, d=5, seed=21, pattern=pattern, nnz_ratio=ratio)
+    eta = p.meta["eta"]
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
+    gm = g["mask"].cpu().numpy().view(np.uint64)
+    diff = gm ^ sk.mask
+    if diff.any():
+        bits = np.unpackbits(diff.view(np.uint8), axis=1, bitorder="little")[:, : p.m]
+        rr, cc = np.nonzero(bits)
+        u = O.uniform01(rr, cc, p.problem_index, p.seed)
+        pst = np.array([sk.prob.pstar(np.array([r]), np.array([c]))[0, 0] for r, c in zip(rr, cc)])
+        assert np.all(np.abs(u - pst) <= 1e-12 * pst), (rr, cc)
+    else:
+        assert g["nnz"] == sk.nnz
+        assert np.array_equal(g["col_idx"].cpu().numpy(), sk.col_idx)
+        assert np.array_equal(g["row_ptr"].cpu().numpy(), sk.row_ptr)
+        np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-13)
+    # no kept entry lies at or beyond the blocking distance pi eta
+    rows = np.repeat(np.arange(p.n), np.diff(g["row_ptr"].cpu().numpy()))
+    cols = g["col_idx"].cpu().numpy()
+    d = np.sqrt(((p.x[rows] - p.y[cols]) ** 2).sum(axis=1))
+    assert np.all(d < math.pi * eta)
+    assert np.all(np.isfinite(g["val"].cpu().numpy())) and np.all(g["val"].cpu().numpy() > 0)
+
+
+def test_spar_sink_uot_wfr_f64_fixed_iterations(api):
+    p = W.wfr_synthetic(500, d=5, seed=22, nnz_ratio=0.5)
+    T = 40
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=T))
+    r = api.spar_sink_uot(_prob(api, p), **_kw(p, tol=0.0, max_iter=T), precision="f64",
+                          return_scalings=True)
+    assert r.iters == T and r.nnz == o.nnz and r.empty_rows == o.empty_rows
+    np.testing.assert_allclose(r.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(r.v.cpu().numpy(), o.sinkhorn.v, rtol=1e-10, atol=0)
+    assert _rel(r.estimate, o.estimate.estimate) < 1e-10
+    assert _rel(r.transport, o.estimate.transport) < 1e-10
+
+
+def test_dense_wfr_f64(api):
+    p = W.wfr_synthetic(300, d=5, seed=23, nnz_ratio=0.5)
+    T = 30
+    o = O.dense_sinkhorn(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=T))
+    r = api.dense_sinkhorn(_prob(api, p), **_kw(p, tol=0.0, max_iter=T), precision="f64",
+                           return_scalings=True)
+    assert r.iters == T
+    np.testing.assert_allclose(r.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(r.v.cpu().numpy(), o.sinkhorn.v, rtol=1e-10, atol=0)
+    assert _rel(r.estimate, o.estimate.estimate) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["f32", "f32_log"])
+def test_dense_wfr_reduced_precision(api, precision):
+    p = W.wfr_synthetic(700, d=5, seed=24, nnz_ratio=0.3)
+    o = O.dense_sinkhorn(p.x, p.y, p.a, p.b, _oopt(p, tol=1e-6, max_iter=3000))
+    r = api.dense_sinkhorn(_prob(api, p), **_kw(p, tol=1e-6, max_iter=3000), precision=precision)
+    assert r.status == 0 and r.marginal_err <= 1e-6
+    assert _rel(r.estimate, o.estimate.estimate) < 1e-4
+
+
+def test_spar_sink_uot_wfr_log_domain(api):
+    p = W.wfr_synthetic(1500, d=5, seed=25, nnz_ratio=0.5, s_factor=16.0)
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=1e-6, max_iter=3000, log_domain=True))
+    r = api.spar_sink_uot(_prob(api, p), **_kw(p, tol=1e-6, max_iter=3000), precision="f32_log")
+    assert r.status == 0 and r.marginal_err <= 1e-6 and r.nnz == o.nnz
+    assert _rel(r.estimate, o.estimate.estimate) < 1e-4
