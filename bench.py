@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-ibp", action="store_true")
     ap.add_argument("--ibp-only", action="store_true", help="only the Spar-IBP workload")
     ap.add_argument("--ibp-n", type=int, default=16384)
+    ap.add_argument("--no-wfr", action="store_true")
+    ap.add_argument("--wfr-only", action="store_true", help="only the WFR workload")
+    ap.add_argument("--wfr-n", type=int, default=65536)
     return ap.parse_args()
 
 
@@ -255,6 +258,53 @@ def ibp_bench(n: int, steps: int, cpu: bool) -> dict:
     return out
 
 
+def wfr_bench(n: int, steps: int, dense: bool) -> dict:
+    """UOT with the Wasserstein-Fisher-Rao cost (the paper's UOT simulation,
+    pattern C1, d = 5, eps = 0.1, lambda = 0.1, masses 5 and 3) at n points,
+    half of the pairs within the blocking distance (R2), s = 8 s0(n),
+    log-domain FP32, stop at residual <= 1e-6; the dense baseline (FP32, K
+    recomputed with its zeros) beside it."""
+    import torch
+
+    from paper_2306_06581_amd import api as A
+    from paper_2306_06581_amd import workloads as W
+
+    p = W.wfr_synthetic(n, d=5, seed=0, pattern="C1", nnz_ratio=0.5, s_factor=8.0)
+    prob = A.Problem(p.x, p.y, p.a, p.b)
+    kw = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, tol=1e-6, max_iter=5000,
+              precision="f32_log", cost="wfr", eta=p.meta["eta"])
+    A.spar_sink_uot(prob, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [A.spar_sink_uot(prob, **kw) for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    r = res[-1]
+    ms_launch = A.ss_time_iterations(prob, 64, eps=p.eps, s=p.s, lam=p.lam, seed=p.seed,
+                                     precision="f32_log", cost="wfr", eta=p.meta["eta"])
+    by = iteration_bytes_per_launch("f32_log", r.nnz, p.n, p.m)
+    out = {"workload": f"wfr_C1 n=m={n} d=5 R2 eta={p.meta['eta']:.4f} eps=0.1 lambda=0.1 "
+                       f"s=8 s0(n) f32_log tol=1e-6",
+           "ms_per_solve": ms, "iters": r.iters, "status": r.status, "nnz": r.nnz,
+           "estimate": r.estimate, "sparse_objective": r.sparse_objective,
+           "stage_ms": {"prep": r.t_prep_ms, "sample": r.t_sample_ms, "iterate": r.t_iter_ms,
+                        "objective": r.t_obj_ms},
+           "ms_per_launch": ms_launch, "launch_GBps": by / (ms_launch * 1e-3) / 1e9}
+    if dense:
+        dkw = dict(kw, precision="f32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = A.dense_sinkhorn(prob, **dkw)
+        torch.cuda.synchronize()
+        dms = (time.perf_counter() - t0) * 1e3
+        out.update({"dense_ms": dms, "dense_iters": d.iters, "dense_status": d.status,
+                    "dense_estimate": d.estimate, "speedup_vs_dense": dms / ms,
+                    "rel_err_vs_dense": abs(r.estimate - d.estimate) / abs(d.estimate),
+                    "sparse_objective_rel_err_vs_dense":
+                        abs(r.sparse_objective - d.estimate) / abs(d.estimate)})
+    return out
+
+
 def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
     """The FP64 oracle timed on a bounded sample of the same workload."""
     import numpy as np
@@ -316,6 +366,11 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"batched": batched_bench(args.batch_count, args.steps)}))
+        return
+    if args.wfr_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"wfr": wfr_bench(args.wfr_n, args.steps, not args.no_dense)}))
         return
     if args.ibp_only:
         import torch
@@ -424,6 +479,8 @@ def main():
         out["warmstart"] = warmstart_bench(args.warmstart_train, args.batch_count)
     if not args.no_ibp:
         out["ibp"] = ibp_bench(args.ibp_n, args.steps, not args.no_cpu)
+    if not args.no_wfr:
+        out["wfr"] = wfr_bench(args.wfr_n, args.steps, not args.no_dense)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, r.iters, args.precision == "f32_log")
     print(json.dumps(out))

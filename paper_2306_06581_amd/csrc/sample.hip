@@ -243,6 +243,7 @@ __global__ __launch_bounds__(256) void k_cmax_rows(const double* __restrict__ x,
         switch (d) {                                          \
             case 2: KERNEL<2>(__VA_ARGS__); break;            \
             case 3: KERNEL<3>(__VA_ARGS__); break;            \
+            case 5: KERNEL<5>(__VA_ARGS__); break;            \
             case 10: KERNEL<10>(__VA_ARGS__); break;          \
             default: KERNEL<0>(__VA_ARGS__); break;           \
         }                                                     \
@@ -327,13 +328,25 @@ hipError_t launch_uot_prep(const double* a, const double* b, int64_t n, int64_t 
     return hipGetLastError();
 }
 
-// q_ij = exp((la_i + lb_j) - (c_ij inv_cmax) inv_tau): eq. (pij-uot) numerator.
-template <int D>
-__device__ __forceinline__ double uot_q(const ProbParams& pp, const double* xi, int64_t i,
-                                        int64_t j) {
-    const double c = sqdist<D>(xi, pp.y + j * pp.d, pp.d);
+// q_ij = exp((la_i + lb_j) - C_ij inv_tau): eq. (pij-uot) numerator, from the
+// squared distance c_ij.
+__device__ __forceinline__ double uot_q_of(const ProbParams& pp, double c, int64_t i, int64_t j) {
     const double C = cost_value(c, pp.cost, pp.inv_cmax, pp.wfr_w);
     return exp((pp.row_fac[i] + pp.col_fac[j]) - C * pp.inv_tau);
+}
+
+// The cost factor exp(-C_ij inv_tau) of q_ij bounded from above by 2^(-t) with
+// t from the squared distance alone: t = c inv_cmax inv_tau log2(e) for the
+// squared Euclidean costs (equality), and for WFR, where cos z <= exp(-z^2/2)
+// on [0, pi/2], cos(z)^(2 inv_tau) <= exp(-z^2 inv_tau) with z^2 = c w^2;
+// t = +inf where z is surely past pi/2 (blocked: q = 0).
+__device__ __forceinline__ double uot_bound_exponent(const ProbParams& pp, double c) {
+    if (pp.cost == kCostWfr) {
+        const double z2 = c * (pp.wfr_w * pp.wfr_w);
+        if (z2 >= (kHalfPi * kHalfPi) * (1.0 + 1e-12)) return INFINITY;
+        return z2 * pp.inv_tau * kLog2e;
+    }
+    return c * (pp.inv_cmax * pp.inv_tau) * kLog2e;
 }
 
 // Z = sum_ij q_ij: per-thread sums over a column tile in column order, a fixed
@@ -486,16 +499,35 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
                 const int64_t j = 256 * g + 64 * s + lane;
                 bool keep = false;
                 if (j < m) {
-                    const double P = rowf * cf[gg * 4 + s] + pc;
+                    const double Pr = rowf * cf[gg * 4 + s];
+                    const double P = Pr + pc;
                     if (!UOT) {
                         keep = keep_decision(h.w[s], P, q, (uint32_t)i, pp.problem_index, pp.k0,
                                              pp.k1, s);
                     } else if ((double)h.w[s] * 0x1p-32 < P) {
-                        // P is an upper bound; only candidates pay for the exact p*.
-                        const double q_ij = uot_q<D>(pp, pp.x + i * pp.d, i, j);
-                        const double pst = fmin(1.0, kappa * q_ij + pp.shrink_c);
-                        keep = keep_decision(h.w[s], pst, q, (uint32_t)i, pp.problem_index, pp.k0,
-                                             pp.k1, s);
+                        // P bounds p* without the cost factor.  Candidates first
+                        // take the cost factor's bound in FP32 (margin 2^-12 for
+                        // the rounding of its argument and of the exponential),
+                        // and only those below it pay for the exact p*.  Where
+                        // the FP32 bound underflows, only hi = 0 can still fall
+                        // below p*, so that case goes to the exact test as well.
+                        // (With the max-normalised cost, C <= 1, the cost factor is
+                        // at least exp(-inv_tau) and the refinement does not pay.)
+                        const double c = sqdist<D>(pp.x + i * pp.d, pp.y + j * pp.d, pp.d);
+                        bool exact = true;
+                        if (pp.cost != SS_COST_SQEUCLID_MAXNORM) {
+                            const double t = uot_bound_exponent(pp, c);
+                            const double e =
+                                t < 200.0 ? (double)__builtin_amdgcn_exp2f(-(float)t) : 0.0;
+                            const double Pt = Pr * e * (1.0 + 0x1p-12) + pc;
+                            exact = (double)h.w[s] * 0x1p-32 < Pt || h.w[s] == 0u;
+                        }
+                        if (exact) {
+                            const double q_ij = uot_q_of(pp, c, i, j);
+                            const double pst = fmin(1.0, kappa * q_ij + pp.shrink_c);
+                            keep = keep_decision(h.w[s], pst, q, (uint32_t)i, pp.problem_index,
+                                                 pp.k0, pp.k1, s);
+                        }
                     }
                 }
                 const uint64_t word = __ballot(keep);

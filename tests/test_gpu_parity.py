@@ -126,6 +126,19 @@ def test_sample_uot(api, n, eps, lam):
     np.testing.assert_allclose(g["row_fac"].cpu().numpy(), sk.prob.la, rtol=1e-15)
 
 
+def test_sample_uot_plain_cost(api):
+    # unnormalised squared Euclidean cost (C up to ~10): the mask's FP32 bound of
+    # the cost factor decides most candidates
+    p = W.uot_mix3(500, seed=8, eps=0.5)
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p, cost="plain"))
+    g = api.ss_sample(_prob(api, p), **_kw(p), cost="plain", precision="f64")
+    assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
+    nd = _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
+    if nd == 0:
+        _check_sketch_structure(g, sk)
+        np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-13)
+
+
 # ---------------------------------------------------------------- Sinkhorn loop
 def _rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
