@@ -401,6 +401,34 @@ int ss_ibp_time_iterations(const ss_ibp_problem *problem, const ss_options *opts
                            size_t ws_bytes, void *stream, int32_t iters, double *ms_per_iter,
                            int64_t *nnz);
 
+/* ------------------------------------------------------------------------
+ * Sinkhorn divergence (the generative-modelling section, eq. (sink-div)):
+ * S(mu, nu) = OT_eps(mu, nu) - (OT_eps(mu, mu) + OT_eps(nu, nu)) / 2 with each
+ * term the Spar-Sink estimate of Alg. 3, from three OT solves on hash streams
+ * problem_index, problem_index + 1 and problem_index + 2.  The cost must be
+ * SS_COST_SQEUCLID (one cost for all three terms) and lambda +INFINITY.
+ * Gradients (optional, device FP64, grad_x n*d and grad_y m*d row-major, both
+ * or neither): the derivatives of the sparse problems' values in the points
+ * by the envelope theorem, sum_j T~_ij 2 (x_i - y_j) per term, with the mask
+ * fixed (the OT probability depends on the masses only); the self terms
+ * contribute through both of their arguments.  opts->u_out, v_out, err_hist,
+ * init_log_u and init_log_v are ignored.  The workspace is the largest of
+ * the three solves' (ss_divergence_workspace_size). */
+typedef struct ss_divergence {
+    double value;          /* S from the Alg. 3 estimates */
+    double value_sparse;   /* S from the sparse problems' values */
+    double ot_xy, ot_xx, ot_yy;
+    double sparse_xy, sparse_xx, sparse_yy;
+    int64_t nnz;           /* entries over the three sketches */
+    int32_t iters_xy, iters_xx, iters_yy, status;
+} ss_divergence;
+
+int ss_divergence_workspace_size(const ss_problem *problem, const ss_options *opts,
+                                 size_t *bytes);
+int ss_sinkhorn_divergence(const ss_problem *problem, const ss_options *opts, double *grad_x,
+                           double *grad_y, void *ws, size_t ws_bytes, void *stream,
+                           ss_divergence *result);
+
 const char *ss_status_string(int status);
 const char *ss_last_error(void);
 int ss_version(void);

@@ -560,3 +560,49 @@ def ss_ibp_time_iterations(prob: IBPProblem, iters: int = 64, *, eps, s, seed=0,
     if rc < 0:
         raise N.SparSinkError(rc, "ss_ibp_time_iterations")
     return float(ms.value), int(nnz.value)
+
+
+# ---------------------------------------------------------------- divergence
+@dataclass
+class DivergenceResult:
+    status: int
+    value: float
+    value_sparse: float
+    ot_xy: float
+    ot_xx: float
+    ot_yy: float
+    sparse_xy: float
+    sparse_xx: float
+    sparse_yy: float
+    nnz: int
+    iters_xy: int
+    iters_xx: int
+    iters_yy: int
+    grad_x: Optional[torch.Tensor] = None
+    grad_y: Optional[torch.Tensor] = None
+
+
+def sinkhorn_divergence(prob: Problem, *, eps, s, tol=1e-6, max_iter=1000, seed=0,
+                        precision="f64", shrink=0.0, graph_iters=0, return_grad=True,
+                        stream=None, raise_on_error=True) -> DivergenceResult:
+    """eq. (sink-div) from three Spar-Sink OT solves, with the envelope
+    gradients in x and y (squared Euclidean cost, unnormalised)."""
+    opts = make_options(eps, s, math.inf, tol, max_iter, seed, precision, "plain", "marginal",
+                        "auto", 0, graph_iters, shrink=shrink)
+    out = ctypes.c_size_t(0)
+    rc = N.lib.ss_divergence_workspace_size(ctypes.byref(prob.c), ctypes.byref(opts),
+                                            ctypes.byref(out))
+    if rc < 0:
+        raise N.SparSinkError(rc, "ss_divergence_workspace_size")
+    ws = workspace(int(out.value))
+    gx = torch.empty_like(prob.x) if return_grad else None
+    gy = torch.empty_like(prob.y) if return_grad else None
+    res = N.SsDivergence()
+    rc = N.lib.ss_sinkhorn_divergence(ctypes.byref(prob.c), ctypes.byref(opts), _ptr(gx), _ptr(gy),
+                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                      _stream(stream), ctypes.byref(res))
+    if rc < 0 and raise_on_error:
+        raise N.SparSinkError(rc, "ss_sinkhorn_divergence")
+    return DivergenceResult(status=rc, grad_x=gx, grad_y=gy,
+                            **{k: getattr(res, k) for k, _ in N.SsDivergence._fields_
+                               if k != "status"})

@@ -504,9 +504,17 @@ void fill_result(const Ctx& c, const IterState& hs, ss_result* R, int64_t nnz) {
 // time_iters > 0: after sampling, run exactly time_iters iterations (tol = 0)
 // as one captured graph, once to warm up and once timed with HIP events, and
 // return the mean duration of one iteration-kernel launch in *ms_out.
+// Where a solve adds the envelope gradients of its sparse value (the
+// divergence): gx += cx * d/dx, gy += cy * d/dy (gy may equal gx).
+struct GradSink {
+    double* gx;
+    double* gy;
+    double cx, cy;
+};
+
 int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes,
                    void* stream, ss_result* R, bool uot, int time_iters = 0,
-                   double* ms_out = nullptr) {
+                   double* ms_out = nullptr, const GradSink* gs = nullptr) {
     int rc = check_args(P, O, false);
     if (rc != SS_OK) return rc;
     if (!R) return fail(SS_E_INVALID_ARG, "result must not be NULL");
@@ -683,6 +691,34 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     oa.y = P->x;
     oa.role = 1;
     HIP_TRY(launch_objective(prec, oa, c.st));
+    if (gs) {
+        // squared Euclidean cost: dC_ij/dx_i = 2 inv_cmax (x_i - y_j), and the
+        // column side symmetrically
+        GradArgs ga;
+        ga.ptr = at<int64_t>(ws, c.L.row_ptr);
+        ga.idx = at<int32_t>(ws, c.L.col_idx);
+        ga.val = at<void>(ws, c.L.val);
+        ga.nlines = n;
+        ga.ys = u[p];
+        ga.zs = v[p];
+        ga.xl = P->x;
+        ga.xo = P->y;
+        ga.d = P->d;
+        ga.coef = 2.0 * c.inv_cmax * gs->cx;
+        ga.out = gs->gx;
+        HIP_TRY(launch_plan_grad(prec, ga, c.st));
+        ga.ptr = at<int64_t>(ws, c.L.col_ptr);
+        ga.idx = at<int32_t>(ws, c.L.row_idx);
+        ga.val = at<void>(ws, c.L.val_t);
+        ga.nlines = m;
+        ga.ys = v[p];
+        ga.zs = u[p];
+        ga.xl = P->y;
+        ga.xo = P->x;
+        ga.coef = 2.0 * c.inv_cmax * gs->cy;
+        ga.out = gs->gy;
+        HIP_TRY(launch_plan_grad(prec, ga, c.st));
+    }
     HIP_TRY(launch_export_scaling(prec, u[p], O->u_out, n, c.st));
     HIP_TRY(launch_export_scaling(prec, v[p], O->v_out, m, c.st));
     HIP_TRY(hipMemcpyAsync(c.stats, at<double>(ws, c.L.stats), sizeof(c.stats),
@@ -1967,6 +2003,91 @@ int ss_ibp_time_iterations(const ss_ibp_problem* P, const ss_options* O, void* w
     if (hs.nonfinite) return fail(SS_E_NONFINITE, "the barycenter became NaN or Inf");
     *ms_per_iter = (double)ms / (double)iters;
     return SS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- divergence
+namespace {
+
+int check_divergence(const ss_problem* P, const ss_options* O) {
+    int rc = check_args(P, O, false);
+    if (rc != SS_OK) return rc;
+    if (isfinite(O->lambda)) return fail(SS_E_INVALID_ARG, "the divergence is built from OT terms");
+    if (O->cost != SS_COST_SQEUCLID)
+        return fail(SS_E_INVALID_ARG, "the divergence needs the unnormalised squared Euclidean cost");
+    // the self terms are n x n and m x m problems with the same options
+    const ss_problem pxx = {P->n, P->n, P->d, P->problem_index, P->x, P->x, P->a, P->a};
+    const ss_problem pyy = {P->m, P->m, P->d, P->problem_index, P->y, P->y, P->b, P->b};
+    rc = check_args(&pxx, O, false);
+    if (rc != SS_OK) return rc;
+    return check_args(&pyy, O, false);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_divergence_workspace_size(const ss_problem* P, const ss_options* O, size_t* bytes) {
+    int rc = check_divergence(P, O);
+    if (rc != SS_OK) return rc;
+    if (!bytes) return fail(SS_E_INVALID_ARG, "bytes must not be NULL");
+    const ss_problem pxx = {P->n, P->n, P->d, P->problem_index, P->x, P->x, P->a, P->a};
+    const ss_problem pyy = {P->m, P->m, P->d, P->problem_index, P->y, P->y, P->b, P->b};
+    size_t b0 = plan(P, O).total, b1 = plan(&pxx, O).total, b2 = plan(&pyy, O).total;
+    *bytes = b0 > b1 ? (b0 > b2 ? b0 : b2) : (b1 > b2 ? b1 : b2);
+    return SS_OK;
+}
+
+int ss_sinkhorn_divergence(const ss_problem* P, const ss_options* O, double* grad_x,
+                           double* grad_y, void* ws, size_t ws_bytes, void* stream,
+                           ss_divergence* R) {
+    int rc = check_divergence(P, O);
+    if (rc != SS_OK) return rc;
+    if (!R) return fail(SS_E_INVALID_ARG, "result must not be NULL");
+    if ((grad_x == nullptr) != (grad_y == nullptr))
+        return fail(SS_E_INVALID_ARG, "grad_x and grad_y are both given or both NULL");
+    memset(R, 0, sizeof *R);
+    hipStream_t st = (hipStream_t)stream;
+    // per-term outputs and warm starts do not apply to the three solves
+    ss_options o = *O;
+    o.init_log_u = o.init_log_v = nullptr;
+    o.u_out = o.v_out = o.err_hist = nullptr;
+    const uint32_t pi = P->problem_index;
+    const ss_problem pxy = {P->n, P->m, P->d, pi, P->x, P->y, P->a, P->b};
+    const ss_problem pxx = {P->n, P->n, P->d, pi + 1u, P->x, P->x, P->a, P->a};
+    const ss_problem pyy = {P->m, P->m, P->d, pi + 2u, P->y, P->y, P->b, P->b};
+    if (grad_x) {
+        HIP_TRY(launch_fill_f64(grad_x, P->n * P->d, 0.0, st));
+        HIP_TRY(launch_fill_f64(grad_y, P->m * P->d, 0.0, st));
+    }
+    const GradSink g_xy = {grad_x, grad_y, 1.0, 1.0};
+    const GradSink g_xx = {grad_x, grad_x, -0.5, -0.5};
+    const GradSink g_yy = {grad_y, grad_y, -0.5, -0.5};
+    ss_result r[3];
+    const ss_problem* probs[3] = {&pxy, &pxx, &pyy};
+    const GradSink* sinks[3] = {&g_xy, &g_xx, &g_yy};
+    int worst = SS_OK;
+    for (int t = 0; t < 3; ++t) {
+        rc = spar_sink_impl(probs[t], &o, ws, ws_bytes, stream, &r[t], false, 0, nullptr,
+                            grad_x ? sinks[t] : nullptr);
+        if (rc < 0) return rc;
+        if (rc > worst) worst = rc;
+    }
+    R->value = r[0].estimate - 0.5 * (r[1].estimate + r[2].estimate);
+    R->value_sparse = r[0].sparse_objective - 0.5 * (r[1].sparse_objective + r[2].sparse_objective);
+    R->ot_xy = r[0].estimate;
+    R->ot_xx = r[1].estimate;
+    R->ot_yy = r[2].estimate;
+    R->sparse_xy = r[0].sparse_objective;
+    R->sparse_xx = r[1].sparse_objective;
+    R->sparse_yy = r[2].sparse_objective;
+    R->nnz = r[0].nnz + r[1].nnz + r[2].nnz;
+    R->iters_xy = r[0].iters;
+    R->iters_xx = r[1].iters;
+    R->iters_yy = r[2].iters;
+    R->status = worst;
+    return worst;
 }
 
 }  // extern "C"

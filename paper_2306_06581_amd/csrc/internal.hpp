@@ -276,6 +276,24 @@ struct ObjArgs {
 };
 hipError_t launch_objective(int precision, const ObjArgs& a, hipStream_t st);
 
+// Gradient of the sparse problem's value in the points of one side (envelope
+// theorem, squared Euclidean cost): out[line * d + k] += coef * sum over the
+// line's entries of T~ (xl[line][k] - xo[other][k]).
+struct GradArgs {
+    const int64_t* ptr;
+    const int32_t* idx;
+    const void* val;
+    int64_t nlines;
+    const void* ys;       // scaling of the line side
+    const void* zs;       // scaling of the other side
+    const double* xl;     // coordinates of the line side
+    const double* xo;     // coordinates of the other side
+    int d;
+    double coef;
+    double* out;
+};
+hipError_t launch_plan_grad(int precision, const GradArgs& a, hipStream_t st);
+
 // ---- dense.hip
 struct DenseArgs {
     const double* xl;     // coordinates of the line side (n_l x d)

@@ -128,6 +128,71 @@ static void run_obj_d(int precision, const ObjArgs& a, hipStream_t st) {
         run_obj<P_LOG, D>(a, st);
 }
 
+// Envelope gradient of the sparse problem's value (the divergence of the
+// generative-modelling section): 16 lanes per line stride its entries, T~ as
+// in the estimate, a fixed xor tree per coordinate, then one read-modify-write
+// of the line's d outputs (lines are disjoint, launches on one stream).
+template <int PREC, int D>
+__global__ __launch_bounds__(256) void k_plan_grad(GradArgs A) {
+    const int tid = threadIdx.x, sub = tid % kObjLanes;
+    const int64_t line = (int64_t)blockIdx.x * (kBlock / kObjLanes) + tid / kObjLanes;
+    if (line >= A.nlines) return;   // the whole 16-lane group leaves together
+    const int64_t k0 = A.ptr[line], k1 = A.ptr[line + 1];
+    const double yl = scal_lin<PREC>(A.ys, line);
+    const double ylog = scal_log<PREC>(A.ys, line);
+    const int d = D > 0 ? D : A.d;
+    const double* xl = A.xl + line * d;
+    if constexpr (D > 0) {
+        double acc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = 0.0;
+        for (int64_t e = k0 + sub; e < k1; e += kObjLanes) {
+            const int64_t o = A.idx[e];
+            const double t = plan_entry<PREC>(yl, ylog, A.val, e, A.zs, o);
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] += t * (xl[k] - A.xo[o * D + k]);
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double g = group_sum<kObjLanes>(acc[k]);
+            if (sub == 0) A.out[line * D + k] += A.coef * g;
+        }
+    } else {
+        for (int k = 0; k < d; ++k) {
+            double acc = 0.0;
+            for (int64_t e = k0 + sub; e < k1; e += kObjLanes) {
+                const int64_t o = A.idx[e];
+                const double t = plan_entry<PREC>(yl, ylog, A.val, e, A.zs, o);
+                acc += t * (xl[k] - A.xo[o * d + k]);
+            }
+            const double g = group_sum<kObjLanes>(acc);
+            if (sub == 0) A.out[line * d + k] += A.coef * g;
+        }
+    }
+}
+
+template <int D>
+static void run_grad_d(int precision, const GradArgs& a, hipStream_t st) {
+    const int nb = (int)((a.nlines + (kBlock / kObjLanes) - 1) / (kBlock / kObjLanes));
+    if (precision == P_F64)
+        hipLaunchKernelGGL((k_plan_grad<P_F64, D>), dim3(nb), dim3(kBlock), 0, st, a);
+    else if (precision == P_F32)
+        hipLaunchKernelGGL((k_plan_grad<P_F32, D>), dim3(nb), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_plan_grad<P_LOG, D>), dim3(nb), dim3(kBlock), 0, st, a);
+}
+
+hipError_t launch_plan_grad(int precision, const GradArgs& a, hipStream_t st) {
+    if (a.nlines <= 0) return hipSuccess;
+    switch (a.d) {
+        case 2: run_grad_d<2>(precision, a, st); break;
+        case 3: run_grad_d<3>(precision, a, st); break;
+        case 10: run_grad_d<10>(precision, a, st); break;
+        default: run_grad_d<0>(precision, a, st); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_objective(int precision, const ObjArgs& a, hipStream_t st) {
     if (a.nlines <= 0) return hipSuccess;
     switch (a.d) {

@@ -98,6 +98,14 @@ class SsIbpResult(ctypes.Structure):
 IBP_MAX_MEASURES = 64
 
 
+class SsDivergence(ctypes.Structure):
+    _fields_ = [("value", c_double), ("value_sparse", c_double), ("ot_xy", c_double),
+                ("ot_xx", c_double), ("ot_yy", c_double), ("sparse_xy", c_double),
+                ("sparse_xx", c_double), ("sparse_yy", c_double), ("nnz", c_int64),
+                ("iters_xy", c_int32), ("iters_xx", c_int32), ("iters_yy", c_int32),
+                ("status", c_int32)]
+
+
 # Every symbol the header declares, with its signature.
 SIGNATURES = {
     "ss_workspace_size": (c_int, [POINTER(SsProblem), POINTER(SsOptions), POINTER(c_size_t)]),
@@ -133,6 +141,11 @@ SIGNATURES = {
     "ss_ibp_time_iterations": (c_int, [POINTER(SsIbpProblem), POINTER(SsOptions), c_void_p,
                                        c_size_t, c_void_p, c_int32, POINTER(c_double),
                                        POINTER(c_int64)]),
+    "ss_divergence_workspace_size": (c_int, [POINTER(SsProblem), POINTER(SsOptions),
+                                             POINTER(c_size_t)]),
+    "ss_sinkhorn_divergence": (c_int, [POINTER(SsProblem), POINTER(SsOptions), c_void_p,
+                                       c_void_p, c_void_p, c_size_t, c_void_p,
+                                       POINTER(SsDivergence)]),
     "ss_status_string": (c_char_p, [c_int]),
     "ss_last_error": (c_char_p, []),
     "ss_version": (c_int, []),

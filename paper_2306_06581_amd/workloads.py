@@ -38,6 +38,10 @@ takes an explicit ``n`` so tests can use small or ragged shapes):
   the pairs has d_ij < pi eta (K > 0): 0.7, 0.5, 0.3 for R1, R2, R3, taken
   as a quantile of the distances of 20000 random pairs (a workload parameter,
   not part of the method).
+* ``latent_pair``  -- the Sinkhorn-divergence regulariser of the generative-
+  modelling section: a batch of n latent codes in R^d (a fixed non-Gaussian
+  warp of Gaussian draws, standing in for encoder outputs) against n draws of
+  the standard Gaussian prior, uniform weights, eps = 0.01, s = 10 s0(n).
 """
 from __future__ import annotations
 
@@ -47,7 +51,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["Problem", "ot_gauss2d", "ot_t5_d10", "uot_mix3", "batch_ot", "s_budget",
-           "IBPProblem", "ibp_synthetic", "s0_budget", "wfr_synthetic"]
+           "IBPProblem", "ibp_synthetic", "s0_budget", "wfr_synthetic", "latent_pair"]
 
 
 @dataclass
@@ -219,3 +223,15 @@ def wfr_synthetic(n: int = 1000, d: int = 5, seed: int = 0, pattern: str = "C1",
     return Problem(x, x.copy(), a, b, eps=eps, s=s_factor * s0_budget(max(n, 2)), lam=lam,
                    seed=seed, name=f"wfr_{pattern}_n{n}_d{d}_r{nnz_ratio:g}",
                    meta={"eta": eta, "pattern": pattern, "nnz_ratio": nnz_ratio})
+
+
+def latent_pair(n: int = 500, d: int = 10, seed: int = 0, eps: float = 0.01,
+                s_factor: float = 10.0) -> Problem:
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n, d))
+    x = 0.8 * z + 0.4 * np.sin(3.0 * z) + 0.3
+    y = rng.standard_normal((n, d))
+    a = np.full(n, 1.0 / n)
+    b = np.full(n, 1.0 / n)
+    return Problem(x, y, a, b, eps=eps, s=s_factor * s0_budget(max(n, 2)), seed=seed,
+                   name=f"latent_pair_n{n}_d{d}")

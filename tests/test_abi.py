@@ -54,7 +54,8 @@ int main(void) {
   P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist) P(ss_options, shrink) P(ss_options, eta)
   P(ss_result, nnz) P(ss_result, iters) P(ss_result, t_obj_ms) P(ss_sparse, capacity)
   P(ss_sparse, z_norm) P(ss_ibp_problem, x) P(ss_ibp_problem, w) P(ss_ibp_result, nnz)
-  P(ss_ibp_result, t_iter_ms)
+  P(ss_ibp_result, t_iter_ms) P(ss_divergence, nnz) P(ss_divergence, status)
+  printf("ss_divergence %zu\n", sizeof(ss_divergence));
   printf("ss_ibp_problem %zu\nss_ibp_result %zu\n", sizeof(ss_ibp_problem), sizeof(ss_ibp_result));
   return 0;
 }
@@ -98,6 +99,9 @@ def test_struct_layout_matches_header():
     assert N.SsIbpProblem.w.offset == lay["ss_ibp_problem.w"]
     assert N.SsIbpResult.nnz.offset == lay["ss_ibp_result.nnz"]
     assert N.SsIbpResult.t_iter_ms.offset == lay["ss_ibp_result.t_iter_ms"]
+    assert ctypes.sizeof(N.SsDivergence) == lay["ss_divergence"]
+    assert N.SsDivergence.nnz.offset == lay["ss_divergence.nnz"]
+    assert N.SsDivergence.status.offset == lay["ss_divergence.status"]
 
 
 def _fake_problem(N, n=8, m=8, d=2):
@@ -311,3 +315,20 @@ def test_wfr_arguments_rejected(case):
                        eta={"eta0": 0.0, "etainf": math.inf}.get(case, 0.3))
     out = ctypes.c_size_t(0)
     assert N.lib.ss_workspace_size(ctypes.byref(prob), ctypes.byref(o), ctypes.byref(out)) == -1
+
+
+@pytest.mark.parametrize("case", ["uot", "maxnorm", "wfr"])
+def test_divergence_arguments_rejected(case):
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd import api as A
+    prob = N.SsProblem(8, 6, 2, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                       ctypes.c_void_p(16))
+    o = A.make_options(eps=0.1, s=10.0, lam=0.5 if case == "uot" else math.inf,
+                       cost={"uot": "plain", "maxnorm": "maxnorm", "wfr": "wfr"}[case], eta=0.3)
+    out = ctypes.c_size_t(0)
+    assert N.lib.ss_divergence_workspace_size(ctypes.byref(prob), ctypes.byref(o),
+                                              ctypes.byref(out)) == -1
+    o2 = A.make_options(eps=0.1, s=10.0, cost="plain")
+    assert N.lib.ss_divergence_workspace_size(ctypes.byref(prob), ctypes.byref(o2),
+                                              ctypes.byref(out)) == 0
+    assert out.value > 0
