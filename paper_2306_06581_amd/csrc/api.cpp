@@ -50,6 +50,8 @@ struct Layout {
     size_t row_fac, col_fac, row_bnd, col_bnd, a_eff, b_eff, la_eff, lb_eff, tmp, tree, u[2], v[2];
     size_t ug[2], vg[2];
     size_t partials, loop_part[2], state, stats, hstage, dense_part, rowsum, colsum;
+    // UOT normaliser by expansion: centre, monomial table, partials, sums
+    size_t zcenter, zexps, zcoef, zpart, zsums;
     // lane plans of the iteration kernel: [0] rows (u-update), [1] columns
     struct PlanOff {
         size_t split, quads, weight, wptr, rstart, info, scan, qs, qe, steplanes, stepoff, lmeta;
@@ -177,6 +179,12 @@ Layout plan(const ss_problem* P, const ss_options* O) {
     L.stats = take(ST_COUNT * 8);
     L.hstage = take(64);
     L.dense_part = take((size_t)64 * nm * 12);  // <= 64 column segments per line
+    const bool uot = isfinite(O->lambda);
+    L.zcenter = take(uot ? 64 * 8 : 0);
+    L.zexps = take(uot ? (size_t)kZMaxMono * 8 : 0);
+    L.zcoef = take(uot ? (size_t)kZMaxMono * 8 : 0);
+    L.zpart = take(uot ? (size_t)2 * kZBlocks * kZMaxMono * 8 : 0);
+    L.zsums = take(uot ? (size_t)2 * kZMaxMono * 8 : 0);
     L.rowsum = take((size_t)64 * n * 8);
     L.colsum = take((size_t)64 * m * 8);
     L.total = off;
@@ -324,7 +332,59 @@ struct Ctx {
     double stats[ST_COUNT];
     int64_t nnz;
     double inv_cmax;
+    // host copy of the monomial table of the normaliser's expansion (kept
+    // until the sampling stage synchronises)
+    std::vector<uint8_t> zexps;
+    std::vector<double> zcoef;
 };
+
+// Degree K of the normaliser's expansion: the remainder of the exponential
+// series at |t| <= T is below T^(K+1)/(K+1)! e^T, relative to a term of at
+// least e^-T; K is the smallest degree with that ratio below 2^-64.  False
+// when no K <= kZMaxDegree works or the monomials exceed kZMaxMono.
+bool zexp_degree(double g, double rx2, double ry2, int d, int* K_out, int* M_out) {
+    if (!(g >= 0.0) || !isfinite(g) || d > 8) return false;
+    const double T = 2.0 * g * sqrt(rx2) * sqrt(ry2) * (1.0 + 1e-9);
+    if (!isfinite(T)) return false;
+    double term = T * exp(2.0 * T);   // T^(K+1)/(K+1)! e^(2T) at K = 0
+    for (int K = 0; K <= kZMaxDegree; ++K) {
+        if (K > 0) term *= T / (double)(K + 1);
+        if (term <= 0x1p-64) {
+            // monomials of degree <= K in d variables: C(K + d, d)
+            double M = 1.0;
+            for (int i = 1; i <= d; ++i) M = M * (double)(K + i) / (double)i;
+            if (M > kZMaxMono) return false;
+            *K_out = K;
+            *M_out = (int)llround(M);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Every multi-index alpha with |alpha| <= K (d <= 8 exponents per entry) and
+// coef_alpha = (2g)^|alpha| / alpha!.
+void zexp_table(int d, int K, double g, std::vector<uint8_t>* exps, std::vector<double>* coef) {
+    exps->clear();
+    coef->clear();
+    uint8_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::function<void(int, int)> rec = [&](int k, int left) {
+        if (k == d) {
+            double c = 1.0;
+            for (int i = 0; i < d; ++i)
+                for (int q = 1; q <= a[i]; ++q) c *= (2.0 * g) / (double)q;
+            exps->insert(exps->end(), a, a + 8);
+            coef->push_back(c);
+            return;
+        }
+        for (int e = 0; e <= left; ++e) {
+            a[k] = (uint8_t)e;
+            rec(k + 1, left - e);
+        }
+        a[k] = 0;
+    };
+    rec(0, K);
+}
 
 // Zeroes state and statistics, checks the inputs, computes max c_ij.
 int stage_start(Ctx& c) {
@@ -335,6 +395,9 @@ int stage_start(Ctx& c) {
     HIP_TRY(launch_validate(P->a, P->n, P->x, P->n * P->d, stats, c.st));
     HIP_TRY(launch_validate(P->b, P->m, P->y, P->m * P->d, stats, c.st));
     HIP_TRY(launch_cmax(P->x, P->y, P->n, P->m, P->d, stats, at<void>(c.ws, c.L.tmp), c.st));
+    if (c.uot)
+        HIP_TRY(launch_center_radii(P->x, P->y, P->n, P->m, P->d, at<void>(c.ws, c.L.tmp),
+                                    at<double>(c.ws, c.L.zcenter), stats, c.st));
     HIP_TRY(hipMemcpyAsync(c.stats, stats, sizeof(c.stats), hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     if (c.stats[ST_BAD_INPUT] != 0.0)
@@ -389,8 +452,38 @@ int stage_sample(Ctx& c) {
         // exp(col_fac) goes to col_bnd until the bounds below replace it
         HIP_TRY(launch_uot_prep(P->a, P->b, n, m, O->lambda, O->eps, (double*)pp.row_fac,
                                 (double*)pp.col_fac, (double*)pp.row_bnd, (double*)pp.col_bnd, st));
-        HIP_TRY(launch_uot_z(pp, n, m, pp.col_bnd, c.stats[ST_CMAX], at<double>(ws, c.L.partials),
-                             tree, stats, st));
+        // Z: by the truncated expansion where the cost is squared Euclidean
+        // and the degree stays small, else pair by pair
+        int K = 0, M = 0;
+        if (O->cost != SS_COST_WFR &&
+            zexp_degree(c.inv_cmax * pp.inv_tau, c.stats[ST_RX2], c.stats[ST_RY2], P->d, &K, &M)) {
+            zexp_table(P->d, K, c.inv_cmax * pp.inv_tau, &c.zexps, &c.zcoef);
+            uint8_t* dexps = at<uint8_t>(ws, c.L.zexps);
+            double* dcoef = at<double>(ws, c.L.zcoef);
+            HIP_TRY(hipMemcpyAsync(dexps, c.zexps.data(), c.zexps.size(), hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(dcoef, c.zcoef.data(), c.zcoef.size() * 8, hipMemcpyHostToDevice,
+                                   st));
+            ZExpArgs za;
+            za.x = P->x;
+            za.y = P->y;
+            za.la = pp.row_fac;
+            za.lb = pp.col_fac;
+            za.n = n;
+            za.m = m;
+            za.d = P->d;
+            za.K = K;
+            za.M = M;
+            za.g = c.inv_cmax * pp.inv_tau;
+            za.center = at<double>(ws, c.L.zcenter);
+            za.exps = dexps;
+            za.coef = dcoef;
+            za.part = at<double>(ws, c.L.zpart);
+            za.sums = at<double>(ws, c.L.zsums);
+            HIP_TRY(launch_uot_zexp(za, stats, st));
+        } else {
+            HIP_TRY(launch_uot_z(pp, n, m, pp.col_bnd, c.stats[ST_CMAX],
+                                 at<double>(ws, c.L.partials), tree, stats, st));
+        }
         HIP_TRY(launch_uot_bounds(pp.col_fac, m, O->s, pp.shrink_w, stats, (double*)pp.col_bnd,
                                   st));
     }

@@ -44,6 +44,8 @@ enum StatSlot {
     ST_BAD_INPUT,   // > 0 if an input was negative or non-finite
     ST_EMPTY_ROWS,  // rows with no entry and a_i > 0 (stored as double)
     ST_EMPTY_COLS,
+    ST_RX2,         // max_i |x_i - c|^2 about the cost-scan centre c
+    ST_RY2,         // max_j |y_j - c|^2
     ST_COUNT = 32
 };
 
@@ -130,6 +132,36 @@ hipError_t launch_tree_sum(const double* in, int64_t n, double* scratch, double*
 hipError_t launch_cmax(const double* x, const double* y, int64_t n, int64_t m, int d,
                        double* stats, void* scratch, hipStream_t st);
 size_t cmax_scratch_bytes(int64_t n);
+// After launch_cmax: copies the centre c of the cost scan to center_out[d]
+// and maximises |x_i - c|^2, |y_j - c|^2 into stats[ST_RX2], stats[ST_RY2]
+// (which must start at 0).
+hipError_t launch_center_radii(const double* x, const double* y, int64_t n, int64_t m, int d,
+                               const void* cmax_scratch, double* center_out, double* stats,
+                               hipStream_t st);
+
+// Z (eq. (pij-uot) normaliser) for the squared Euclidean costs by the
+// truncated expansion of exp(2 g x~.y~) in monomials of degree <= K about the
+// centre (g = inv_cmax inv_tau): Z = sum_alpha coef_alpha S_alpha T_alpha.
+// exps: M x 8 exponents (d <= 8); coef: M; part: 2 x kZBlocks x M scratch,
+// sums: 2 x M.  Writes stats[ST_Z].
+constexpr int kZBlocks = 512;
+constexpr int kZMaxMono = 1024;
+constexpr int kZMaxDegree = 24;
+struct ZExpArgs {
+    const double* x;
+    const double* y;
+    const double* la;   // th_u log a (row factor)
+    const double* lb;   // th_u log b
+    int64_t n, m;
+    int d, K, M;
+    double g;
+    const double* center;
+    const uint8_t* exps;
+    const double* coef;
+    double* part;
+    double* sums;
+};
+hipError_t launch_uot_zexp(const ZExpArgs& a, double* stats, hipStream_t st);
 hipError_t launch_ot_prep(const double* a, const double* b, int64_t n, int64_t m, double s,
                           double shrink_w, double* ra, double* rb, double* scratch,
                           double* stats, hipStream_t st);

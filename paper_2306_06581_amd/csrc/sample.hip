@@ -436,6 +436,144 @@ hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double
     return launch_tree_sum(partials, nct * nrt, scratch, stats + ST_Z, st);
 }
 
+// ------------------------------------------------------------------ Z by expansion
+// With x~ = x - c and y~ = y - c for a centre c, c_ij = |x~_i|^2 + |y~_j|^2 -
+// 2 x~_i . y~_j, so q_ij = A_i B_j exp(2 g x~_i . y~_j) with
+// A_i = exp(la_i - g |x~_i|^2), B_j = exp(lb_j - g |y~_j|^2), and
+// exp(2 g x~.y~) = sum_alpha (2g)^|alpha| / alpha! x~^alpha y~^alpha (the
+// multinomial form of the exponential series).  Cut at |alpha| <= K (the host
+// picks K so that the remainder is below 2^-64 of the smallest term), Z =
+// sum_alpha coef_alpha S_alpha T_alpha with S_alpha = sum_i A_i x~_i^alpha,
+// T_alpha = sum_j B_j y~_j^alpha: O((n + m) M) work for M monomials instead
+// of nm exponentials.  Every sum runs in a fixed order.
+__global__ __launch_bounds__(256) void k_cm_radii(const double* __restrict__ x,
+                                                  const double* __restrict__ y, int64_t n,
+                                                  int64_t m, int d, const CmaxScratch* cs,
+                                                  double* __restrict__ center_out, double* stats) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < d) center_out[t] = cs->center[t];
+    double rx = t < n ? center_sqdist(x + t * d, cs->center, d) : 0.0;
+    double ry = t < m ? center_sqdist(y + t * d, cs->center, d) : 0.0;
+    rx = group_max<kWave>(rx);
+    ry = group_max<kWave>(ry);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicMax((unsigned long long*)&stats[ST_RX2], (unsigned long long)__double_as_longlong(rx));
+        atomicMax((unsigned long long*)&stats[ST_RY2], (unsigned long long)__double_as_longlong(ry));
+    }
+}
+
+hipError_t launch_center_radii(const double* x, const double* y, int64_t n, int64_t m, int d,
+                               const void* cmax_scratch, double* center_out, double* stats,
+                               hipStream_t st) {
+    const int64_t t = n > m ? n : m;
+    hipLaunchKernelGGL(k_cm_radii, dim3(grid_for(t > d ? t : d)), dim3(256), 0, st, x, y, n, m, d,
+                       (const CmaxScratch*)cmax_scratch, center_out, stats);
+    return hipGetLastError();
+}
+
+constexpr int kZPts = 32;   // points staged per round
+
+// Block partials of S_alpha (side 0: x, la) or T_alpha (side 1: y, lb) over a
+// grid-stride of point chunks; thread t owns monomials t, t + 256, ...
+template <int D>
+__global__ __launch_bounds__(256) void k_zexp_part(ZExpArgs A, int side) {
+    __shared__ double pw[kZPts][8][kZMaxDegree + 1];
+    __shared__ double w[kZPts];
+    const double* pts = side == 0 ? A.x : A.y;
+    const double* lw = side == 0 ? A.la : A.lb;
+    const int64_t np = side == 0 ? A.n : A.m;
+    const int d = D > 0 ? D : A.d;
+    double acc[kZMaxMono / 256];
+#pragma unroll
+    for (int s = 0; s < kZMaxMono / 256; ++s) acc[s] = 0.0;
+    for (int64_t p0 = (int64_t)blockIdx.x * kZPts; p0 < np; p0 += (int64_t)gridDim.x * kZPts) {
+        __syncthreads();   // the previous chunk is no longer read
+        for (int t = threadIdx.x; t < kZPts * d; t += blockDim.x) {
+            const int p = t / d, k = t - p * d;
+            const int64_t i = p0 + p;
+            const double v = i < np ? pts[i * d + k] - A.center[k] : 0.0;
+            double e = 1.0;
+            for (int q = 0; q <= A.K; ++q) {
+                pw[p][k][q] = e;
+                e *= v;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kZPts) {
+            const int p = threadIdx.x;
+            const int64_t i = p0 + p;
+            double r2 = 0.0;
+            for (int k = 0; k < d; ++k) r2 = r2 + pw[p][k][1] * pw[p][k][1];
+            w[p] = i < np ? exp(lw[i] - A.g * r2) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kZMaxMono / 256; ++s) {
+            const int a = threadIdx.x + 256 * s;
+            if (a < A.M) {
+                const uint8_t* ex = A.exps + (int64_t)a * 8;
+                uint8_t e[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) e[k] = ex[k];
+                double sum = 0.0;
+                for (int p = 0; p < kZPts; ++p) {
+                    double f = w[p];
+#pragma unroll
+                    for (int k = 0; k < (D > 0 ? D : 8); ++k)
+                        if (D > 0 || k < d) f *= pw[p][k][e[k]];
+                    sum += f;
+                }
+                acc[s] += sum;
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < kZMaxMono / 256; ++s) {
+        const int a = threadIdx.x + 256 * s;
+        if (a < A.M) A.part[((int64_t)side * gridDim.x + blockIdx.x) * A.M + a] = acc[s];
+    }
+}
+
+// sums[side][alpha] = sum over blocks, in block order.
+__global__ __launch_bounds__(256) void k_zexp_sum(ZExpArgs A, int nblocks) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int side = blockIdx.y;
+    if (a >= A.M) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += A.part[((int64_t)side * nblocks + b) * A.M + a];
+    A.sums[side * A.M + a] = s;
+}
+
+// Z = sum_alpha coef_alpha S_alpha T_alpha (one block, fixed tree).
+__global__ __launch_bounds__(256) void k_zexp_final(ZExpArgs A, double* stats) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int a = threadIdx.x; a < A.M; a += blockDim.x)
+        acc += A.coef[a] * (A.sums[a] * A.sums[A.M + a]);
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) stats[ST_Z] = acc;
+}
+
+template <int D>
+static void run_zexp(const ZExpArgs& a, hipStream_t st) {
+    for (int side = 0; side < 2; ++side)
+        hipLaunchKernelGGL(k_zexp_part<D>, dim3(kZBlocks), dim3(256), 0, st, a, side);
+}
+
+hipError_t launch_uot_zexp(const ZExpArgs& a, double* stats, hipStream_t st) {
+    if (a.d > 8 || a.M > kZMaxMono || a.K > kZMaxDegree) return hipErrorInvalidValue;
+    switch (a.d) {
+        case 2: run_zexp<2>(a, st); break;
+        case 3: run_zexp<3>(a, st); break;
+        case 5: run_zexp<5>(a, st); break;
+        default: run_zexp<0>(a, st); break;
+    }
+    hipLaunchKernelGGL(k_zexp_sum, dim3((unsigned)((a.M + 255) / 256), 2), dim3(256), 0, st, a,
+                       kZBlocks);
+    hipLaunchKernelGGL(k_zexp_final, dim3(1), dim3(256), 0, st, a, stats);
+    return hipGetLastError();
+}
+
 // Column factor of a rigorous upper bound on p*: for every (i, j),
 // p*_ij <= ea_i * fb_j + c (1 + 2^-30) with fb_j = (1 - g)(s/Z) exp(lb_j)
 // (1 + 2^-30) and c the uniform part of shrinkage; the margins cover the
