@@ -534,14 +534,17 @@ __global__ __launch_bounds__(256) void k_zexp_part(ZExpArgs A, int side) {
     }
 }
 
-// sums[side][alpha] = sum over blocks, in block order.
+// sums[side][alpha] = sum over the blocks' partials: one block per (alpha,
+// side), a thread-strided pass and the fixed block tree.
 __global__ __launch_bounds__(256) void k_zexp_sum(ZExpArgs A, int nblocks) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sh[16];
+    const int a = blockIdx.x;
     const int side = blockIdx.y;
-    if (a >= A.M) return;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += A.part[((int64_t)side * nblocks + b) * A.M + a];
-    A.sums[side * A.M + a] = s;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        s += A.part[((int64_t)side * nblocks + b) * A.M + a];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) A.sums[side * A.M + a] = s;
 }
 
 // Z = sum_alpha coef_alpha S_alpha T_alpha (one block, fixed tree).
@@ -568,8 +571,7 @@ hipError_t launch_uot_zexp(const ZExpArgs& a, double* stats, hipStream_t st) {
         case 5: run_zexp<5>(a, st); break;
         default: run_zexp<0>(a, st); break;
     }
-    hipLaunchKernelGGL(k_zexp_sum, dim3((unsigned)((a.M + 255) / 256), 2), dim3(256), 0, st, a,
-                       kZBlocks);
+    hipLaunchKernelGGL(k_zexp_sum, dim3((unsigned)a.M, 2), dim3(256), 0, st, a, kZBlocks);
     hipLaunchKernelGGL(k_zexp_final, dim3(1), dim3(256), 0, st, a, stats);
     return hipGetLastError();
 }
