@@ -59,7 +59,9 @@ __device__ __forceinline__ bool keep_decision(uint32_t hi, double P, uint32_t q,
     if (h >= P) return false;
     if (h + (0x1p-32 - 0x1p-53) < P) return true;
     const Words4 lo = philox10(q, i, k, 1u, k0, k1);
-    const uint64_t bits = ((uint64_t)hi << 32) | (uint64_t)lo.w[slot];
+    // a select, not an index: `slot` may be a run-time value
+    const uint32_t lw = slot == 0 ? lo.w[0] : slot == 1 ? lo.w[1] : slot == 2 ? lo.w[2] : lo.w[3];
+    const uint64_t bits = ((uint64_t)hi << 32) | (uint64_t)lw;
     const double U = (double)(bits >> 11) * 0x1p-53;
     return U < P;
 }

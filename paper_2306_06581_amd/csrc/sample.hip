@@ -597,84 +597,150 @@ hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrin
 
 // ------------------------------------------------------------------ mask
 // Block tile: 16 rows x 64 mask words (4096 columns).  Wave w owns hash
-// groups 4w..4w+3 of the tile (one Philox call per lane per group and row)
-// and keeps its 16 column factors in registers while it walks the 16 rows.
+// groups 4w..4w+3 of the tile: one Philox call per lane per group and row
+// gives the high words of four columns 64 apart.
+//
+// Two phases per wave, so that the hash loop stays small (few registers,
+// high occupancy) and no wave idles while one lane evaluates an exact p*:
+//  1. filter: hash the high words and keep as a candidate every entry that
+//     can still be sampled, hi < 2^32 P with P the decision's probability
+//     (OT) or its cost-free bound (UOT), scaled by 2^32 (1 + 2^-40) so that
+//     the filter only ever adds candidates; candidates go to a per-wave list
+//     in LDS (ballot + lane prefix count, no atomics);
+//  2. decide: when the list may overflow, and at the end, every lane takes
+//     one listed entry and runs the exact decision (the same test and
+//     arithmetic as a pair-by-pair evaluation: the OT comparison of U with
+//     p*; for UOT the cost-free bound, the cost factor's bound for the
+//     unnormalised and WFR costs, then the exact p* and U).  Kept entries set
+//     their bit in the wave's own words of the tile.
+// An entry that the filter drops has hi >= 2^32 P, so U >= P: it is never
+// kept.  The mask is therefore the same as a pair-by-pair evaluation's.
 constexpr int kMaskRows = 16;
+constexpr int kMaskCand = 512;  // list entries per wave (>= 256 + one row's 256)
 
 // One tile: rows row0 .. row0 + 15 of one problem, mask words ct * 64 ..
 // ct * 64 + 63; adds the popcounts to row_cnt.  All 256 threads call it.
-template <bool UOT, int D>
+// `cand` holds kMaskCand entries per wave.  WFR = false: the cost is not the
+// WFR cost (its cosine and logarithm are left out of the kernel).
+template <bool UOT, int D, bool WFR>
 __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64_t m, int64_t W,
                                           int64_t rt, int64_t ct, uint64_t* __restrict__ mask,
                                           int32_t* __restrict__ row_cnt, double kappa,
-                                          uint64_t (*tile)[64]) {
+                                          uint64_t (*tile)[64], uint64_t (*cand)[kMaskCand]) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
     const int64_t row0 = rt * kMaskRows;
-    double cf[16];
+    const int nrows = (int)(n - row0 < kMaskRows ? n - row0 : kMaskRows);
+    // the wave's 16 words of each row start empty
 #pragma unroll
-    for (int gg = 0; gg < 4; ++gg) {
+    for (int e = lane; e < kMaskRows * 16; e += kWave) tile[e >> 4][wv * 16 + (e & 15)] = 0;
+    const double* __restrict__ rsrc = UOT ? pp.row_bnd : pp.row_fac;
+    const double* __restrict__ csrc = UOT ? pp.col_bnd : pp.col_fac;
+    // the uniform part of shrinkage (0 without it); for the UOT bound with
+    // the bound's margin
+    const double pc = UOT ? pp.shrink_c * (1.0 + 0x1p-30) : pp.shrink_c;
+    // filter scale 2^32 (1 + 2^-40); the constant 2^-900 keeps every entry
+    // with hi = 0 a candidate where the scaled product underflows
+    constexpr double kScale = 0x1p32 * (1.0 + 0x1p-40);
+    const double pcf = pc * kScale + 0x1p-900;
+    // lane r < 16 holds row r's factor, scaled
+    const double rowv = lane < nrows ? rsrc[row0 + lane] * kScale : 0.0;
+    // the cost as a value the compiler sees: without WFR one of the two
+    // squared Euclidean kinds, so the WFR branches fold away
+    ProbParams lp = pp;
+    if constexpr (!WFR)
+        lp.cost = pp.cost == SS_COST_SQEUCLID ? SS_COST_SQEUCLID : SS_COST_SQEUCLID_MAXNORM;
+    uint64_t* const list = cand[wv];
+    int cnt = 0;  // wave-uniform
+    const int64_t g_end = (W + 3) / 4;  // hash groups of 256 columns (4 words)
+    const int64_t g_first = ct * 16 + wv * 4;
+    const int ng = (int)(g_end - g_first < 4 ? (g_end - g_first > 0 ? g_end - g_first : 0) : 4);
+    for (int gg = 0; gg < ng; ++gg) {
+        const int64_t g = g_first + gg;
+        const uint32_t q = (uint32_t)(g * 64 + lane);
+        // column factors of this group; -inf past the last column makes the
+        // filter's bound -inf (or NaN for a zero row factor): never a candidate
+        double cf[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int64_t g = ct * 16 + wv * 4 + gg;
             const int64_t j = 256 * g + 64 * s + lane;
-            cf[gg * 4 + s] = (j < m) ? (UOT ? pp.col_bnd[j] : pp.col_fac[j]) : 0.0;
+            cf[s] = j < m ? csrc[j] : -INFINITY;
         }
-    }
-    for (int r = 0; r < kMaskRows; ++r) {
-        const int64_t i = row0 + r;
-        if (i >= n) break;
-        const double rowf = UOT ? pp.row_bnd[i] : pp.row_fac[i];
-        // the uniform part of shrinkage (0 without it); for the UOT bound with
-        // the bound's margin
-        const double pc = UOT ? pp.shrink_c * (1.0 + 0x1p-30) : pp.shrink_c;
-        uint64_t mine = 0;
-#pragma unroll
-        for (int gg = 0; gg < 4; ++gg) {
-            const int64_t g = ct * 16 + wv * 4 + gg;
-            if (4 * g >= W) continue;
-            const uint32_t q = (uint32_t)(g * 64 + lane);
+        for (int r = 0; r < nrows; ++r) {
+            const int64_t i = row0 + r;
+            const uint32_t lo = __builtin_amdgcn_readlane((int)__double2loint(rowv), r);
+            const uint32_t hi = __builtin_amdgcn_readlane((int)__double2hiint(rowv), r);
+            const double rowf = __hiloint2double((int)hi, (int)lo);
             const Words4 h = philox10(q, (uint32_t)i, pp.problem_index, 0u, pp.k0, pp.k1);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const int64_t j = 256 * g + 64 * s + lane;
+                const bool c = (double)h.w[s] < fma(rowf, cf[s], pcf);
+                const uint64_t bal = __ballot(c);
+                if (bal) {
+                    if (c) {
+                        const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                                  (uint32_t)(bal >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        list[pos] = ((uint64_t)((r << 10) | ((gg * 4 + s) << 6) | lane) << 32) |
+                                    (uint64_t)h.w[s];
+                    }
+                    cnt += __popcll(bal);
+                }
+            }
+            if (cnt <= kMaskCand - 256 && (r + 1 < nrows || gg + 1 < ng)) continue;
+            // ---- decide the listed entries, one per lane (the list was written
+            // by other lanes of this wave: LDS operations of a wave complete in
+            // order; the wait and clobber also keep the compiler's order)
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            for (int base = 0; base < cnt; base += kWave) {
+                const int e = base + lane;
+                if (e >= cnt) break;
+                const uint64_t it = list[e];
+                const uint32_t hw = (uint32_t)it;
+                const int meta = (int)(it >> 32);
+                const int er = meta >> 10, slot = (meta >> 6) & 15, lc = meta & 63;
+                const int es = slot & 3;
+                const int64_t eg = g_first + (slot >> 2);
+                const int64_t ej = 256 * eg + 64 * es + lc;
+                const int64_t ei = row0 + er;
+                const uint32_t eq = (uint32_t)(eg * 64 + lc);
                 bool keep = false;
-                if (j < m) {
-                    const double Pr = rowf * cf[gg * 4 + s];
+                if (ej < m) {
+                    const double Pr = rsrc[ei] * csrc[ej];
                     const double P = Pr + pc;
                     if (!UOT) {
-                        keep = keep_decision(h.w[s], P, q, (uint32_t)i, pp.problem_index, pp.k0,
-                                             pp.k1, s);
-                    } else if ((double)h.w[s] * 0x1p-32 < P) {
-                        // P bounds p* without the cost factor.  Candidates first
-                        // take the cost factor's bound in FP32 (margin 2^-12 for
-                        // the rounding of its argument and of the exponential),
-                        // and only those below it pay for the exact p*.  Where
-                        // the FP32 bound underflows, only hi = 0 can still fall
-                        // below p*, so that case goes to the exact test as well.
-                        // (With the max-normalised cost, C <= 1, the cost factor is
-                        // at least exp(-inv_tau) and the refinement does not pay.)
-                        const double c = sqdist<D>(pp.x + i * pp.d, pp.y + j * pp.d, pp.d);
+                        keep = keep_decision(hw, P, eq, (uint32_t)ei, pp.problem_index, pp.k0, pp.k1,
+                                             es);
+                    } else if ((double)hw * 0x1p-32 < P) {
+                        // P bounds p* without the cost factor.  Candidates first take
+                        // the cost factor's bound in FP32 (margin 2^-12 for the
+                        // rounding of its argument and of the exponential), and only
+                        // those below it pay for the exact p*.  Where the FP32 bound
+                        // underflows, only hi = 0 can still fall below p*, so that
+                        // case goes to the exact test as well.  (With the
+                        // max-normalised cost, C <= 1, the cost factor is at least
+                        // exp(-inv_tau) and the refinement does not pay.)
+                        const double c = sqdist<D>(pp.x + ei * pp.d, pp.y + ej * pp.d, pp.d);
                         bool exact = true;
-                        if (pp.cost != SS_COST_SQEUCLID_MAXNORM) {
-                            const double t = uot_bound_exponent(pp, c);
-                            const double e =
-                                t < 200.0 ? (double)__builtin_amdgcn_exp2f(-(float)t) : 0.0;
-                            const double Pt = Pr * e * (1.0 + 0x1p-12) + pc;
-                            exact = (double)h.w[s] * 0x1p-32 < Pt || h.w[s] == 0u;
+                        if (lp.cost != SS_COST_SQEUCLID_MAXNORM) {
+                            const double t = uot_bound_exponent(lp, c);
+                            const double ex = t < 200.0 ? (double)__builtin_amdgcn_exp2f(-(float)t) : 0.0;
+                            const double Pt = Pr * ex * (1.0 + 0x1p-12) + pc;
+                            exact = (double)hw * 0x1p-32 < Pt || hw == 0u;
                         }
                         if (exact) {
-                            const double q_ij = uot_q_of(pp, c, i, j);
+                            const double q_ij = uot_q_of(lp, c, ei, ej);
                             const double pst = fmin(1.0, kappa * q_ij + pp.shrink_c);
-                            keep = keep_decision(h.w[s], pst, q, (uint32_t)i, pp.problem_index,
-                                                 pp.k0, pp.k1, s);
+                            keep = keep_decision(hw, pst, eq, (uint32_t)ei, pp.problem_index, pp.k0,
+                                                 pp.k1, es);
                         }
                     }
                 }
-                const uint64_t word = __ballot(keep);
-                if (lane == gg * 4 + s) mine = word;
+                if (keep)
+                    atomicOr((unsigned long long*)&tile[er][wv * 16 + slot], 1ull << lc);
             }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // list slots are rewritten next
+            cnt = 0;
         }
-        if (lane < 16) tile[r][wv * 16 + lane] = mine;
     }
     __syncthreads();
 #pragma unroll
@@ -691,34 +757,59 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
     }
 }
 
+// Six waves per SIMD (the LDS of six blocks fills a compute unit): the hash
+// loop then fits in 80 registers; only the decision phase reloads a few
+// spilled values.  The WFR decision (FP64 cosine and logarithm) needs more,
+// so its kernel keeps the compiler's register count instead of spilling in
+// the hash loop.
 template <bool UOT, int D>
-__global__ __launch_bounds__(256) void k_mask(ProbParams pp, int64_t n, int64_t m, int64_t W,
-                                              int64_t ncol_tiles, uint64_t* __restrict__ mask,
-                                              int32_t* __restrict__ row_cnt,
-                                              const double* __restrict__ stats) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_mask(
+    ProbParams pp, int64_t n, int64_t m, int64_t W, int64_t ncol_tiles, uint64_t* __restrict__ mask,
+    int32_t* __restrict__ row_cnt, const double* __restrict__ stats) {
     __shared__ uint64_t tile[kMaskRows][64];
+    __shared__ uint64_t cand[4][kMaskCand];
     const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
     const double kappa = UOT ? pp.shrink_w * (pp.s / stats[ST_Z]) : 0.0;
-    mask_tile<UOT, D>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile);
+    mask_tile<UOT, D, false>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile, cand);
 }
 
-template <bool UOT, int D>
+template <int D>
+__global__ __launch_bounds__(256) void k_mask_wfr(ProbParams pp, int64_t n, int64_t m, int64_t W,
+                                                  int64_t ncol_tiles, uint64_t* __restrict__ mask,
+                                                  int32_t* __restrict__ row_cnt,
+                                                  const double* __restrict__ stats) {
+    __shared__ uint64_t tile[kMaskRows][64];
+    __shared__ uint64_t cand[4][kMaskCand];
+    const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
+    const double kappa = pp.shrink_w * (pp.s / stats[ST_Z]);
+    mask_tile<true, D, true>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile, cand);
+}
+
+template <bool UOT, int D, bool WFR>
 static void run_mask(const ProbParams& pp, int64_t n, int64_t m, uint64_t* mask, int32_t* row_cnt,
                      const double* stats, hipStream_t st) {
     const int64_t W = (m + 63) / 64;
     const int64_t nct = (W + 63) / 64;
     const int64_t nrt = (n + kMaskRows - 1) / kMaskRows;
-    hipLaunchKernelGGL((k_mask<UOT, D>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n, m, W,
-                       nct, mask, row_cnt, stats);
+    const dim3 grid((unsigned)(nct * nrt));
+    if constexpr (WFR)
+        hipLaunchKernelGGL((k_mask_wfr<D>), grid, dim3(256), 0, st, pp, n, m, W, nct, mask,
+                           row_cnt, stats);
+    else
+        hipLaunchKernelGGL((k_mask<UOT, D>), grid, dim3(256), 0, st, pp, n, m, W, nct, mask,
+                           row_cnt, stats);
 }
 
 template <int D>
 static void run_mask_d(const ProbParams& pp, int64_t n, int64_t m, uint64_t* mask,
                        int32_t* row_cnt, const double* stats, hipStream_t st) {
     if (pp.uot)
-        run_mask<true, D>(pp, n, m, mask, row_cnt, stats, st);
+        if (pp.cost == kCostWfr)
+            run_mask<true, D, true>(pp, n, m, mask, row_cnt, stats, st);
+        else
+            run_mask<true, D, false>(pp, n, m, mask, row_cnt, stats, st);
     else
-        run_mask<false, 2>(pp, n, m, mask, row_cnt, stats, st);  // OT never reads coordinates
+        run_mask<false, 2, false>(pp, n, m, mask, row_cnt, stats, st);  // OT never reads coordinates
 }
 
 hipError_t launch_mask(const ProbParams& pp, int64_t n, int64_t m, uint64_t* mask,
@@ -1164,6 +1255,7 @@ __global__ __launch_bounds__(1024) void k_b_prep(BatchArgs A) {
 
 __global__ __launch_bounds__(256) void k_b_mask(BatchArgs A) {
     __shared__ uint64_t tile[kMaskRows][64];
+    __shared__ uint64_t cand[4][kMaskCand];
     const int k = owner_of(A.tile_mask, A.count, blockIdx.x);
     const BProb P = A.prob[k];
     const int64_t t = blockIdx.x - A.tile_mask[k];
@@ -1179,8 +1271,8 @@ __global__ __launch_bounds__(256) void k_b_mask(BatchArgs A) {
     pp.problem_index = P.pidx;
     pp.k0 = A.k0;
     pp.k1 = A.k1;
-    mask_tile<false, 2>(pp, P.n, P.m, P.W, t / nct, t % nct, A.mask + P.mo, A.row_cnt + P.xo, 0.0,
-                        tile);
+    mask_tile<false, 2, false>(pp, P.n, P.m, P.W, t / nct, t % nct, A.mask + P.mo, A.row_cnt + P.xo, 0.0,
+                        tile, cand);
 }
 
 __global__ __launch_bounds__(256) void k_b_transpose(BatchArgs A) {
