@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-wfr", action="store_true")
     ap.add_argument("--wfr-only", action="store_true", help="only the WFR workload")
     ap.add_argument("--wfr-n", type=int, default=65536)
+    ap.add_argument("--no-divergence", action="store_true")
+    ap.add_argument("--divergence-only", action="store_true")
+    ap.add_argument("--divergence-n", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -305,6 +308,46 @@ def wfr_bench(n: int, steps: int, dense: bool) -> dict:
     return out
 
 
+def divergence_bench(n: int, steps: int, cpu: bool) -> dict:
+    """Sinkhorn divergence with gradients (the generative-modelling section's
+    regulariser): n latent codes in R^3 against n prior draws, uniform
+    weights, eps = 1 on the unnormalised squared distance, s = 10 s0(n) per
+    term, log-domain FP32, tol 1e-6; three Spar-Sink solves plus the envelope
+    gradients per evaluation."""
+    import torch
+
+    from paper_2306_06581_amd import api as A
+    from paper_2306_06581_amd import workloads as W
+
+    p = W.latent_pair(n, d=3, seed=0, eps=1.0)
+    prob = A.Problem(p.x, p.y, p.a, p.b)
+    kw = dict(eps=p.eps, s=p.s, seed=p.seed, tol=1e-6, max_iter=5000, precision="f32_log")
+    A.sinkhorn_divergence(prob, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [A.sinkhorn_divergence(prob, **kw) for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    r = res[-1]
+    out = {"workload": f"latent_pair n=m={n} d=3 eps=1 s=10 s0(n) f32_log tol=1e-6, with gradients",
+           "ms_per_evaluation": ms, "status": r.status, "value": r.value,
+           "value_sparse": r.value_sparse, "iters": [r.iters_xy, r.iters_xx, r.iters_yy],
+           "nnz": r.nnz}
+    if cpu:
+        from oracle import divergence_oracle as D
+        from oracle import sparsink_oracle as O
+        t0 = time.perf_counter()
+        o = D.sinkhorn_divergence(p.x, p.a, p.y, p.b,
+                                  O.Options(eps=p.eps, s=p.s, seed=p.seed, cost="plain", tol=1e-6,
+                                            max_iter=5000, log_domain=True))
+        out["cpu_oracle"] = {"s": time.perf_counter() - t0, "cores": 1, "kind": "oracle",
+                             "value_sparse": o.value_sparse,
+                             "grad_rel_l2_vs_gpu": float(
+                                 np.linalg.norm(o.grad_x - r.grad_x.cpu().numpy())
+                                 / np.linalg.norm(o.grad_x))}
+    return out
+
+
 def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
     """The FP64 oracle timed on a bounded sample of the same workload."""
     import numpy as np
@@ -366,6 +409,12 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"batched": batched_bench(args.batch_count, args.steps)}))
+        return
+    if args.divergence_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"divergence": divergence_bench(args.divergence_n, args.steps,
+                                                         not args.no_cpu)}))
         return
     if args.wfr_only:
         import torch
@@ -481,6 +530,8 @@ def main():
         out["ibp"] = ibp_bench(args.ibp_n, args.steps, not args.no_cpu)
     if not args.no_wfr:
         out["wfr"] = wfr_bench(args.wfr_n, args.steps, not args.no_dense)
+    if not args.no_divergence:
+        out["divergence"] = divergence_bench(args.divergence_n, args.steps, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, r.iters, args.precision == "f32_log")
     print(json.dumps(out))
