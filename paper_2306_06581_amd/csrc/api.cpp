@@ -275,12 +275,33 @@ struct Timer {
     }
 };
 
+// Two pinned host slots for the loop state per host thread, kept for the
+// thread's lifetime (a copy into pinned memory is asynchronous, so the host
+// can enqueue the next replay before it reads the previous one's state);
+// nullptr if pinned memory is unavailable.
+static IterState* pinned_state_slots() {
+    thread_local IterState* slots = nullptr;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        void* p = nullptr;
+        if (hipHostMalloc(&p, 2 * sizeof(IterState), hipHostMallocDefault) == hipSuccess)
+            slots = (IterState*)p;
+    }
+    return slots;
+}
+
 // Runs the Sinkhorn loop: `iter(k, stream)` enqueues iteration k (its
 // ping-pong parity is k & 1).  With graph_iters > 0 an even number of
-// iterations is captured once and replayed; the host polls the 8-byte stop
-// state after each replay.
+// iterations is captured once and replayed.  Replays are pipelined: replay
+// r + 1 is enqueued before the host reads the stop state that replay r copies
+// into a pinned slot, so the device never waits for the host between
+// replays.  The replay in flight when the stop is seen runs its launches as
+// no-ops (they return at entry); the stream is synchronised before return.
+// `tol` (the stop tolerance, or 0) only steers the lookahead.
 int run_loop(const std::function<hipError_t(int, hipStream_t)>& iter, int graph_iters,
-             int max_iter, IterState* d_state, IterState* h_state, hipStream_t stream) {
+             int max_iter, double tol, IterState* d_state, IterState* h_state,
+             hipStream_t stream) {
     const int total = max_iter + 1;  // the last launch only closes the residual
     if (graph_iters > 0) {
         int G = graph_iters + (graph_iters & 1);
@@ -296,14 +317,59 @@ int run_loop(const std::function<hipError_t(int, hipStream_t)>& iter, int graph_
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         int rc = SS_OK;
         if (e != hipSuccess) rc = fail(SS_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-        for (int done = 0; rc == SS_OK && done < total; done += G) {
-            e = hipGraphLaunch(exec, stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(h_state, d_state, sizeof(IterState), hipMemcpyDeviceToHost, stream);
+        const int nrep = (total + G - 1) / G;
+        IterState* slot = pinned_state_slots();
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        bool piped = slot != nullptr;
+        for (auto& x : ev)
+            if (piped && hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) piped = false;
+        if (rc == SS_OK && piped) {
+            auto enqueue = [&](int r) -> hipError_t {
+                hipError_t er = hipGraphLaunch(exec, stream);
+                if (er == hipSuccess)
+                    er = hipMemcpyAsync(&slot[r & 1], d_state, sizeof(IterState),
+                                        hipMemcpyDeviceToHost, stream);
+                if (er == hipSuccess) er = hipEventRecord(ev[r & 1], stream);
+                return er;
+            };
+            // Lookahead is skipped for the replay after the one the residual
+            // trend says will stop: its launches would all be no-ops.  The
+            // trend (geometric decay of the latest err over the last two
+            // replays read) only schedules replays; the stop test stays on
+            // the device.
+            double e1 = -1.0, e2 = -1.0;  // proxies after the last two replays read
+            auto likely_last = [&]() {
+                if (!(tol > 0.0) || !(e1 > 0.0) || !(e2 > e1)) return false;
+                const double reps = std::log(tol / e1) / std::log(e1 / e2);
+                return reps <= 1.0;
+            };
+            int queued = 0;
+            e = enqueue(queued++);
+            for (int r = 0; e == hipSuccess && r < nrep; ++r) {
+                if (queued == r + 1 && queued < nrep && !likely_last()) e = enqueue(queued++);
+                if (e == hipSuccess) e = hipEventSynchronize(ev[r & 1]);
+                if (e != hipSuccess) break;
+                *h_state = slot[r & 1];
+                if (h_state->stop_iter != 0 || h_state->nonfinite != 0) break;
+                e2 = e1;
+                e1 = h_state->err_last;
+                if (queued == r + 1 && queued < nrep) e = enqueue(queued++);
+            }
             if (e == hipSuccess) e = hipStreamSynchronize(stream);
             if (e != hipSuccess) rc = fail(SS_E_HIP, "loop failed: %s", hipGetErrorString(e));
-            if (h_state->stop_iter != 0 || h_state->nonfinite != 0) break;
+        } else {
+            for (int done = 0; rc == SS_OK && done < total; done += G) {
+                e = hipGraphLaunch(exec, stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(h_state, d_state, sizeof(IterState), hipMemcpyDeviceToHost,
+                                       stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(stream);
+                if (e != hipSuccess) rc = fail(SS_E_HIP, "loop failed: %s", hipGetErrorString(e));
+                if (h_state->stop_iter != 0 || h_state->nonfinite != 0) break;
+            }
         }
+        for (auto& x : ev)
+            if (x) (void)hipEventDestroy(x);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         (void)hipStreamDestroy(cs);
@@ -745,7 +811,7 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     const int G = O->graph_iters == 0 ? 16 : O->graph_iters;
     IterState hs;
     memset(&hs, 0, sizeof hs);
-    rc = run_loop(iter, G, O->max_iter, d_state, &hs, c.st);
+    rc = run_loop(iter, G, O->max_iter, O->tol, d_state, &hs, c.st);
     if (rc != SS_OK) return rc;
     tm.mark(3, c.st);
     if (hs.nonfinite) return fail(SS_E_NONFINITE, "a scaling became NaN or Inf");
@@ -1685,7 +1751,7 @@ int dense_sinkhorn(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     const int G = O->graph_iters == 0 ? 8 : O->graph_iters;
     IterState hs;
     memset(&hs, 0, sizeof hs);
-    rc = run_loop(iter, G, O->max_iter, d_state, &hs, c.st);
+    rc = run_loop(iter, G, O->max_iter, O->tol, d_state, &hs, c.st);
     if (rc != SS_OK) return rc;
     tm.mark(3, c.st);
     if (hs.nonfinite) return fail(SS_E_NONFINITE, "a scaling became NaN or Inf");
@@ -2018,7 +2084,7 @@ int spar_ibp(const ss_ibp_problem* P, const ss_options* O, double* q_out, void* 
     const int G = O->graph_iters == 0 ? 16 : O->graph_iters;
     IterState hs;
     memset(&hs, 0, sizeof hs);
-    rc = run_loop(iter, G, O->max_iter, A.st, &hs, c.st);
+    rc = run_loop(iter, G, O->max_iter, O->tol, A.st, &hs, c.st);
     if (rc != SS_OK) return rc;
     tm.mark(2, c.st);
     if (hs.nonfinite) return fail(SS_E_NONFINITE, "the barycenter became NaN or Inf");

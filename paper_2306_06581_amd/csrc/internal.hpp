@@ -18,7 +18,7 @@ struct IterState {
     double err_col;      // column residual of the previous iterate (marginal rule)
     double err_row;      // |du| of the current iteration (delta rule)
     double err_final;    // err of the returned iterate
-    double pad;
+    double err_last;     // err of the latest iterate tested (the host's replay schedule)
 };
 
 // Grid cap of the iteration kernels (grid-stride over lines): 8 blocks per CU.

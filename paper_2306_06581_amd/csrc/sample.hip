@@ -852,19 +852,28 @@ __device__ __forceinline__ void transpose_tile(const uint64_t* __restrict__ mask
     uint64_t out[4][kTrRowBlocks];
     const int lr = threadIdx.x >> 2;          // row of the tile this thread loads
     const int lq = (threadIdx.x & 3) * 4;     // first of its 4 words
-#pragma unroll
-    for (int rho = 0; rho < kTrRowBlocks; ++rho) {
+    // the words of row block rho + 1 are in flight while block rho is
+    // transposed: the barriers wait for LDS only, not for those loads
+    uint64_t nx[4];
+    auto load_block = [&](int rho) __attribute__((always_inline)) {
         const int64_t I = rt * kTrRowBlocks + rho;
         const int64_t i = 64 * I + lr;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t wc = ct * kTrWordCols + lq + q;
-            tile[lr][lq + q] = (I < Wn && i < n && wc < W) ? mask[i * W + wc] : 0ull;
+            nx[q] = (I < Wn && i < n && wc < W) ? mask[i * W + wc] : 0ull;
         }
-        __syncthreads();
+    };
+    load_block(0);
+#pragma unroll
+    for (int rho = 0; rho < kTrRowBlocks; ++rho) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tile[lr][lq + q] = nx[q];
+        if (rho + 1 < kTrRowBlocks) load_block(rho + 1);
+        lds_barrier();
 #pragma unroll
         for (int k = 0; k < 4; ++k) out[k][rho] = transpose64(tile[lane][wv * 4 + k]);
-        __syncthreads();
+        lds_barrier();
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1028,37 +1037,42 @@ __device__ __forceinline__ void store_value(void* val, int64_t pos, double v, do
 
 // One line, by one wave: `row` is the line's mask words, `base` its first
 // entry slot, `line` its index in the problem; indices are written as IdxT.
+// The words are read 16 per lane ahead of the prefix-popcount (one load per
+// word would leave the wave waiting on each); entries past the queue's
+// capacity take their values in a second scan of the words.
 template <int ROLE, bool UOT, int PREC, int D, typename IdxT>
 __device__ __forceinline__ void fill_line(const ProbParams& pp, double kappa, bool active,
                                           const uint64_t* __restrict__ row, int64_t line,
                                           int64_t words, int64_t base, IdxT* __restrict__ idx,
                                           void* __restrict__ val, int64_t cap, int32_t* queue) {
+    constexpr int NB = 16;  // words per lane read ahead
     const int lane = threadIdx.x & (kWave - 1);
     int64_t run = base;
-    for (int64_t w0 = 0; w0 < words; w0 += kWave) {
-        const int64_t widx = w0 + lane;
-        uint64_t word = (active && widx < words) ? row[widx] : 0ull;
-        const int c = __popcll(word);
-        const int incl = wave_inclusive_scan(c);
-        int64_t pos = run + (incl - c);
-        while (word) {
-            const int b = __ffsll((unsigned long long)word) - 1;
-            word &= word - 1;
-            const int64_t other = 64 * widx + b;
-            const int64_t local = pos - base;
-            if (pos < cap) idx[pos] = (IdxT)other;
-            if (local < kFillQueue) {
-                queue[local] = (int32_t)other;
-            } else if (pos < cap) {
-                const int64_t i = ROLE == 0 ? line : other;
-                const int64_t j = ROLE == 0 ? other : line;
-                double lv;
-                const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
-                store_value<PREC>(val, pos, v, lv);
-            }
-            ++pos;
+    for (int64_t g0 = 0; g0 < words; g0 += NB * kWave) {
+        uint64_t wd[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int64_t widx = g0 + k * kWave + lane;
+            wd[k] = (active && widx < words) ? row[widx] : 0ull;
         }
-        run += __shfl(incl, kWave - 1, kWave);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            uint64_t word = wd[k];
+            const int64_t widx = g0 + k * kWave + lane;
+            const int c = __popcll(word);
+            const int incl = wave_inclusive_scan(c);
+            int64_t pos = run + (incl - c);
+            while (word) {
+                const int b = __ffsll((unsigned long long)word) - 1;
+                word &= word - 1;
+                const int64_t other = 64 * widx + b;
+                if (pos < cap) idx[pos] = (IdxT)other;
+                const int64_t local = pos - base;
+                if (local < kFillQueue) queue[local] = (int32_t)other;
+                ++pos;
+            }
+            run += __shfl(incl, kWave - 1, kWave);
+        }
     }
     __syncthreads();
     const int64_t cnt = run - base;
@@ -1072,6 +1086,30 @@ __device__ __forceinline__ void fill_line(const ProbParams& pp, double kappa, bo
         double lv;
         const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
         store_value<PREC>(val, pos, v, lv);
+    }
+    if (cnt > kFillQueue) {  // wave-uniform
+        int64_t run2 = base;
+        for (int64_t w0 = 0; w0 < words; w0 += kWave) {
+            const int64_t widx = w0 + lane;
+            uint64_t word = (active && widx < words) ? row[widx] : 0ull;
+            const int c = __popcll(word);
+            const int incl = wave_inclusive_scan(c);
+            int64_t pos = run2 + (incl - c);
+            while (word) {
+                const int b = __ffsll((unsigned long long)word) - 1;
+                word &= word - 1;
+                if (pos - base >= kFillQueue && pos < cap) {
+                    const int64_t other = 64 * widx + b;
+                    const int64_t i = ROLE == 0 ? line : other;
+                    const int64_t j = ROLE == 0 ? other : line;
+                    double lv;
+                    const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
+                    store_value<PREC>(val, pos, v, lv);
+                }
+                ++pos;
+            }
+            run2 += __shfl(incl, kWave - 1, kWave);
+        }
     }
 }
 

@@ -112,6 +112,7 @@ __device__ __forceinline__ void loop_decide(IterState* st, int role, int margina
         st->cnt_u = t;
     }
     if (decide) {
+        st->err_last = err;
         if (err_hist) err_hist[t - 2] = err;
         if (err <= tol || t - 1 >= max_iter) {
             st->err_final = err;
