@@ -855,13 +855,26 @@ __device__ __forceinline__ void transpose_tile(const uint64_t* __restrict__ mask
     // the words of row block rho + 1 are in flight while block rho is
     // transposed: the barriers wait for LDS only, not for those loads
     uint64_t nx[4];
+    // a row's 4 words in two 16-byte loads when they all exist (an aligned
+    // base and W even keep them 16-byte aligned)
+    const bool wfull = ((uintptr_t)mask & 15) == 0 && (W & 1) == 0 &&
+                       ct * kTrWordCols + lq + 4 <= W;
     auto load_block = [&](int rho) __attribute__((always_inline)) {
         const int64_t I = rt * kTrRowBlocks + rho;
         const int64_t i = 64 * I + lr;
+        if (wfull && I < Wn && i < n) {
+            const ulonglong2* src = (const ulonglong2*)(mask + i * W + ct * kTrWordCols + lq);
+            const ulonglong2 a = src[0], b = src[1];
+            nx[0] = a.x;
+            nx[1] = a.y;
+            nx[2] = b.x;
+            nx[3] = b.y;
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t wc = ct * kTrWordCols + lq + q;
-            nx[q] = (I < Wn && i < n && wc < W) ? mask[i * W + wc] : 0ull;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t wc = ct * kTrWordCols + lq + q;
+                nx[q] = (I < Wn && i < n && wc < W) ? mask[i * W + wc] : 0ull;
+            }
         }
     };
     load_block(0);
@@ -881,12 +894,26 @@ __device__ __forceinline__ void transpose_tile(const uint64_t* __restrict__ mask
         const int64_t j = 64 * wc + lane;
         if (j >= m) continue;
         int cnt = 0;
+        if (((uintptr_t)maskT & 15) == 0 && (Wn & 1) == 0 &&
+            rt * kTrRowBlocks + kTrRowBlocks <= Wn) {
+            // the column's 8 words in four 16-byte stores (aligned base, Wn even)
+            ulonglong2* dst = (ulonglong2*)(maskT + j * Wn + rt * kTrRowBlocks);
 #pragma unroll
-        for (int rho = 0; rho < kTrRowBlocks; ++rho) {
-            const int64_t I = rt * kTrRowBlocks + rho;
-            if (I < Wn) {
-                maskT[j * Wn + I] = out[k][rho];
-                cnt += __popcll(out[k][rho]);
+            for (int h = 0; h < kTrRowBlocks / 2; ++h) {
+                ulonglong2 t;
+                t.x = out[k][2 * h];
+                t.y = out[k][2 * h + 1];
+                dst[h] = t;
+                cnt += __popcll(t.x) + __popcll(t.y);
+            }
+        } else {
+#pragma unroll
+            for (int rho = 0; rho < kTrRowBlocks; ++rho) {
+                const int64_t I = rt * kTrRowBlocks + rho;
+                if (I < Wn) {
+                    maskT[j * Wn + I] = out[k][rho];
+                    cnt += __popcll(out[k][rho]);
+                }
             }
         }
         if (cnt) atomicAdd(&col_cnt[j], cnt);
@@ -1077,15 +1104,20 @@ __device__ __forceinline__ void fill_line(const ProbParams& pp, double kappa, bo
     __syncthreads();
     const int64_t cnt = run - base;
     const int64_t nq = cnt < kFillQueue ? cnt : kFillQueue;
-    for (int64_t e = lane; e < nq; e += kWave) {
-        const int64_t pos = base + e;
-        if (pos >= cap) break;
-        const int64_t other = queue[e];
-        const int64_t i = ROLE == 0 ? line : other;
-        const int64_t j = ROLE == 0 ? other : line;
-        double lv;
-        const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
-        store_value<PREC>(val, pos, v, lv);
+    // two entries per lane at a time, so that their loads overlap
+    const int64_t nv = cap - base < nq ? (cap - base > 0 ? cap - base : 0) : nq;
+    for (int64_t e = lane; e < nv; e += 2 * kWave) {
+        const int64_t e2 = e + kWave;
+        const bool two = e2 < nv;
+        const int64_t oa = queue[e];
+        const int64_t ob = two ? queue[e2] : oa;
+        double la, lb;
+        const double va = entry_value<UOT, D>(pp, kappa, ROLE == 0 ? line : oa,
+                                              ROLE == 0 ? oa : line, &la);
+        const double vb = entry_value<UOT, D>(pp, kappa, ROLE == 0 ? line : ob,
+                                              ROLE == 0 ? ob : line, &lb);
+        store_value<PREC>(val, base + e, va, la);
+        if (two) store_value<PREC>(val, base + e2, vb, lb);
     }
     if (cnt > kFillQueue) {  // wave-uniform
         int64_t run2 = base;
