@@ -251,7 +251,13 @@ int ss_batch_workspace_size(const ss_batch *batch, const ss_options *opts, size_
 /* Solves every problem of the batch on `stream`: one launch per sampling
  * stage over all problems, one persistent iteration launch in which every
  * problem runs Alg. 1 to its own tolerance, one objective launch; the device
- * part is captured in a hipGraph and replayed once.  `schedule` NULL picks
+ * part is captured in a hipGraph and replayed once.  With max_iter > 64 the
+ * persistent launch first runs at most 64 iterations; if one or two problems
+ * are then still above tol, each continues on the single-problem solver
+ * (spar_sink_ot's path, the same sketch) from its iterate for the remaining
+ * max_iter - 64 iterations (its outs[k] is then that solve's result with
+ * iters counted from the start); with more such problems the persistent
+ * launch is run again from the start to max_iter.  `schedule` NULL picks
  * the schedule with ss_autotune_batched (cached per process for batches of
  * the same precision and size class).  outs: host array [count]; each entry
  * is filled as by spar_sink_ot (z_norm 0; stage times are those of the whole

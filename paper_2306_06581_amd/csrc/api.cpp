@@ -899,6 +899,7 @@ struct BLayout {
     size_t prob, stat, tile_cmax, tile_mask, tile_tr, row_off, col_off, order, queue, gstats;
     size_t row_fac, col_fac, a_eff, b_eff, mask, maskT, row_cnt, col_cnt, row_ptr, col_ptr, scan;
     size_t col_idx, row_idx, val, val_t, u, v;
+    size_t hlog, handoff, handoff_bytes;  // straggler hand-off: log scalings, solver workspace
     size_t total;
     int64_t rows, cols, cap, nt_cmax, nt_mask, nt_tr;
     int nmax, mmax;
@@ -991,6 +992,21 @@ BLayout bplan(const ss_batch* B, const ss_options* O) {
     L.val_t = take((size_t)(L.cap + 64) * es);
     L.u = take((size_t)L.rows * es);
     L.v = take((size_t)L.cols * es);
+    // hand-off of stragglers to the single-problem solver: its workspace for
+    // the largest sides and budget of the batch (every region grows with n,
+    // m and s) and the log scalings that start it
+    double smax = 0.0;
+    for (int k = 0; k < K; ++k) smax = B->s[k] > smax ? B->s[k] : smax;
+    ss_problem hp;
+    memset(&hp, 0, sizeof hp);
+    hp.n = L.nmax;
+    hp.m = L.mmax;
+    hp.d = B->d;
+    ss_options ho = *O;
+    ho.s = smax;
+    L.hlog = take((size_t)(L.nmax + L.mmax) * 8);
+    L.handoff_bytes = plan(&hp, &ho).total;
+    L.handoff = take(L.handoff_bytes);
     L.total = off;
     return L;
 }
@@ -1477,6 +1493,18 @@ int ss_autotune_batched(const ss_batch* B, const ss_options* O, void* ws, size_t
     return batch_autotune(c, best, cand_ms, ncand);
 }
 
+}  // extern "C"
+
+// Straggler hand-off: iterations of the batch loop before stragglers are
+// counted, and the most stragglers handed to the single-problem solver (one
+// problem there takes every compute unit for (iters - kHandoffIters) x ~10
+// us; one block of the batch loop takes ~50 us an iteration at n = 4096, so a
+// hand-off pays while only a few problems remain).
+constexpr int kHandoffIters = 64;
+constexpr int kHandoffMax = 2;
+
+extern "C" {
+
 int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule* schedule, void* ws,
                       size_t ws_bytes, void* stream, ss_result* outs) {
     if (!outs) return fail(SS_E_INVALID_ARG, "outs must not be NULL");
@@ -1519,12 +1547,36 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
         }
     }
     tm.mark(2, c.st);
-    HIP_TRY(run_captured([&](hipStream_t s) { return batch_iterate(c, c.ia, sc, s); }, c.st));
+    // The loop runs at most kHandoffIters iterations first.  When at most
+    // kHandoffMax problems are still short of the tolerance, each continues
+    // on the single-problem solver (every compute unit on one problem) from
+    // its current iterate, with the same sketch; otherwise the batch loop is
+    // run again from the start to max_iter.
+    const int K = B->count;
+    std::vector<int> strag;
+    if (O->max_iter > kHandoffIters) {
+        BIterArgs ia = c.ia;
+        ia.max_iter = kHandoffIters;
+        HIP_TRY(run_captured([&](hipStream_t s) { return batch_iterate(c, ia, sc, s); }, c.st));
+        std::vector<BStat> st0(K);
+        HIP_TRY(hipMemcpyAsync(st0.data(), at<void>(ws, c.L.stat), (size_t)K * sizeof(BStat),
+                               hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        for (int k = 0; k < K; ++k)
+            if (st0[k].status == SS_NOT_CONVERGED && st0[k].iters == kHandoffIters)
+                strag.push_back(k);
+        if ((int)strag.size() > kHandoffMax) {
+            strag.clear();
+            HIP_TRY(run_captured([&](hipStream_t s) { return batch_iterate(c, c.ia, sc, s); },
+                                 c.st));
+        }
+    } else {
+        HIP_TRY(run_captured([&](hipStream_t s) { return batch_iterate(c, c.ia, sc, s); }, c.st));
+    }
     tm.mark(3, c.st);
     HIP_TRY(run_captured(
         [&](hipStream_t s) { return launch_batch_objective(O->precision, B->count, c.oa, s); }, c.st));
     tm.mark(4, c.st);
-    const int K = B->count;
     std::vector<BStat> stat(K);
     double gst[ST_COUNT];
     int64_t tot[2];
@@ -1567,6 +1619,61 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
         R.t_obj_ms = t_obj;
         if (S.status < 0 && (worst >= 0)) worst = S.status;
         if (S.status == SS_NOT_CONVERGED && worst == SS_OK) worst = SS_NOT_CONVERGED;
+    }
+    // hand-offs: the single-problem solver continues each straggler from its
+    // iterate (log u, log v of the batch loop) for the remaining iterations
+    float t_hand = 0.f;
+    if (!strag.empty()) {
+        Timer th;
+        th.mark(0, c.st);
+        for (int k : strag) {
+            const BProb& bp = c.H.prob[k];
+            double* lu = at<double>(ws, c.L.hlog);
+            double* lv = lu + c.L.nmax;
+            const int prec = O->precision == SS_F64 ? P_F64 : P_F32;
+            const size_t es = O->precision == SS_F64 ? 8 : 4;
+            HIP_TRY(launch_batch_log_scaling(prec, at<char>(ws, c.L.u) + bp.xo * es, lu, bp.n, c.st));
+            HIP_TRY(launch_batch_log_scaling(prec, at<char>(ws, c.L.v) + bp.yo * es, lv, bp.m, c.st));
+            ss_problem hp;
+            memset(&hp, 0, sizeof hp);
+            hp.n = bp.n;
+            hp.m = bp.m;
+            hp.d = B->d;
+            hp.x = B->x + bp.xo * B->d;
+            hp.y = B->y + bp.yo * B->d;
+            hp.a = B->a + bp.xo;
+            hp.b = B->b + bp.yo;
+            hp.problem_index = bp.pidx;
+            ss_options ho = *O;
+            ho.s = B->s[k];
+            ho.max_iter = O->max_iter - kHandoffIters;
+            ho.init_log_u = lu;
+            ho.init_log_v = lv;
+            ho.u_out = O->u_out ? O->u_out + bp.xo : nullptr;
+            ho.v_out = O->v_out ? O->v_out + bp.yo : nullptr;
+            ho.err_hist = nullptr;
+            ho.block_threads = 0;
+            ho.graph_iters = 0;
+            ss_result R;
+            memset(&R, 0, sizeof R);
+            const int hr = spar_sink_impl(&hp, &ho, at<void>(ws, c.L.handoff), c.L.handoff_bytes,
+                                          c.st, &R, false);
+            if (hr < 0) return fail(hr, "problem %d: hand-off to the single-problem solver failed", k);
+            R.iters += kHandoffIters;
+            R.t_prep_ms = outs[k].t_prep_ms;
+            R.t_sample_ms = outs[k].t_sample_ms;
+            R.t_obj_ms = outs[k].t_obj_ms;
+            outs[k] = R;
+        }
+        th.mark(1, c.st);
+        HIP_TRY(hipStreamSynchronize(c.st));
+        t_hand = th.ms(0, 1);
+    }
+    worst = SS_OK;
+    for (int k = 0; k < K; ++k) {
+        outs[k].t_iter_ms = t_iter + t_hand;
+        if (outs[k].status < 0 && worst >= 0) worst = outs[k].status;
+        if (outs[k].status == SS_NOT_CONVERGED && worst == SS_OK) worst = SS_NOT_CONVERGED;
     }
     if (worst < 0) return fail(worst, "a problem of the batch failed: %s", "see outs[k].status");
     return worst;

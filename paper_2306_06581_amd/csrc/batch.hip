@@ -298,4 +298,20 @@ hipError_t launch_batch_objective(int precision, int count, const BObjArgs& a, h
     return hipGetLastError();
 }
 
+__global__ void k_b_log_scaling(int precision, const void* __restrict__ y,
+                                double* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = precision == P_F64 ? ((const double*)y)[i] : (double)((const float*)y)[i];
+    out[i] = log(v);
+}
+
+hipError_t launch_batch_log_scaling(int precision, const void* y, double* out, int64_t n,
+                                    hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_log_scaling, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       precision, y, out, n);
+    return hipGetLastError();
+}
+
 }  // namespace ss

@@ -465,6 +465,9 @@ int batch_iter_grid(int precision, int lanes, int block, int nmax, int mmax);
 hipError_t launch_batch_iterate(int precision, int lanes, int block, int grid, const BIterArgs& a,
                                 hipStream_t st);
 hipError_t launch_batch_objective(int precision, int count, const BObjArgs& a, hipStream_t st);
+// out[i] = log y[i] (y FP64 or FP32 by precision): a batch iterate as a warm start.
+hipError_t launch_batch_log_scaling(int precision, const void* y, double* out, int64_t n,
+                                    hipStream_t st);
 
 // ---- mlp.hip (learned warm start)
 // One side of a problem: the points whose scalings are predicted and the

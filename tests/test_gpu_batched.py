@@ -101,6 +101,38 @@ def test_batched_matches_single_problem_solver(api):
         assert abs(g.iters - r32.iters) <= max(2, 0.02 * r32.iters), p.name
 
 
+def test_batched_straggler_hand_off(api):
+    # The config-4 batch (seed 0) holds a problem whose sampled support admits
+    # no exact fit of the marginals: once it is the only one left past the
+    # batch loop's first 64 iterations, it continues on the single-problem
+    # solver from its iterate.  It must end where a single-problem solve of the
+    # same problem (same sketch) ends, up to FP32 summation order.
+    probs = W.batch_ot(512, seed=0)
+    B = api.Batch.from_problems(probs)
+    rc, res = api.spar_sink_batched(B, eps=0.05, tol=1e-6, max_iter=1000, seed=0,
+                                    precision="f32", raise_on_error=False)
+    assert rc in (0, 1)
+    slow = [k for k, r in enumerate(res) if r.iters > 64]
+    assert 1 <= len(slow) <= 2
+    for k in slow:
+        p = probs[k]
+        prob = api.Problem(p.x, p.y, p.a, p.b, problem_index=p.problem_index)
+        r = api.spar_sink_ot(prob, eps=0.05, s=p.s, seed=0, tol=1e-6, max_iter=1000,
+                             precision="f32", raise_on_error=False)
+        g = res[k]
+        assert g.nnz == r.nnz and g.empty_rows == r.empty_rows and g.empty_cols == r.empty_cols
+        assert g.status == r.status, k
+        if r.status == 0:
+            assert abs(g.iters - r.iters) <= max(2, 0.02 * r.iters), k
+        else:
+            assert g.iters == r.iters == 1000, k
+        assert _rel(g.estimate, r.estimate) < 1e-4, k
+        assert _rel(g.sparse_objective, r.sparse_objective) < 1e-4, k
+        assert _rel(g.marginal_err, r.marginal_err) < 0.05, k
+    # every other problem converged inside the batch loop
+    assert all(r.status == 0 for k, r in enumerate(res) if k not in slow)
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_every_schedule_gives_the_same_answer(api, precision):
     probs = _ragged_batch(2)[3:]
