@@ -1145,28 +1145,90 @@ __device__ __forceinline__ void fill_line(const ProbParams& pp, double kappa, bo
     }
 }
 
-template <int ROLE, bool UOT, int PREC, int D>
-__global__ __launch_bounds__(256) void k_fill(ProbParams pp, const double* __restrict__ stats,
-                                              const uint64_t* __restrict__ bits, int64_t nlines,
-                                              int64_t words, const int64_t* __restrict__ ptr,
-                                              int32_t* __restrict__ idx, void* __restrict__ val,
-                                              int64_t cap) {
-    __shared__ int32_t queue[4][kFillQueue];
-    const int wv = threadIdx.x >> 6;
-    const int64_t line = (int64_t)blockIdx.x * 4 + wv;
-    const bool active = line < nlines;
+// Single-problem fill in two passes, so that neither waits on the other's
+// latency: the index pass streams the mask at high occupancy (no FP64 work),
+// the value pass takes each line's entries two per lane.
+//
+// Index pass: one wave per line; the words are read 16 per lane ahead of the
+// prefix-popcount, and every kept entry's index goes to its slot (ascending).
+__global__ __launch_bounds__(256) void k_fill_idx(const uint64_t* __restrict__ bits,
+                                                  int64_t nlines, int64_t words,
+                                                  const int64_t* __restrict__ ptr,
+                                                  int32_t* __restrict__ idx, int64_t cap) {
+    constexpr int NB = 16;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (line >= nlines) return;  // the whole wave
+    const uint64_t* __restrict__ row = bits + line * words;
+    int64_t run = ptr[line];
+    for (int64_t g0 = 0; g0 < words; g0 += NB * kWave) {
+        uint64_t wd[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int64_t widx = g0 + k * kWave + lane;
+            wd[k] = widx < words ? row[widx] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            uint64_t word = wd[k];
+            const int64_t widx = g0 + k * kWave + lane;
+            const int c = __popcll(word);
+            const int incl = wave_inclusive_scan(c);
+            int64_t pos = run + (incl - c);
+            while (word) {
+                const int b = __ffsll((unsigned long long)word) - 1;
+                word &= word - 1;
+                if (pos < cap) idx[pos] = (int32_t)(64 * widx + b);
+                ++pos;
+            }
+            run += __shfl(incl, kWave - 1, kWave);
+        }
+    }
+}
+
+// Value pass: one wave per line, two entries per lane at a time.  WFR =
+// false: the cost is a squared Euclidean kind (the WFR branches fold away).
+template <int ROLE, bool UOT, int PREC, int D, bool WFR>
+__global__ __launch_bounds__(256) void k_fill_val(ProbParams pp, const double* __restrict__ stats,
+                                                  int64_t nlines, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ idx,
+                                                  void* __restrict__ val, int64_t cap) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t line = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (line >= nlines) return;
     const double kappa = UOT ? pp.shrink_w * (pp.s / stats[ST_Z]) : 0.0;
-    fill_line<ROLE, UOT, PREC, D, int32_t>(pp, kappa, active, bits + (active ? line : 0) * words,
-                                          line, words, active ? ptr[line] : 0, idx, val, cap,
-                                          queue[wv]);
+    ProbParams lp = pp;
+    if constexpr (!WFR)
+        lp.cost = pp.cost == SS_COST_SQEUCLID ? SS_COST_SQEUCLID : SS_COST_SQEUCLID_MAXNORM;
+    const int64_t e0 = ptr[line];
+    const int64_t e1 = ptr[line + 1] < cap ? ptr[line + 1] : cap;
+    for (int64_t e = e0 + lane; e < e1; e += 2 * kWave) {
+        const int64_t e2 = e + kWave;
+        const bool two = e2 < e1;
+        const int64_t oa = idx[e];
+        const int64_t ob = two ? idx[e2] : oa;
+        double la, lb;
+        const double va = entry_value<UOT, D>(lp, kappa, ROLE == 0 ? line : oa,
+                                              ROLE == 0 ? oa : line, &la);
+        const double vb = entry_value<UOT, D>(lp, kappa, ROLE == 0 ? line : ob,
+                                              ROLE == 0 ? ob : line, &lb);
+        store_value<PREC>(val, e, va, la);
+        if (two) store_value<PREC>(val, e2, vb, lb);
+    }
 }
 
 template <int ROLE, bool UOT, int PREC, int D>
 static void run_fill4(const ProbParams& pp, const double* stats, const uint64_t* bits,
                       int64_t nlines, int64_t words, const int64_t* ptr, int32_t* idx, void* val,
                       int64_t cap, hipStream_t st) {
-    hipLaunchKernelGGL((k_fill<ROLE, UOT, PREC, D>), dim3((unsigned)((nlines + 3) / 4)), dim3(256),
-                       0, st, pp, stats, bits, nlines, words, ptr, idx, val, cap);
+    const dim3 grid((unsigned)((nlines + 3) / 4));
+    hipLaunchKernelGGL(k_fill_idx, grid, dim3(256), 0, st, bits, nlines, words, ptr, idx, cap);
+    if (pp.cost == kCostWfr)
+        hipLaunchKernelGGL((k_fill_val<ROLE, UOT, PREC, D, true>), grid, dim3(256), 0, st, pp,
+                           stats, nlines, ptr, idx, val, cap);
+    else
+        hipLaunchKernelGGL((k_fill_val<ROLE, UOT, PREC, D, false>), grid, dim3(256), 0, st, pp,
+                           stats, nlines, ptr, idx, val, cap);
 }
 
 template <int D>
