@@ -126,6 +126,32 @@ def test_sample_uot(api, n, eps, lam):
     np.testing.assert_allclose(g["row_fac"].cpu().numpy(), sk.prob.la, rtol=1e-15)
 
 
+# Budgets at which most or all entries are kept: the mask kernel's per-wave
+# candidate list then fills within every few rows of a tile, so its exact
+# decision phase runs many times per tile; with p* = 1 everywhere every entry
+# is kept.  m = 333 leaves a partial hash group and a partial mask word.
+@pytest.mark.parametrize("frac", [0.5, 1e6])
+def test_sample_ot_dense_budgets(api, frac):
+    p = W.ot_gauss2d(300, seed=9, m=333)
+    p.s = frac * p.n * p.m
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    _check_sketch_structure(g, sk)
+    if frac > 1:
+        assert sk.nnz == p.n * p.m
+    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=4e-16 * 8, atol=0)
+
+
+def test_sample_uot_dense_budget(api):
+    p = W.uot_mix3(300, seed=10, eps=0.05)
+    p.s = 0.5 * p.n * p.m
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    nd = _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
+    if nd == 0:
+        _check_sketch_structure(g, sk)
+
+
 def test_sample_uot_plain_cost(api):
     # unnormalised squared Euclidean cost (C up to ~10): the mask's FP32 bound of
     # the cost factor decides most candidates
