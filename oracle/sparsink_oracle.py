@@ -24,11 +24,12 @@ Choices where the paper is silent (all restated in the design notes):
 
 * Randomness: the Bernoulli draw for entry (i, j) of problem k is a
   counter-based hash, Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw,
-  "Parallel random numbers: as easy as 1, 2, 3", SC 2011).  Column j maps to
-  counter word q = (j >> 8) * 64 + (j & 63) and output slot (j >> 6) & 3;
-  the counter is (q, i, k, w) with key (seed lo32, seed hi32).  The slot of
-  the w=0 call gives the high 32 bits, the same slot of the w=1 call the low
-  32 bits; U = (bits >> 11) * 2^-53 and the entry is kept iff U < p*.
+  "Parallel random numbers: as easy as 1, 2, 3", SC 2011), with counters
+  (q, i, k, w) and key (seed lo32, seed hi32).  Column j maps to counter word
+  q = (j >> 9) * 64 + (j & 63) and slot s = (j >> 6) & 7.  The high 16 bits
+  of a 48-bit word are 16-bit half s & 1 (low half first) of output word
+  s >> 1 of the w = 0 call; the low 32 bits are output word s & 3 of the
+  w = 1 + (s >> 2) call.  U = bits * 2^-48 and the entry is kept iff U < p*.
 * Sums that decide sampled entries (sum sqrt(a), sum sqrt(b)) are the perfect
   binary-tree sum over the zero-padded power-of-two vector (adjacent pairs,
   level by level), so the OT mask is reproducible bit for bit.
@@ -85,24 +86,25 @@ def philox4x32_10(ctr, key):
 
 
 def uniform_bits(i, j, problem_index: int, seed: int):
-    """64-bit hash word for entries (i, j) (broadcast arrays) of one problem."""
+    """48-bit hash word for entries (i, j) (broadcast arrays) of one problem."""
     i = np.asarray(i, dtype=np.uint64)
     j = np.asarray(j, dtype=np.uint64)
-    q = (j >> np.uint64(8)) * np.uint64(64) + (j & np.uint64(63))
-    slot = (j >> np.uint64(6)) & np.uint64(3)
+    q = (j >> np.uint64(9)) * np.uint64(64) + (j & np.uint64(63))
+    slot = ((j >> np.uint64(6)) & np.uint64(7)).astype(np.int64)
     key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
     k = np.uint64(problem_index)
-    hi_words = philox4x32_10((q, i, k, np.uint64(0)), key)
-    lo_words = philox4x32_10((q, i, k, np.uint64(1)), key)
-    hi = np.choose(slot.astype(np.int64), hi_words)
-    lo = np.choose(slot.astype(np.int64), lo_words)
+    coarse = philox4x32_10((q, i, k, np.uint64(0)), key)
+    word = np.choose(slot >> 1, coarse)
+    hi = (word >> (np.uint64(16) * (slot & 1).astype(np.uint64))) & np.uint64(0xFFFF)
+    fine_a = philox4x32_10((q, i, k, np.uint64(1)), key)
+    fine_b = philox4x32_10((q, i, k, np.uint64(2)), key)
+    lo = np.where(slot < 4, np.choose(slot & 3, fine_a), np.choose(slot & 3, fine_b))
     return (hi << _SH32) | lo
 
 
 def uniform01(i, j, problem_index: int, seed: int):
-    """U_ij = (bits >> 11) * 2^-53, exactly representable in float64."""
-    bits = uniform_bits(i, j, problem_index, seed)
-    return (bits >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    """U_ij = bits * 2^-48, exactly representable in float64."""
+    return uniform_bits(i, j, problem_index, seed).astype(np.float64) * 2.0 ** -48
 
 
 # --------------------------------------------------------------------------
@@ -467,7 +469,9 @@ def marginal_error(K, KT, u, v, a, b, th, row_active, col_active) -> float:
     ktu = KT @ u
     up = u if th == 1.0 else u ** (1.0 / th)
     vp = v if th == 1.0 else v ** (1.0 / th)
-    return float(np.abs(up * kv - a)[row_active].sum() + np.abs(vp * ktu - b)[col_active].sum())
+    # only active lines enter (an empty line's scaling may be infinite)
+    ra, ca = row_active, col_active
+    return float(np.abs(up[ra] * kv[ra] - a[ra]).sum() + np.abs(vp[ca] * ktu[ca] - b[ca]).sum())
 
 
 def sinkhorn(K, a, b, opt: Options, row_active=None, col_active=None, u0=None, v0=None):

@@ -46,24 +46,33 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
 }
 
 // Hash layout of the Poisson mask.  Column j of row i in problem k uses the
-// counter (q, i, k, w) with q = (j >> 8) * 64 + (j & 63) and output slot
-// (j >> 6) & 3: the w = 0 call gives the high 32 bits, the w = 1 call the low
-// 32 bits of a 64-bit word; U = (bits >> 11) * 2^-53.  A wave therefore covers
-// 256 consecutive columns with one call per lane and four ballots.
+// counters (q, i, k, w) with q = (j >> 9) * 64 + (j & 63) and slot
+// s = (j >> 6) & 7.  A 48-bit word holds, as its high 16 bits, half s & 1
+// (low half first) of output word s >> 1 of the w = 0 call, and as its low
+// 32 bits output word s & 3 of the w = 1 + (s >> 2) call; U = bits * 2^-48.
+// A wave therefore covers 512 consecutive columns with one call per lane and
+// eight ballots.
 //
-// keep(i, j) = [U < P].  U lies in [h, h + 2^-32 - 2^-53] with h = hi * 2^-32,
-// so the high word alone decides unless P falls inside that interval, which
-// happens with probability 2^-32 per entry; only then is the low word drawn.
+// keep(i, j) = [U < P].  U lies in [h, h + 2^-16 - 2^-48] with h = hi * 2^-16,
+// so the 16-bit half alone decides unless P falls inside that interval, which
+// happens with probability 2^-16 per entry; only then is the low word drawn.
+__device__ __forceinline__ uint32_t coarse_half(const Words4& w, int slot) {
+    const int t = slot >> 1;
+    const uint32_t x = t == 0 ? w.w[0] : t == 1 ? w.w[1] : t == 2 ? w.w[2] : w.w[3];
+    return (slot & 1) ? (x >> 16) : (x & 0xFFFFu);
+}
+
 __device__ __forceinline__ bool keep_decision(uint32_t hi, double P, uint32_t q, uint32_t i,
                                               uint32_t k, uint32_t k0, uint32_t k1, int slot) {
-    const double h = (double)hi * 0x1p-32;
+    const double h = (double)hi * 0x1p-16;
     if (h >= P) return false;
-    if (h + (0x1p-32 - 0x1p-53) < P) return true;
-    const Words4 lo = philox10(q, i, k, 1u, k0, k1);
+    if (h + (0x1p-16 - 0x1p-48) < P) return true;
+    const Words4 lo = philox10(q, i, k, 1u + (uint32_t)(slot >> 2), k0, k1);
     // a select, not an index: `slot` may be a run-time value
-    const uint32_t lw = slot == 0 ? lo.w[0] : slot == 1 ? lo.w[1] : slot == 2 ? lo.w[2] : lo.w[3];
+    const int s4 = slot & 3;
+    const uint32_t lw = s4 == 0 ? lo.w[0] : s4 == 1 ? lo.w[1] : s4 == 2 ? lo.w[2] : lo.w[3];
     const uint64_t bits = ((uint64_t)hi << 32) | (uint64_t)lw;
-    const double U = (double)(bits >> 11) * 0x1p-53;
+    const double U = (double)bits * 0x1p-48;
     return U < P;
 }
 

@@ -597,14 +597,14 @@ hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrin
 
 // ------------------------------------------------------------------ mask
 // Block tile: 16 rows x 64 mask words (4096 columns).  Wave w owns hash
-// groups 4w..4w+3 of the tile: one Philox call per lane per group and row
-// gives the high words of four columns 64 apart.
+// groups 2w, 2w+1 of the tile (512 columns each): one Philox call per lane per
+// group and row gives the 16-bit high halves of eight columns 64 apart.
 //
 // Two phases per wave, so that the hash loop stays small (few registers,
 // high occupancy) and no wave idles while one lane evaluates an exact p*:
-//  1. filter: hash the high words and keep as a candidate every entry that
-//     can still be sampled, hi < 2^32 P with P the decision's probability
-//     (OT) or its cost-free bound (UOT), scaled by 2^32 (1 + 2^-40) so that
+//  1. filter: hash the high halves and keep as a candidate every entry that
+//     can still be sampled, hi < 2^16 P with P the decision's probability
+//     (OT) or its cost-free bound (UOT), scaled by 2^16 (1 + 2^-40) so that
 //     the filter only ever adds candidates; candidates go to a per-wave list
 //     in LDS (ballot + lane prefix count, no atomics);
 //  2. decide: when the list may overflow, and at the end, every lane takes
@@ -613,10 +613,11 @@ hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrin
 //     p*; for UOT the cost-free bound, the cost factor's bound for the
 //     unnormalised and WFR costs, then the exact p* and U).  Kept entries set
 //     their bit in the wave's own words of the tile.
-// An entry that the filter drops has hi >= 2^32 P, so U >= P: it is never
+// An entry that the filter drops has hi >= 2^16 P, so U >= P: it is never
 // kept.  The mask is therefore the same as a pair-by-pair evaluation's.
+// A list entry is 32 bits: row (4), slot of the wave (4), lane (6), high half.
 constexpr int kMaskRows = 16;
-constexpr int kMaskCand = 512;  // list entries per wave (>= 256 + one row's 256)
+constexpr int kMaskCand = 1024;  // list entries per wave (>= 512 + one row's 512)
 
 // One tile: rows row0 .. row0 + 15 of one problem, mask words ct * 64 ..
 // ct * 64 + 63; adds the popcounts to row_cnt.  All 256 threads call it.
@@ -626,7 +627,7 @@ template <bool UOT, int D, bool WFR>
 __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64_t m, int64_t W,
                                           int64_t rt, int64_t ct, uint64_t* __restrict__ mask,
                                           int32_t* __restrict__ row_cnt, double kappa,
-                                          uint64_t (*tile)[64], uint64_t (*cand)[kMaskCand]) {
+                                          uint64_t (*tile)[64], uint32_t (*cand)[kMaskCand]) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
     const int64_t row0 = rt * kMaskRows;
     const int nrows = (int)(n - row0 < kMaskRows ? n - row0 : kMaskRows);
@@ -638,9 +639,9 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
     // the uniform part of shrinkage (0 without it); for the UOT bound with
     // the bound's margin
     const double pc = UOT ? pp.shrink_c * (1.0 + 0x1p-30) : pp.shrink_c;
-    // filter scale 2^32 (1 + 2^-40); the constant 2^-900 keeps every entry
+    // filter scale 2^16 (1 + 2^-40); the constant 2^-900 keeps every entry
     // with hi = 0 a candidate where the scaled product underflows
-    constexpr double kScale = 0x1p32 * (1.0 + 0x1p-40);
+    constexpr double kScale = 0x1p16 * (1.0 + 0x1p-40);
     const double pcf = pc * kScale + 0x1p-900;
     // lane r < 16 holds row r's factor, scaled
     const double rowv = lane < nrows ? rsrc[row0 + lane] * kScale : 0.0;
@@ -649,20 +650,20 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
     ProbParams lp = pp;
     if constexpr (!WFR)
         lp.cost = pp.cost == SS_COST_SQEUCLID ? SS_COST_SQEUCLID : SS_COST_SQEUCLID_MAXNORM;
-    uint64_t* const list = cand[wv];
+    uint32_t* const list = cand[wv];
     int cnt = 0;  // wave-uniform
-    const int64_t g_end = (W + 3) / 4;  // hash groups of 256 columns (4 words)
-    const int64_t g_first = ct * 16 + wv * 4;
-    const int ng = (int)(g_end - g_first < 4 ? (g_end - g_first > 0 ? g_end - g_first : 0) : 4);
+    const int64_t g_end = (W + 7) / 8;  // hash groups of 512 columns (8 words)
+    const int64_t g_first = ct * 8 + wv * 2;
+    const int ng = (int)(g_end - g_first < 2 ? (g_end - g_first > 0 ? g_end - g_first : 0) : 2);
     for (int gg = 0; gg < ng; ++gg) {
         const int64_t g = g_first + gg;
         const uint32_t q = (uint32_t)(g * 64 + lane);
         // column factors of this group; -inf past the last column makes the
         // filter's bound -inf (or NaN for a zero row factor): never a candidate
-        double cf[4];
+        double cf[8];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int64_t j = 256 * g + 64 * s + lane;
+        for (int s = 0; s < 8; ++s) {
+            const int64_t j = 512 * g + 64 * s + lane;
             cf[s] = j < m ? csrc[j] : -INFINITY;
         }
         for (int r = 0; r < nrows; ++r) {
@@ -672,21 +673,22 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
             const double rowf = __hiloint2double((int)hi, (int)lo);
             const Words4 h = philox10(q, (uint32_t)i, pp.problem_index, 0u, pp.k0, pp.k1);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const bool c = (double)h.w[s] < fma(rowf, cf[s], pcf);
+            for (int s = 0; s < 8; ++s) {
+                const uint32_t hs = coarse_half(h, s);
+                const bool c = (double)hs < fma(rowf, cf[s], pcf);
                 const uint64_t bal = __ballot(c);
                 if (bal) {
                     if (c) {
                         const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi(
                                                   (uint32_t)(bal >> 32),
                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                        list[pos] = ((uint64_t)((r << 10) | ((gg * 4 + s) << 6) | lane) << 32) |
-                                    (uint64_t)h.w[s];
+                        list[pos] = ((uint32_t)r << 26) | ((uint32_t)(gg * 8 + s) << 22) |
+                                    ((uint32_t)lane << 16) | hs;
                     }
                     cnt += __popcll(bal);
                 }
             }
-            if (cnt <= kMaskCand - 256 && (r + 1 < nrows || gg + 1 < ng)) continue;
+            if (cnt <= kMaskCand - 512 && (r + 1 < nrows || gg + 1 < ng)) continue;
             // ---- decide the listed entries, one per lane (the list was written
             // by other lanes of this wave: LDS operations of a wave complete in
             // order; the wait and clobber also keep the compiler's order)
@@ -694,13 +696,13 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
             for (int base = 0; base < cnt; base += kWave) {
                 const int e = base + lane;
                 if (e >= cnt) break;
-                const uint64_t it = list[e];
-                const uint32_t hw = (uint32_t)it;
-                const int meta = (int)(it >> 32);
-                const int er = meta >> 10, slot = (meta >> 6) & 15, lc = meta & 63;
-                const int es = slot & 3;
-                const int64_t eg = g_first + (slot >> 2);
-                const int64_t ej = 256 * eg + 64 * es + lc;
+                const uint32_t it = list[e];
+                const uint32_t hw = it & 0xFFFFu;
+                const int er = (int)(it >> 26), slot = (int)(it >> 22) & 15,
+                          lc = (int)(it >> 16) & 63;
+                const int es = slot & 7;
+                const int64_t eg = g_first + (slot >> 3);
+                const int64_t ej = 512 * eg + 64 * es + lc;
                 const int64_t ei = row0 + er;
                 const uint32_t eq = (uint32_t)(eg * 64 + lc);
                 bool keep = false;
@@ -710,7 +712,7 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
                     if (!UOT) {
                         keep = keep_decision(hw, P, eq, (uint32_t)ei, pp.problem_index, pp.k0, pp.k1,
                                              es);
-                    } else if ((double)hw * 0x1p-32 < P) {
+                    } else if ((double)hw * 0x1p-16 < P) {
                         // P bounds p* without the cost factor.  Candidates first take
                         // the cost factor's bound in FP32 (margin 2^-12 for the
                         // rounding of its argument and of the exponential), and only
@@ -725,7 +727,7 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
                             const double t = uot_bound_exponent(lp, c);
                             const double ex = t < 200.0 ? (double)__builtin_amdgcn_exp2f(-(float)t) : 0.0;
                             const double Pt = Pr * ex * (1.0 + 0x1p-12) + pc;
-                            exact = (double)hw * 0x1p-32 < Pt || hw == 0u;
+                            exact = (double)hw * 0x1p-16 < Pt || hw == 0u;
                         }
                         if (exact) {
                             const double q_ij = uot_q_of(lp, c, ei, ej);
@@ -767,7 +769,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     ProbParams pp, int64_t n, int64_t m, int64_t W, int64_t ncol_tiles, uint64_t* __restrict__ mask,
     int32_t* __restrict__ row_cnt, const double* __restrict__ stats) {
     __shared__ uint64_t tile[kMaskRows][64];
-    __shared__ uint64_t cand[4][kMaskCand];
+    __shared__ uint32_t cand[4][kMaskCand];
     const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
     const double kappa = UOT ? pp.shrink_w * (pp.s / stats[ST_Z]) : 0.0;
     mask_tile<UOT, D, false>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile, cand);
@@ -779,7 +781,7 @@ __global__ __launch_bounds__(256) void k_mask_wfr(ProbParams pp, int64_t n, int6
                                                   int32_t* __restrict__ row_cnt,
                                                   const double* __restrict__ stats) {
     __shared__ uint64_t tile[kMaskRows][64];
-    __shared__ uint64_t cand[4][kMaskCand];
+    __shared__ uint32_t cand[4][kMaskCand];
     const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
     const double kappa = pp.shrink_w * (pp.s / stats[ST_Z]);
     mask_tile<true, D, true>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile, cand);
@@ -1387,7 +1389,7 @@ __global__ __launch_bounds__(1024) void k_b_prep(BatchArgs A) {
 
 __global__ __launch_bounds__(256) void k_b_mask(BatchArgs A) {
     __shared__ uint64_t tile[kMaskRows][64];
-    __shared__ uint64_t cand[4][kMaskCand];
+    __shared__ uint32_t cand[4][kMaskCand];
     const int k = owner_of(A.tile_mask, A.count, blockIdx.x);
     const BProb P = A.prob[k];
     const int64_t t = blockIdx.x - A.tile_mask[k];

@@ -37,26 +37,38 @@ def test_philox_known_answer(ctr, key, out):
 
 
 def test_uniform_slot_mapping_uses_kat_words():
-    # Entry (0, j) of problem 0 with seed 0 takes its high word from slot
-    # (j>>6)&3 of the counter (j>>8)*64 + (j&63) = 0 for j in {0, 64, 128, 192}:
-    # that is exactly the all-zero known-answer vector.
+    # Entry (0, j) of problem 0 with seed 0, j in {0, 64, ..., 448}, uses
+    # counter word (j>>9)*64 + (j&63) = 0 and slot (j>>6)&7 = j/64: its high 16
+    # bits are half (slot & 1) of word slot >> 1 of the all-zero known-answer
+    # vector, its low 32 bits word slot & 3 of the call with last counter word
+    # 1 + (slot >> 2).
     kat0 = _kat_rows()[0][2]
-    bits = O.uniform_bits(np.zeros(4, np.int64), np.array([0, 64, 128, 192]), 0, 0)
-    assert [int(b) >> 32 for b in bits] == kat0
-    # the low word comes from the counter with last word 1
-    lo = O.philox4x32_10([np.uint64(0), np.uint64(0), np.uint64(0), np.uint64(1)], (0, 0))
-    assert [int(b) & 0xFFFFFFFF for b in bits] == [int(v) for v in lo]
+    j = np.arange(8) * 64
+    bits = O.uniform_bits(np.zeros(8, np.int64), j, 0, 0)
+    fine = [O.philox4x32_10([np.uint64(0), np.uint64(0), np.uint64(0), np.uint64(w)], (0, 0))
+            for w in (1, 2)]
+    for s in range(8):
+        assert int(bits[s]) >> 32 == (kat0[s >> 1] >> (16 * (s & 1))) & 0xFFFF
+        assert int(bits[s]) & 0xFFFFFFFF == int(fine[s >> 2][s & 3])
+    # the next counter word starts at column 512
+    assert O.uniform_bits(np.zeros(1, np.int64), np.array([512]), 0, 0)[0] != bits[0]
 
 
 def test_uniform_range_and_exactness():
-    i, j = np.meshgrid(np.arange(37), np.arange(300), indexing="ij")
+    i, j = np.meshgrid(np.arange(37), np.arange(600), indexing="ij")
     bits = O.uniform_bits(i, j, 3, 12345)
     u = O.uniform01(i, j, 3, 12345)
     assert u.min() >= 0.0 and u.max() < 1.0
-    # exact: u * 2^53 is the integer bits >> 11
-    assert np.array_equal((u * 2.0 ** 53).astype(np.uint64), bits >> np.uint64(11))
-    # all 64-bit words distinct across (i, j)
+    # exact: u * 2^48 is the 48-bit integer
+    assert bits.max() < (1 << 48)
+    assert np.array_equal((u * 2.0 ** 48).astype(np.uint64), bits)
+    # all 48-bit words distinct across (i, j)
     assert np.unique(bits).size == bits.size
+    # the 16-bit high parts are uniform over their 65536 values (chi-square, 5 sigma)
+    h = np.bincount(((bits >> np.uint64(32)).astype(np.int64) >> 8).ravel(), minlength=256)
+    e = bits.size / 256.0
+    chi2 = float(((h - e) ** 2 / e).sum())
+    assert abs(chi2 - 255.0) < 5.0 * np.sqrt(2 * 255.0)
     # different problem index or seed gives different streams
     assert not np.array_equal(bits, O.uniform_bits(i, j, 4, 12345))
     assert not np.array_equal(bits, O.uniform_bits(i, j, 3, 12345 + (1 << 32)))
