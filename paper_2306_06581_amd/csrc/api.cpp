@@ -896,7 +896,7 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
 
 // ------------------------------------------------------------------ batches
 struct BLayout {
-    size_t prob, stat, tile_cmax, tile_mask, tile_tr, row_off, col_off, order, queue, gstats;
+    size_t prob, stat, tile_cmax, tile_mask, tile_tr, row_off, col_off, owner, order, queue, gstats;
     size_t row_fac, col_fac, a_eff, b_eff, mask, maskT, row_cnt, col_cnt, row_ptr, col_ptr, scan;
     size_t col_idx, row_idx, val, val_t, u, v;
     size_t hlog, handoff, handoff_bytes;  // straggler hand-off: log scalings, solver workspace
@@ -971,6 +971,7 @@ BLayout bplan(const ss_batch* B, const ss_options* O) {
     L.tile_tr = take((size_t)(K + 1) * 8);
     L.row_off = take((size_t)(K + 1) * 8);
     L.col_off = take((size_t)(K + 1) * 8);
+    L.owner = take((size_t)(L.rows + L.cols) * 4);
     L.order = take((size_t)K * 4);
     L.queue = take(64);
     L.gstats = take(ST_COUNT * 8);
@@ -1093,6 +1094,7 @@ int batch_setup(BCtx& c) {
     a.tile_tr = at<int64_t>(ws, c.L.tile_tr);
     a.row_off = at<int64_t>(ws, c.L.row_off);
     a.col_off = at<int64_t>(ws, c.L.col_off);
+    a.owner = at<int32_t>(ws, c.L.owner);
     a.rows = c.L.rows;
     a.cols = c.L.cols;
     a.x = B->x;

@@ -407,6 +407,7 @@ struct BatchArgs {
     const int64_t* tile_tr;     // [count + 1] prefix of transpose tiles
     const int64_t* row_off;     // [count + 1] prefix of n
     const int64_t* col_off;     // [count + 1] prefix of m
+    int32_t* owner;             // [rows + cols]: problem of each row, then of each column
     int64_t rows, cols;         // sum n, sum m
     const double *x, *y, *a, *b;
     double *row_fac, *col_fac;  // alpha_i, sqrt(b_j)

@@ -1050,101 +1050,11 @@ __device__ __forceinline__ double entry_value(const ProbParams& pp, double kappa
     return K / P;
 }
 
-// One wave per line (row for the CSR, column for the CSC).  Phase 1: a
-// prefix-popcount of the line's mask words gives each kept entry its slot, in
-// ascending order; the index is written out and queued in LDS.  Phase 2: the
-// whole wave computes the queued values, one entry per lane (a line's entries
-// are too sparse among its words to keep the lanes busy in phase 1).
-constexpr int kFillQueue = 512;
-
 template <int PREC>
 __device__ __forceinline__ void store_value(void* val, int64_t pos, double v, double lv) {
     if (PREC == P_F64) ((double*)val)[pos] = v;
     if (PREC == P_F32) ((float*)val)[pos] = (float)v;
     if (PREC == P_LOG) ((float*)val)[pos] = (float)lv;
-}
-
-// One line, by one wave: `row` is the line's mask words, `base` its first
-// entry slot, `line` its index in the problem; indices are written as IdxT.
-// The words are read 16 per lane ahead of the prefix-popcount (one load per
-// word would leave the wave waiting on each); entries past the queue's
-// capacity take their values in a second scan of the words.
-template <int ROLE, bool UOT, int PREC, int D, typename IdxT>
-__device__ __forceinline__ void fill_line(const ProbParams& pp, double kappa, bool active,
-                                          const uint64_t* __restrict__ row, int64_t line,
-                                          int64_t words, int64_t base, IdxT* __restrict__ idx,
-                                          void* __restrict__ val, int64_t cap, int32_t* queue) {
-    constexpr int NB = 16;  // words per lane read ahead
-    const int lane = threadIdx.x & (kWave - 1);
-    int64_t run = base;
-    for (int64_t g0 = 0; g0 < words; g0 += NB * kWave) {
-        uint64_t wd[NB];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const int64_t widx = g0 + k * kWave + lane;
-            wd[k] = (active && widx < words) ? row[widx] : 0ull;
-        }
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            uint64_t word = wd[k];
-            const int64_t widx = g0 + k * kWave + lane;
-            const int c = __popcll(word);
-            const int incl = wave_inclusive_scan(c);
-            int64_t pos = run + (incl - c);
-            while (word) {
-                const int b = __ffsll((unsigned long long)word) - 1;
-                word &= word - 1;
-                const int64_t other = 64 * widx + b;
-                if (pos < cap) idx[pos] = (IdxT)other;
-                const int64_t local = pos - base;
-                if (local < kFillQueue) queue[local] = (int32_t)other;
-                ++pos;
-            }
-            run += __shfl(incl, kWave - 1, kWave);
-        }
-    }
-    __syncthreads();
-    const int64_t cnt = run - base;
-    const int64_t nq = cnt < kFillQueue ? cnt : kFillQueue;
-    // two entries per lane at a time, so that their loads overlap
-    const int64_t nv = cap - base < nq ? (cap - base > 0 ? cap - base : 0) : nq;
-    for (int64_t e = lane; e < nv; e += 2 * kWave) {
-        const int64_t e2 = e + kWave;
-        const bool two = e2 < nv;
-        const int64_t oa = queue[e];
-        const int64_t ob = two ? queue[e2] : oa;
-        double la, lb;
-        const double va = entry_value<UOT, D>(pp, kappa, ROLE == 0 ? line : oa,
-                                              ROLE == 0 ? oa : line, &la);
-        const double vb = entry_value<UOT, D>(pp, kappa, ROLE == 0 ? line : ob,
-                                              ROLE == 0 ? ob : line, &lb);
-        store_value<PREC>(val, base + e, va, la);
-        if (two) store_value<PREC>(val, base + e2, vb, lb);
-    }
-    if (cnt > kFillQueue) {  // wave-uniform
-        int64_t run2 = base;
-        for (int64_t w0 = 0; w0 < words; w0 += kWave) {
-            const int64_t widx = w0 + lane;
-            uint64_t word = (active && widx < words) ? row[widx] : 0ull;
-            const int c = __popcll(word);
-            const int incl = wave_inclusive_scan(c);
-            int64_t pos = run2 + (incl - c);
-            while (word) {
-                const int b = __ffsll((unsigned long long)word) - 1;
-                word &= word - 1;
-                if (pos - base >= kFillQueue && pos < cap) {
-                    const int64_t other = 64 * widx + b;
-                    const int64_t i = ROLE == 0 ? line : other;
-                    const int64_t j = ROLE == 0 ? other : line;
-                    double lv;
-                    const double v = entry_value<UOT, D>(pp, kappa, i, j, &lv);
-                    store_value<PREC>(val, pos, v, lv);
-                }
-                ++pos;
-            }
-            run2 += __shfl(incl, kWave - 1, kWave);
-        }
-    }
 }
 
 // Single-problem fill in two passes, so that neither waits on the other's
@@ -1303,7 +1213,8 @@ hipError_t launch_empty_policy(const double* a, const int32_t* cnt, int64_t n, i
 // ================================================================== batches
 // The sampling stages of a batch of OT problems, one launch per stage over
 // all problems: block b works on tile b - pre[k] of the problem k that owns
-// it (pre = prefix of the per-problem tile counts, searched by every block).
+// it (pre = prefix of the per-problem tile counts, searched by every block);
+// the fills, one wave per line, read the line's problem from a table.
 
 // Last k in [0, count) with pre[k] <= key.
 __device__ __forceinline__ int owner_of(const int64_t* __restrict__ pre, int count, int64_t key) {
@@ -1419,17 +1330,52 @@ __global__ __launch_bounds__(256) void k_b_transpose(BatchArgs A) {
                    A.col_cnt + P.yo, tile);
 }
 
-template <int ROLE, int PREC, int D>
-__global__ __launch_bounds__(256) void k_b_fill(BatchArgs A) {
-    __shared__ int32_t queue[4][kFillQueue];
-    const int wv = threadIdx.x >> 6;
+// Problem of every row and every column (one block per problem).
+__global__ __launch_bounds__(256) void k_b_owner(BatchArgs A) {
+    const int k = blockIdx.x;
+    for (int64_t l = A.row_off[k] + threadIdx.x; l < A.row_off[k + 1]; l += blockDim.x)
+        A.owner[l] = k;
+    for (int64_t l = A.col_off[k] + threadIdx.x; l < A.col_off[k + 1]; l += blockDim.x)
+        A.owner[A.rows + l] = k;
+}
+
+// Batched fill in two passes, one wave per line (a batch line has at most
+// 64 mask words: SS_BATCH_MAX_SIDE = 4096).  Index pass: one word per lane,
+// the prefix-popcount, local indices in ascending order.
+template <int ROLE>
+__global__ __launch_bounds__(256) void k_b_fill_idx(BatchArgs A) {
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t lines = ROLE == 0 ? A.rows : A.cols;
-    const int64_t L = (int64_t)blockIdx.x * 4 + wv;
-    const bool active = L < lines;
-    const int64_t* off = ROLE == 0 ? A.row_off : A.col_off;
-    const int k = owner_of(off, A.count, active ? L : lines - 1);
+    const int64_t L = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (L >= lines) return;  // the whole wave
+    const int k = A.owner[(ROLE == 0 ? 0 : A.rows) + L];
     const BProb P = A.prob[k];
-    const int64_t local = (active ? L : lines - 1) - off[k];
+    const int64_t local = L - (ROLE == 0 ? A.row_off : A.col_off)[k];
+    const int64_t words = ROLE == 0 ? P.W : P.Wn;
+    const uint64_t* bits = ROLE == 0 ? A.mask + P.mo + local * P.W : A.maskT + P.mto + local * P.Wn;
+    uint64_t word = lane < words ? bits[lane] : 0ull;
+    const int c = __popcll(word);
+    const int incl = wave_inclusive_scan(c);
+    int64_t pos = (ROLE == 0 ? A.row_ptr : A.col_ptr)[L] + (incl - c);
+    uint16_t* idx = ROLE == 0 ? A.col_idx : A.row_idx;
+    while (word) {
+        const int b = __ffsll((unsigned long long)word) - 1;
+        word &= word - 1;
+        if (pos < A.cap) idx[pos] = (uint16_t)(64 * lane + b);
+        ++pos;
+    }
+}
+
+// Value pass: one wave per line, two entries per lane at a time.
+template <int ROLE, int PREC, int D>
+__global__ __launch_bounds__(256) void k_b_fill_val(BatchArgs A) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t lines = ROLE == 0 ? A.rows : A.cols;
+    const int64_t L = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (L >= lines) return;
+    const int k = A.owner[(ROLE == 0 ? 0 : A.rows) + L];
+    const BProb P = A.prob[k];
+    const int64_t local = L - (ROLE == 0 ? A.row_off : A.col_off)[k];
     ProbParams pp;
     pp.uot = 0;
     pp.shrink_w = 1.0;
@@ -1444,16 +1390,26 @@ __global__ __launch_bounds__(256) void k_b_fill(BatchArgs A) {
     pp.x = A.x + P.xo * A.d;
     pp.y = A.y + P.yo * A.d;
     pp.d = A.d;
-    const uint64_t* bits = ROLE == 0 ? A.mask + P.mo + local * P.W : A.maskT + P.mto + local * P.Wn;
-    const int64_t words = ROLE == 0 ? P.W : P.Wn;
     const int64_t* ptr = ROLE == 0 ? A.row_ptr : A.col_ptr;
-    fill_line<ROLE, false, PREC, D, uint16_t>(pp, 0.0, active, bits, local, words,
-                                             active ? ptr[L] : 0, ROLE == 0 ? A.col_idx : A.row_idx,
-                                             ROLE == 0 ? A.val : A.val_t, A.cap, queue[wv]);
+    const uint16_t* idx = ROLE == 0 ? A.col_idx : A.row_idx;
+    void* val = ROLE == 0 ? A.val : A.val_t;
+    const int64_t e0 = ptr[L];
+    const int64_t e1 = ptr[L + 1] < A.cap ? ptr[L + 1] : A.cap;
+    for (int64_t e = e0 + lane; e < e1; e += 2 * kWave) {
+        const int64_t e2 = e + kWave;
+        const bool two = e2 < e1;
+        const int64_t oa = idx[e];
+        const int64_t ob = two ? idx[e2] : oa;
+        double la, lb;
+        const double va = entry_value<false, D>(pp, 0.0, ROLE == 0 ? local : oa,
+                                                ROLE == 0 ? oa : local, &la);
+        const double vb = entry_value<false, D>(pp, 0.0, ROLE == 0 ? local : ob,
+                                                ROLE == 0 ? ob : local, &lb);
+        store_value<PREC>(val, e, va, la);
+        if (two) store_value<PREC>(val, e2, vb, lb);
+    }
 }
 
-// One block (1024 threads) per problem, after the counts: the empty-line
-// policy on both sides and the problem's entry count.
 __global__ __launch_bounds__(1024) void k_b_empty(BatchArgs A) {
     __shared__ double v[kBatchMaxSide];
     __shared__ double sh[1024];
@@ -1499,8 +1455,11 @@ static void run_b_cmax(const BatchArgs& a, int64_t nt, hipStream_t st) {
 
 template <int PREC, int D>
 static void run_b_fill(const BatchArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((k_b_fill<0, PREC, D>), dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, st, a);
-    hipLaunchKernelGGL((k_b_fill<1, PREC, D>), dim3((unsigned)((a.cols + 3) / 4)), dim3(256), 0, st, a);
+    const dim3 gr((unsigned)((a.rows + 3) / 4)), gc((unsigned)((a.cols + 3) / 4));
+    hipLaunchKernelGGL((k_b_fill_idx<0>), gr, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_b_fill_val<0, PREC, D>), gr, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_b_fill_idx<1>), gc, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_b_fill_val<1, PREC, D>), gc, dim3(256), 0, st, a);
 }
 
 template <int D>
@@ -1521,6 +1480,7 @@ hipError_t launch_batch_sample(int precision, const BatchArgs& a, int64_t ntile_
     if (e == hipSuccess) e = launch_validate(a.a, a.rows, a.x, a.rows * a.d, a.gstats, st);
     if (e == hipSuccess) e = launch_validate(a.b, a.cols, a.y, a.cols * a.d, a.gstats, st);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_b_owner, dim3(a.count), dim3(256), 0, st, a);
     SS_DISPATCH_D(a.d, run_b_cmax, a, ntile_cmax, st);
     hipLaunchKernelGGL(k_b_prep, dim3(a.count), dim3(1024), 0, st, a);
     hipLaunchKernelGGL(k_b_mask, dim3((unsigned)ntile_mask), dim3(256), 0, st, a);
