@@ -898,7 +898,7 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
 struct BLayout {
     size_t prob, stat, tile_cmax, tile_mask, tile_tr, row_off, col_off, owner, order, queue, gstats;
     size_t row_fac, col_fac, a_eff, b_eff, mask, maskT, row_cnt, col_cnt, row_ptr, col_ptr, scan;
-    size_t col_idx, row_idx, val, val_t, u, v;
+    size_t col_idx, row_idx, val, val_t, u, v, obj_part;
     size_t hlog, handoff, handoff_bytes;  // straggler hand-off: log scalings, solver workspace
     size_t total;
     int64_t rows, cols, cap, nt_cmax, nt_mask, nt_tr;
@@ -993,6 +993,7 @@ BLayout bplan(const ss_batch* B, const ss_options* O) {
     L.val_t = take((size_t)(L.cap + 64) * es);
     L.u = take((size_t)L.rows * es);
     L.v = take((size_t)L.cols * es);
+    L.obj_part = take((size_t)K * kBObjSplit * 3 * 8);
     // hand-off of stragglers to the single-problem solver: its workspace for
     // the largest sides and budget of the batch (every region grows with n,
     // m and s) and the log scalings that start it
@@ -1166,6 +1167,7 @@ int batch_setup(BCtx& c) {
     ob.cols = a.cols;
     ob.cap = a.cap;
     ob.col_ptr = a.col_ptr;
+    ob.part = at<double>(ws, c.L.obj_part);
     return SS_OK;
 }
 

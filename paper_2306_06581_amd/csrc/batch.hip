@@ -235,33 +235,41 @@ hipError_t launch_batch_iterate(int precision, int lanes, int block, int grid, c
 // sum T~ (log u + log v - 1) over the kept entries (Alg. 3; 0 log 0 = 0).
 constexpr int kBObjLanes = 16;
 
+// Block (k, b) of kBObjSplit per problem sums rows b, b + kBObjSplit, ... of
+// problem k (in groups of blockDim / kBObjLanes rows) into its partials.  The
+// problem's v is staged in LDS (the entries gather it at random columns).
 template <int PREC, int D>
 __global__ __launch_bounds__(256) void k_b_objective(BObjArgs A) {
     typedef typename BTypes<PREC>::V V;
     __shared__ double sh[16];
+    __shared__ double vs[SS_BATCH_MAX_SIDE];
     if (A.row_ptr[A.rows] > A.cap || A.col_ptr[A.cols] > A.cap) return;
-    const int k = blockIdx.x;
+    const int k = blockIdx.x / kBObjSplit, blk = blockIdx.x % kBObjSplit;
     const BProb P = A.prob[k];
+    for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x) vs[j] = (double)((const V*)A.v)[P.yo + j];
+    __syncthreads();
     const int sub = threadIdx.x % kBObjLanes;
     const double inv_cmax = A.stat[k].inv_cmax;
     const V* u = (const V*)A.u + P.xo;
-    const V* v = (const V*)A.v + P.yo;
     const V* val = (const V*)A.val;
     const double* x = A.x + P.xo * A.d;
     const double* y = A.y + P.yo * A.d;
+    constexpr int RPB = 256 / kBObjLanes;  // rows in flight per block
     double s_tc = 0.0, s_ent = 0.0, s_sp = 0.0;
-    for (int64_t r = threadIdx.x / kBObjLanes; r < P.n; r += blockDim.x / kBObjLanes) {
+    for (int64_t r = (int64_t)blk * RPB + threadIdx.x / kBObjLanes; r < P.n;
+         r += (int64_t)kBObjSplit * RPB) {
         const int64_t k0 = A.row_ptr[P.xo + r], k1 = A.row_ptr[P.xo + r + 1];
         const double ur = (double)u[r];
         const double lu = log(ur);
         for (int64_t e = k0 + sub; e < k1; e += kBObjLanes) {
             const int64_t o = A.col_idx[e];
-            const double t = ur * (double)val[e] * (double)v[o];
+            const double vo = vs[o];
+            const double t = ur * (double)val[e] * vo;
             if (t > 0.0) {
                 const double c = sqdist<D>(x + r * A.d, y + o * A.d, A.d) * inv_cmax;
                 s_tc += t * c;
                 s_ent += t * (log(t) - 1.0);
-                s_sp += t * ((lu + log((double)v[o])) - 1.0);
+                s_sp += t * ((lu + log(vo)) - 1.0);
             }
         }
     }
@@ -269,15 +277,32 @@ __global__ __launch_bounds__(256) void k_b_objective(BObjArgs A) {
     s_ent = block_sum(s_ent, sh);
     s_sp = block_sum(s_sp, sh);
     if (threadIdx.x == 0) {
-        A.stat[k].transport = s_tc;
-        A.stat[k].negent = s_ent;
-        A.stat[k].sparseobj = s_sp;
+        double* pt = A.part + ((int64_t)k * kBObjSplit + blk) * 3;
+        pt[0] = s_tc;
+        pt[1] = s_ent;
+        pt[2] = s_sp;
     }
+}
+
+// Per problem: the partials of its blocks in block order.
+__global__ void k_b_obj_final(BObjArgs A, int count) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    if (A.row_ptr[A.rows] > A.cap || A.col_ptr[A.cols] > A.cap) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < kBObjSplit; ++b)
+        for (int q = 0; q < 3; ++q) s[q] += A.part[((int64_t)k * kBObjSplit + b) * 3 + q];
+    A.stat[k].transport = s[0];
+    A.stat[k].negent = s[1];
+    A.stat[k].sparseobj = s[2];
 }
 
 template <int PREC, int D>
 static void run_b_obj(int count, const BObjArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((k_b_objective<PREC, D>), dim3(count), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_b_objective<PREC, D>), dim3((unsigned)(count * kBObjSplit)), dim3(256), 0,
+                       st, a);
+    hipLaunchKernelGGL(k_b_obj_final, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, a,
+                       count);
 }
 
 template <int D>

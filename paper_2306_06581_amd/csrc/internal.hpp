@@ -455,7 +455,9 @@ struct BObjArgs {
     const double *x, *y;
     int64_t rows, cols, cap;
     const int64_t* col_ptr;
+    double* part;  // [count][kBObjSplit][3] block partials
 };
+constexpr int kBObjSplit = 8;  // objective blocks per problem
 
 hipError_t launch_batch_sample(int precision, const BatchArgs& a, int64_t ntile_cmax,
                                int64_t ntile_mask, int64_t ntile_tr, int64_t* scan_scratch,
