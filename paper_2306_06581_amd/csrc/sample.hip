@@ -1250,29 +1250,101 @@ __device__ double block_tree4096(const double* v, int64_t n, double* sh) {
     return r;
 }
 
+// Block maximum (1024 threads); the result is in every thread.
+__device__ __forceinline__ double block_max1024(double x, double* sh) {
+    x = group_max<kWave>(x);
+    __syncthreads();  // sh is free
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = x;
+    __syncthreads();
+    double r = sh[0];
+    for (int w = 1; w < 1024 / kWave; ++w) r = sh[w] > r ? sh[w] : r;
+    return r;
+}
+
+// Exact cost maximum of every problem, one block of 1024 threads per problem,
+// pruned like the single-problem scan: with c the mean of y (fixed-order tree
+// sums) and R = max_j |y_j - c|, row i reaches at most (|x_i - c| + R)^2 (the
+// triangle inequality, with a 1e-9 relative margin for rounding); the full
+// row of the x farthest from c gives a lower bound L, and only rows whose
+// bound reaches L are scanned, with the brute-force distance code.  The row
+// holding the maximum always survives, so the result is the brute-force
+// maximum bit for bit.
 template <int D>
-__global__ __launch_bounds__(256) void k_b_cmax(BatchArgs A) {
-    const int k = owner_of(A.tile_cmax, A.count, blockIdx.x);
+__global__ __launch_bounds__(1024) void k_b_cmax(BatchArgs A) {
+    __shared__ double v[kBatchMaxSide];
+    __shared__ double sh[1024];
+    __shared__ double cen[64];
+    __shared__ int surv[kBatchMaxSide];
+    __shared__ int nsurv, far_row;
+    const int k = blockIdx.x;
     const BProb P = A.prob[k];
-    const int64_t t = blockIdx.x - A.tile_cmax[k];
-    const int64_t nct = (P.m + kCostTileCols - 1) / kCostTileCols;
-    const int64_t rt = t / nct, ct = t % nct;
     const int d = A.d;
+    const int tid = threadIdx.x;
     const double* x = A.x + P.xo * d;
     const double* y = A.y + P.yo * d;
-    const int64_t i = rt * 256 + threadIdx.x;
-    const int64_t j0 = ct * kCostTileCols;
-    const int64_t j1 = (j0 + kCostTileCols < P.m) ? j0 + kCostTileCols : P.m;
-    double mx = 0.0;
-    if (i < P.n) {
-        for (int64_t j = j0; j < j1; ++j) {
+    // centre: mean of y per coordinate
+    for (int c = 0; c < d; ++c) {
+        for (int64_t j = tid; j < P.m; j += 1024) v[j] = y[j * d + c];
+        const double sum = block_tree4096(v, P.m, sh);
+        __syncthreads();  // every thread has the sum before v is rewritten
+        if (tid == 0) cen[c] = sum / (double)P.m;
+    }
+    __syncthreads();
+    // R^2 = max_j |y_j - c|^2; |x_i - c| into v
+    double r2 = 0.0;
+    for (int64_t j = tid; j < P.m; j += 1024) {
+        double acc = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double t = y[j * d + c] - cen[c];
+            acc = acc + t * t;
+        }
+        r2 = acc > r2 ? acc : r2;
+    }
+    const double R = sqrt(block_max1024(r2, sh));
+    double rmax = -1.0;
+    for (int64_t i = tid; i < P.n; i += 1024) {
+        double acc = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double t = x[i * d + c] - cen[c];
+            acc = acc + t * t;
+        }
+        v[i] = sqrt(acc);
+        rmax = v[i] > rmax ? v[i] : rmax;
+    }
+    rmax = block_max1024(rmax, sh);
+    if (tid == 0) {
+        far_row = (int)P.n;
+        nsurv = 0;
+    }
+    __syncthreads();
+    // the farthest row (smallest index among ties)
+    for (int64_t i = tid; i < P.n; i += 1024)
+        if (v[i] == rmax) atomicMin(&far_row, (int)i);
+    __syncthreads();
+    const int64_t f = far_row;
+    double lb = 0.0;
+    for (int64_t j = tid; j < P.m; j += 1024) {
+        const double c = sqdist<D>(x + f * d, y + j * d, d);
+        lb = c > lb ? c : lb;
+    }
+    const double L = block_max1024(lb, sh);
+    // survivors (any order: the maximum is order-free)
+    for (int64_t i = tid; i < P.n; i += 1024) {
+        const double b = (v[i] + R) * (v[i] + R) * (1.0 + 1e-9);
+        if (b >= L) surv[atomicAdd(&nsurv, 1)] = (int)i;
+    }
+    __syncthreads();
+    const int ns = nsurv;
+    double mx = L;
+    for (int q = 0; q < ns; ++q) {
+        const int64_t i = surv[q];
+        for (int64_t j = tid; j < P.m; j += 1024) {
             const double c = sqdist<D>(x + i * d, y + j * d, d);
             mx = c > mx ? c : mx;
         }
     }
-    mx = group_max<kWave>(mx);
-    if ((threadIdx.x & (kWave - 1)) == 0)
-        atomicMax((unsigned long long*)&A.stat[k].cmax, (unsigned long long)__double_as_longlong(mx));
+    mx = block_max1024(mx, sh);
+    if (tid == 0) A.stat[k].cmax = mx;
 }
 
 // One block (1024 threads) per problem: C scale, S_a, S_b (tree sums of
@@ -1450,7 +1522,8 @@ __global__ __launch_bounds__(1024) void k_b_empty(BatchArgs A) {
 
 template <int D>
 static void run_b_cmax(const BatchArgs& a, int64_t nt, hipStream_t st) {
-    hipLaunchKernelGGL(k_b_cmax<D>, dim3((unsigned)nt), dim3(256), 0, st, a);
+    (void)nt;
+    hipLaunchKernelGGL(k_b_cmax<D>, dim3((unsigned)a.count), dim3(1024), 0, st, a);
 }
 
 template <int PREC, int D>
