@@ -87,25 +87,31 @@ __device__ __forceinline__ void opp_feature(const MlpArgs& A, const WSide& S, in
 
 // ---------------------------------------------------------------- inputs
 // C_s = max |x_i - y_j|^2 per problem (FP32, a feature scale): block (k, c)
-// scans rows [64 c, 64 c + 64) of problem k against all its columns; the
+// scans rows [64 c, 64 c + 64) of problem k (staged in LDS) against all its
+// columns (each loaded once by one thread); the
 // maximum is order-free, so one atomic max per block (non-negative floats
 // order like their bit patterns) gives the same value in any order.
 constexpr int kPrepRows = 64;
 
 __global__ __launch_bounds__(256) void k_ws_cmax(MlpArgs A, int chunks) {
     __shared__ float smax[4];
+    __shared__ float xs[kPrepRows][3];
     const int k = blockIdx.x / chunks, c = blockIdx.x % chunks;
     const WSide S = A.sides[2 * k];
     const int64_t n = S.npts, m = S.nopp;
     const double* x = A.x + 3 * S.pts_off;
     const double* y = A.y + 3 * S.opp_off;
+    const int64_t i0 = (int64_t)c * kPrepRows;
+    if (i0 >= n) return;  // the whole block
+    const int nr = (int)(n - i0 < kPrepRows ? n - i0 : kPrepRows);
+    // the block's rows in LDS; each column is loaded once and meets every row
+    if (threadIdx.x < nr * 3) xs[threadIdx.x / 3][threadIdx.x % 3] = (float)x[3 * i0 + threadIdx.x];
+    __syncthreads();
     float mx = 0.0f;
-    const int64_t i1 = (int64_t)(c + 1) * kPrepRows < n ? (int64_t)(c + 1) * kPrepRows : n;
-    for (int64_t i = (int64_t)c * kPrepRows; i < i1; ++i) {
-        const float x0 = (float)x[3 * i], x1 = (float)x[3 * i + 1], x2 = (float)x[3 * i + 2];
-        for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
-            const float d0 = x0 - (float)y[3 * j], d1 = x1 - (float)y[3 * j + 1],
-                        d2 = x2 - (float)y[3 * j + 2];
+    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
+        const float y0 = (float)y[3 * j], y1 = (float)y[3 * j + 1], y2 = (float)y[3 * j + 2];
+        for (int r = 0; r < nr; ++r) {
+            const float d0 = xs[r][0] - y0, d1 = xs[r][1] - y1, d2 = xs[r][2] - y2;
             mx = fmaxf(mx, d0 * d0 + d1 * d1 + d2 * d2);
         }
     }
@@ -151,11 +157,20 @@ __global__ __launch_bounds__(256) void k_ws_embed(MlpArgs A) {
     const int s = blockIdx.x, t = threadIdx.x;
     const WSide S = A.sides[s];
     const __bf16* wb = (const __bf16*)A.wbf;
+    // unit t's weights in registers (phi_pre's arithmetic, in its order)
+    const float pb = bf(wb, OFF_p + t);
+    float pw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pw[c] = bf(wb, OFF_P + 4 * t + c);
     float acc = 0.0f;
+#pragma unroll 4
     for (int64_t j = 0; j < S.nopp; ++j) {
         float f[4];
         opp_feature(A, S, j, f);
-        acc += fmaxf(phi_pre(wb, t, f), 0.0f);
+        float z = pb;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z = fmaf(pw[c], f[c], z);
+        acc += fmaxf(z, 0.0f);
     }
     const float e = acc / (float)S.nopp;
     e_s[t] = e;
@@ -486,11 +501,19 @@ __global__ __launch_bounds__(256) void k_ws_embed_bwd(MlpArgs A) {
     float de = 0.0f;  // (U^T dg)_t
     for (int r = 0; r < kH; ++r) de = fmaf(bf(wb, OFF_U + r * kH + t), dg_s[r], de);
     const float scale = de / (float)S.nopp;
+    const float pb = bf(wb, OFF_p + t);
+    float pw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pw[c] = bf(wb, OFF_P + 4 * t + c);
     float gP[4] = {0.f, 0.f, 0.f, 0.f}, gp = 0.f;
+#pragma unroll 4
     for (int64_t j = 0; j < S.nopp; ++j) {
         float f[4];
         opp_feature(A, S, j, f);
-        if (phi_pre(wb, t, f) > 0.0f) {
+        float z = pb;  // phi_pre with unit t's weights in registers
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z = fmaf(pw[c], f[c], z);
+        if (z > 0.0f) {
             gp += scale;
 #pragma unroll
             for (int c = 0; c < 4; ++c) gP[c] = fmaf(scale, f[c], gP[c]);
