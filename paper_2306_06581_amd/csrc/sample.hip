@@ -397,6 +397,40 @@ __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t
                 acc = fma(p, eb[j], acc);
             }
             acc = acc * (pp.row_bnd[i] * e_quarter);
+        } else if (pp.cost == kCostWfr) {
+            // WFR: q = exp(la + lb) cos(z)^(2 inv_tau).  cos z is its Taylor
+            // series in t = z^2 = c w^2 < (pi/2)^2 up to t^11 (truncation below
+            // 1e-19), so the pair needs no square root and no range reduction;
+            // blocked pairs (z >= pi/2) add nothing, and so does a pair whose
+            // cosine rounds to <= 0 at the boundary (its term is below 1e-90).
+            constexpr double c0 = 1.0, c1 = 1.0 / 2, c2 = 1.0 / 24, c3 = 1.0 / 720,
+                             c4 = 1.0 / 40320, c5 = 1.0 / 3628800, c6 = 1.0 / 479001600,
+                             c7 = 1.0 / 87178291200.0, c8 = 1.0 / 20922789888000.0,
+                             c9 = 1.0 / 6402373705728000.0, c10 = 1.0 / 2432902008176640000.0,
+                             c11 = 1.0 / 1124000727777607680000.0;
+            const double la = pp.row_fac[i];
+            const double w2 = pp.wfr_w * pp.wfr_w;
+            const double k2 = 2.0 * pp.inv_tau;
+            for (int64_t j = j0; j < j1; ++j) {
+                const double c = sqdist<D>(D > 0 ? xi : xp, pp.y + j * pp.d, pp.d);
+                const double t = c * w2;
+                if (t < kHalfPi * kHalfPi) {
+                    const double u = -t;  // cos z = sum_k u^k / (2k)!
+                    double p = c11;
+                    p = fma(p, u, c10);
+                    p = fma(p, u, c9);
+                    p = fma(p, u, c8);
+                    p = fma(p, u, c7);
+                    p = fma(p, u, c6);
+                    p = fma(p, u, c5);
+                    p = fma(p, u, c4);
+                    p = fma(p, u, c3);
+                    p = fma(p, u, c2);
+                    p = fma(p, u, c1);
+                    p = fma(p, u, c0);
+                    if (p > 0.0) acc = acc + exp((la + pp.col_fac[j]) + k2 * log(p));
+                }
+            }
         } else {
             const double la = pp.row_fac[i];
             for (int64_t j = j0; j < j1; ++j) {
