@@ -401,8 +401,8 @@ __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t
             // WFR: q = exp(la + lb) cos(z)^(2 inv_tau).  cos z is its Taylor
             // series in t = z^2 = c w^2 < (pi/2)^2 up to t^11 (truncation below
             // 1e-19), so the pair needs no square root and no range reduction;
-            // blocked pairs (z >= pi/2) add nothing, and so does a pair whose
-            // cosine rounds to <= 0 at the boundary (its term is below 1e-90).
+            // blocked pairs (z >= pi/2) add nothing, and neither does a pair
+            // whose series rounds to <= 0 (z within about 1e-16 of pi/2).
             constexpr double c0 = 1.0, c1 = 1.0 / 2, c2 = 1.0 / 24, c3 = 1.0 / 720,
                              c4 = 1.0 / 40320, c5 = 1.0 / 3628800, c6 = 1.0 / 479001600,
                              c7 = 1.0 / 87178291200.0, c8 = 1.0 / 20922789888000.0,
