@@ -72,6 +72,17 @@ def test_sample_wfr(api, pattern, ratio):
     assert np.all(np.isfinite(g["val"].cpu().numpy())) and np.all(g["val"].cpu().numpy() > 0)
 
 
+@pytest.mark.parametrize("lam,eps", [(5.0, 0.1), (0.02, 0.05), (0.1, 0.1)])
+def test_wfr_normaliser_exponents(api, lam, eps):
+    # the device evaluates cos(z)^(2/(2 lam + eps)) from a series in z^2; the
+    # exponent runs from about 0.2 (pairs near the blocking distance weigh in)
+    # to 22 (only close pairs count)
+    p = W.wfr_synthetic(700, d=5, seed=23, pattern="C2", nnz_ratio=0.6)
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p, lam=lam, eps=eps))
+    g = api.ss_sample(_prob(api, p), **_kw(p, lam=lam, eps=eps), precision="f64")
+    assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
+
+
 def test_spar_sink_uot_wfr_f64_fixed_iterations(api):
     p = W.wfr_synthetic(500, d=5, seed=22, nnz_ratio=0.5)
     T = 40
