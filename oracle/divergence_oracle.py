@@ -37,8 +37,8 @@ def plan_entries(res: O.SolveResult, log_domain: bool):
     cols = sk.col_idx.astype(np.int64)
     u, v = res.sinkhorn.u, res.sinkhorn.v
     if log_domain:
-        with np.errstate(divide="ignore"):
-            t = np.exp(np.log(u)[rows] + sk.logval + np.log(v)[cols])
+        lu, lv = res.sinkhorn.logs()
+        t = np.exp(lu[rows] + sk.logval + lv[cols])
     else:
         t = u[rows] * sk.val * v[cols]
     return rows, cols, t

@@ -192,14 +192,18 @@ class EmptySupportError(RuntimeError):
     pass
 
 
+class NonFiniteError(RuntimeError):
+    """A scaling became NaN or +inf (the library reports SS_E_NONFINITE)."""
+
+
 def is_uot(opt: Options) -> bool:
     return math.isfinite(opt.lam)
 
 
-def cost_scale(x, y, opt: Options) -> tuple[float, float]:
+def cost_scale(x, y, opt: Options, workers: int = 1) -> tuple[float, float]:
     """(cmax, inv_cmax) -- C_ij = c_ij * inv_cmax for the squared Euclidean
     costs (cmax is reported for every cost)."""
-    cmax = max_sq_dist(x, y)
+    cmax = max_sq_dist(x, y, workers=workers)
     if opt.cost == "maxnorm":
         return cmax, (1.0 / cmax if cmax > 0 else 1.0)
     return cmax, 1.0
@@ -352,29 +356,35 @@ def sample_rows(x, y, a, b, opt: Options, rows, prob=None, inv_cmax=None):
     return keep, pst, u01
 
 
-def build_sketch(x, y, a, b, opt: Options, chunk: int = 256, prob=None) -> Sketch:
+def build_sketch(x, y, a, b, opt: Options, chunk: int = 256, prob=None,
+                 workers: int = 1) -> Sketch:
     """Alg. 3/4 step 1: construct K~ by eq. (pois) with eq. (pij-ot)/(pij-uot),
-    or with the given probabilities `prob` (an object with pstar(rows, cols))."""
+    or with the given probabilities `prob` (an object with pstar(rows, cols)).
+    `workers` > 1 scans row chunks on a thread pool; every decision and value
+    is the same."""
     x = np.asarray(x, np.float64)
     y = np.asarray(y, np.float64)
     n, m = x.shape[0], y.shape[0]
-    cmax, inv_cmax = cost_scale(x, y, opt)
+    cmax, inv_cmax = cost_scale(x, y, opt, workers=workers)
     if prob is not None:
         pass
     elif is_uot(opt):
         prob = uot_probabilities(a, b, x, y, opt.s, opt.lam, opt.eps, inv_cmax,
-                                 shrink=opt.shrink, cost=opt.cost, eta=opt.eta)
+                                 shrink=opt.shrink, cost=opt.cost, eta=opt.eta, workers=workers)
     else:
         prob = ot_probabilities(a, b, opt.s, shrink=opt.shrink)
-    masks, ri, ci, pvals = [], [], [], []
-    for r0 in range(0, n, chunk):
+
+    def one_chunk(r0):
         rows = np.arange(r0, min(n, r0 + chunk))
         keep, pst, _ = sample_rows(x, y, a, b, opt, rows, prob)
-        masks.append(_pack_mask(keep))
         rr, cc = np.nonzero(keep)
-        ri.append(rows[rr])
-        ci.append(cc)
-        pvals.append(pst[rr, cc])
+        return _pack_mask(keep), rows[rr], cc, pst[rr, cc]
+
+    parts = _map_chunks(one_chunk, range(0, n, chunk), workers)
+    masks = [q[0] for q in parts]
+    ri = [q[1] for q in parts]
+    ci = [q[2] for q in parts]
+    pvals = [q[3] for q in parts]
     mask = np.concatenate(masks, axis=0) if masks else np.zeros((0, (m + 63) // 64), np.uint64)
     ri = np.concatenate(ri).astype(np.int64) if ri else np.zeros(0, np.int64)
     ci = np.concatenate(ci).astype(np.int64) if ci else np.zeros(0, np.int64)
@@ -452,6 +462,17 @@ class SinkhornResult:
     err: float
     hist: list
     converged: bool
+    # log-domain runs: the potentials f = log u, g = log v themselves (exp(f)
+    # may overflow where f is finite)
+    log_u: np.ndarray | None = None
+    log_v: np.ndarray | None = None
+
+    def logs(self):
+        """(log u, log v), from the potentials where the run kept them."""
+        if self.log_u is not None:
+            return self.log_u, self.log_v
+        with np.errstate(divide="ignore"):
+            return np.log(self.u), np.log(self.v)
 
 
 def _quotient(num, den, th):
@@ -471,7 +492,23 @@ def marginal_error(K, KT, u, v, a, b, th, row_active, col_active) -> float:
     vp = v if th == 1.0 else v ** (1.0 / th)
     # only active lines enter (an empty line's scaling may be infinite)
     ra, ca = row_active, col_active
-    return float(np.abs(up[ra] * kv[ra] - a[ra]).sum() + np.abs(vp[ca] * ktu[ca] - b[ca]).sum())
+    err = float(np.abs(up[ra] * kv[ra] - a[ra]).sum() + np.abs(vp[ca] * ktu[ca] - b[ca]).sum())
+    if math.isnan(err):
+        raise NonFiniteError("the marginal error is NaN")
+    return err
+
+
+def _check_finite(u, v):
+    """Linear domain: every scaling finite (empty lines hold 0)."""
+    if not (np.all(np.isfinite(u)) and np.all(np.isfinite(v))):
+        raise NonFiniteError("a scaling is not finite")
+
+
+def _check_finite_log(f, g):
+    """Log domain: no potential NaN or +inf (-inf is a zero scaling)."""
+    for p in (f, g):
+        if np.any(np.isnan(p)) or np.any(p == np.inf):
+            raise NonFiniteError("a potential is NaN or +inf")
 
 
 def sinkhorn(K, a, b, opt: Options, row_active=None, col_active=None, u0=None, v0=None):
@@ -491,8 +528,10 @@ def sinkhorn(K, a, b, opt: Options, row_active=None, col_active=None, u0=None, v
     t = 0
     for t in range(1, opt.max_iter + 1):
         u_prev, v_prev = u, v
-        u = _quotient(a, K @ v, th)
-        v = _quotient(b, KT @ u, th)
+        with np.errstate(over="ignore"):
+            u = _quotient(a, K @ v, th)
+            v = _quotient(b, KT @ u, th)
+        _check_finite(u, v)
         if opt.stop_rule == "delta":
             err = float(np.abs(u - u_prev).sum() + np.abs(v - v_prev).sum())
         else:
@@ -541,6 +580,7 @@ def sinkhorn_log(sk: Sketch, a, b, opt: Options, row_active, col_active, f0=None
         lse_c = _segment_logsumexp(l_c + f[order_rows], sk.col_ptr)
         with np.errstate(invalid="ignore"):
             g = np.where(col_active, th * (lb - lse_c), -np.inf)
+        _check_finite_log(f, g)
         if opt.stop_rule == "delta":
             err = float(np.abs(np.exp(f) - np.exp(f_prev)).sum()
                         + np.abs(np.exp(g) - np.exp(g_prev)).sum())
@@ -553,7 +593,9 @@ def sinkhorn_log(sk: Sketch, a, b, opt: Options, row_active, col_active, f0=None
         hist.append(err)
         if err <= opt.tol:
             break
-    return SinkhornResult(u=np.exp(f), v=np.exp(g), iters=t, err=err, hist=hist,
+    with np.errstate(over="ignore"):
+        u, v = np.exp(f), np.exp(g)
+    return SinkhornResult(u=u, v=v, iters=t, err=err, hist=hist, log_u=f, log_v=g,
                           converged=err <= opt.tol)
 
 
@@ -570,15 +612,20 @@ class Estimate:
     sparse_objective: float  # <T~, C~> - eps H(T~) (+ lam KLs), C~ = -eps log K~
 
 
-def estimate_from_entries(rows, cols, t, cost, u, v, a, b, opt: Options) -> Estimate:
+def estimate_from_entries(rows, cols, t, cost, u, v, a, b, opt: Options,
+                          logs=None) -> Estimate:
+    """`logs` = (log u, log v) where the run kept its potentials."""
     pos = t > 0
     # entries with t = 0 carry no transport, also where C = +inf (WFR)
     transport = float(np.sum(t[pos] * cost[pos]))
     neg_ent = float(np.sum(t[pos] * (np.log(t[pos]) - 1.0)))
     row_sum = np.bincount(rows, weights=t, minlength=len(a))
     col_sum = np.bincount(cols, weights=t, minlength=len(b))
-    with np.errstate(divide="ignore"):
-        lu, lv = np.log(u), np.log(v)
+    if logs is not None:
+        lu, lv = logs
+    else:
+        with np.errstate(divide="ignore"):
+            lu, lv = np.log(u), np.log(v)
     sparse_obj = opt.eps * float(np.sum(t[pos] * (lu[rows[pos]] + lv[cols[pos]] - 1.0)))
     est = transport + opt.eps * neg_ent
     kl_a = kl_b = 0.0
@@ -606,11 +653,12 @@ class SolveResult:
     cmax: float
 
 
-def spar_sink(x, y, a, b, opt: Options) -> SolveResult:
-    """Alg. 3 (OT, lam = inf) and Alg. 4 (UOT)."""
+def spar_sink(x, y, a, b, opt: Options, workers: int = 1) -> SolveResult:
+    """Alg. 3 (OT, lam = inf) and Alg. 4 (UOT).  `workers`: threads of the
+    sketch's full scans (the result does not depend on it)."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
-    sk = build_sketch(x, y, a, b, opt)
+    sk = build_sketch(x, y, a, b, opt, workers=workers)
     row_cnt = np.diff(sk.row_ptr)
     col_cnt = np.diff(sk.col_ptr)
     a_eff, b_eff, ra, ca, da, db = apply_empty_policy(a, b, row_cnt, col_cnt, opt)
@@ -618,13 +666,12 @@ def spar_sink(x, y, a, b, opt: Options) -> SolveResult:
     cols = sk.col_idx.astype(np.int64)
     if opt.log_domain:
         res = sinkhorn_log(sk, a_eff, b_eff, opt, ra, ca)
-        with np.errstate(divide="ignore"):
-            lu, lv = np.log(res.u), np.log(res.v)
+        lu, lv = res.logs()
         t = np.exp(lu[rows] + sk.logval + lv[cols])
     else:
         res = sinkhorn(sk.csr(), a_eff, b_eff, opt, ra, ca)
         t = res.u[rows] * sk.val * res.v[cols]
-    est = estimate_from_entries(rows, cols, t, sk.cost, res.u, res.v, a, b, opt)
+    est = estimate_from_entries(rows, cols, t, sk.cost, res.u, res.v, a, b, opt, res.logs())
     return SolveResult(est, res, sk, sk.nnz, int(np.sum(~ra & (a > 0))),
                        int(np.sum(~ca & (b > 0))), da, db, sk.cmax)
 
@@ -640,14 +687,15 @@ def dense_sinkhorn(x, y, a, b, opt: Options) -> SolveResult:
     if opt.log_domain:
         sk = _dense_as_sketch(cost, opt, cmax, inv_cmax)
         res = sinkhorn_log(sk, a, b, opt, np.ones(n, bool), np.ones(m, bool))
-        with np.errstate(divide="ignore"):
-            t = np.exp(np.log(res.u)[:, None] - cost / opt.eps + np.log(res.v)[None, :])
+        lu, lv = res.logs()
+        t = np.exp(lu[:, None] - cost / opt.eps + lv[None, :])
     else:
         res = sinkhorn(K, a, b, opt)
         t = res.u[:, None] * K * res.v[None, :]
     rows = np.repeat(np.arange(n), m)
     cols = np.tile(np.arange(m), n)
-    est = estimate_from_entries(rows, cols, t.ravel(), cost.ravel(), res.u, res.v, a, b, opt)
+    est = estimate_from_entries(rows, cols, t.ravel(), cost.ravel(), res.u, res.v, a, b, opt,
+                                res.logs())
     return SolveResult(est, res, None, n * m, 0, 0, 0.0, 0.0, cmax)
 
 

@@ -6,9 +6,10 @@ The oracle cannot build a whole sketch at these sizes, so it computes the
 global scalars exactly (cmax; for UOT the normaliser Z, eq. (pij-uot)) and
 then, for a sample of rows and of columns, every keep decision, every stored
 value and the fixed-point residual of the returned scalings on its own K~.
-Bars as elsewhere: OT mask bits bit-exact; UOT mask bits equal except on the
-decision boundary |U - p*| <= 1e-12 p*; FP32 values within the rounding of
-FP32 storage; the sampled residual terms within the solver's reported error."""
+Bars as elsewhere: mask bits, offsets and indices bit-exact (OT and UOT; a
+failure names each differing position and its distance |U - p*| / p* to the
+keep boundary); FP32 values within the rounding of FP32 storage; the sampled
+residual terms within the solver's reported error."""
 import os
 
 import numpy as np
@@ -68,15 +69,10 @@ def _check_lines(side, lines, keep, pst, u01, cost, eps, gbits, ptr, idx, val, p
     """Mask bits, offsets, indices and values of the sampled lines."""
     for k, r in enumerate(lines):
         diff = np.nonzero(keep[k] != gbits[k])[0]
-        if diff.size:
-            # only possible for UOT: p* involves exponentials and a sum in a
-            # different order on the two sides
-            assert uot, (side, r, diff[:8])
-            assert np.all(np.abs(u01[k, diff] - pst[k, diff]) <= 1e-12 * pst[k, diff]), (side, r)
+        assert diff.size == 0, (side, int(r), [(int(c), float(abs(u01[k, c] - pst[k, c]) / pst[k, c]))
+                                               for c in diff[:8]])
         lo, hi = int(ptr[r]), int(ptr[r + 1])
         assert hi - lo == int(gbits[k].sum()), (side, r)
-        if diff.size:
-            continue
         pos = np.nonzero(keep[k])[0]
         assert np.array_equal(idx[lo:hi], pos), (side, r)
         c, ps = cost[k, pos], pst[k, pos]
@@ -168,3 +164,40 @@ def test_ot_scale_full_size(api):
                          tol=1e-6, max_iter=5000, precision="f32", return_scalings=True)
     assert r.status == 0 and r.marginal_err <= 1e-6
     _check_residual(p, r, L, 1.0)
+
+
+def test_ot_scale_full_size_whole_sketch_and_estimate(api):
+    """OT, n = m = 16384, d = 10, s = 8 n ln n, tol 1e-6: the oracle builds the
+    whole sketch (2.7e8 pairs on a thread pool) and solves it, so the whole
+    mask, CSR and CSC are compared bit for bit, the FP64 values within 8 ulp,
+    and the estimates of the FP64 and FP32 solves against the FP64 oracle's
+    (FP64 within 1e-9 relative at the same stopping iteration; FP32 within
+    the 1e-4 bar)."""
+    p = W.ot_t5_d10(16384, seed=0, s_factor=8.0)
+    o = O.spar_sink(p.x, p.y, p.a, p.b,
+                    O.Options(eps=p.eps, s=p.s, seed=p.seed, tol=1e-6, max_iter=5000),
+                    workers=WORKERS)
+    sk = o.sketch
+    prob = api.Problem(p.x, p.y, p.a, p.b, problem_index=p.problem_index)
+    g = api.ss_sample(prob, eps=p.eps, s=p.s, seed=p.seed, precision="f64")
+    assert g["nnz"] == sk.nnz
+    assert np.array_equal(g["mask"].cpu().numpy().view(np.uint64), sk.mask)
+    for k in ("row_ptr", "col_idx", "col_ptr", "row_idx"):
+        assert np.array_equal(g[k].cpu().numpy(), getattr(sk, k)), k
+    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=4e-16 * 8, atol=0)
+    np.testing.assert_allclose(g["val_t"].cpu().numpy(), sk.val_t, rtol=4e-16 * 8, atol=0)
+    del g
+    est, spo = o.estimate.estimate, o.estimate.sparse_objective
+    r64 = api.spar_sink_ot(prob, eps=p.eps, s=p.s, seed=p.seed, tol=1e-6, max_iter=5000,
+                           precision="f64")
+    assert r64.status == 0 and r64.iters == o.sinkhorn.iters and r64.nnz == o.nnz
+    assert r64.empty_rows == o.empty_rows and r64.empty_cols == o.empty_cols
+    assert abs(r64.estimate - est) <= 1e-9 * abs(est)
+    assert abs(r64.sparse_objective - spo) <= 1e-9 * abs(spo)
+    r32 = api.spar_sink_ot(prob, eps=p.eps, s=p.s, seed=p.seed, tol=1e-6, max_iter=5000,
+                           precision="f32")
+    assert r32.status == 0 and r32.marginal_err <= 1e-6
+    rel32 = abs(r32.estimate - est) / abs(est)
+    print(f"n=16384 OT: oracle estimate {est:.12f}, FP32 relative error {rel32:.2e}")
+    assert rel32 < 1e-4
+    assert abs(r32.sparse_objective - spo) <= 1e-4 * abs(spo)

@@ -2,10 +2,11 @@
 
 Bars: integer/index/bit outputs bit-exact; FP64 scalings and estimates within
 1e-10 relative; FP32 and log-FP32 estimates within 1e-4 relative of the FP64
-oracle.  For UOT the keep decision depends on exponentials (host libm vs
-device library, which may differ in the last bit) and on a normaliser summed
-in a different order, so any differing mask bit must sit on the decision
-boundary: |U - p*| <= 1e-12 p* (probability ~1e-15 per kept entry)."""
+oracle.  The UOT keep decision depends on exponentials (host libm against the
+device library) and on a normaliser summed in a different order, so a mask
+bit could differ where U lies within about 1e-15 of p* (expected count per
+case below 1e-8).  The UOT tests still require every bit to be equal; a
+failure reports the differing positions and their distance to the boundary."""
 import math
 
 import numpy as np
@@ -14,6 +15,7 @@ import torch
 
 from oracle import sparsink_oracle as O
 from paper_2306_06581_amd import workloads as W
+from maskcheck import assert_mask_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -95,20 +97,7 @@ def test_sample_precisions_share_the_mask(api):
 
 
 def _uot_mask_compare(g_mask, sk, p, rows):
-    """Equal bits, or differing bits on the decision boundary only."""
-    gm = g_mask[rows]
-    om = sk.mask[rows]
-    diff = gm ^ om
-    if not diff.any():
-        return 0
-    bits = np.unpackbits(diff.view(np.uint8), axis=1, bitorder="little")[:, : p.m]
-    rr, cc = np.nonzero(bits)
-    rr = np.asarray(rows)[rr]
-    u = O.uniform01(rr, cc, p.problem_index, p.seed)
-    pst = sk.prob.pstar(rr, cc)
-    pst = pst[np.arange(len(rr)), np.arange(len(rr))] if pst.ndim == 2 else pst
-    assert np.all(np.abs(u - pst) <= 1e-12 * pst), (rr, cc)
-    return len(rr)
+    assert_mask_equal(g_mask[rows], sk.mask[rows], p, sk.prob, rows)
 
 
 # lam = 1: the normaliser's short-range exponential (1/(2 lam + eps) <= 1/2);
@@ -119,10 +108,10 @@ def test_sample_uot(api, n, eps, lam):
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
     g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
     assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
-    nd = _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
-    if nd == 0:
-        _check_sketch_structure(g, sk)
-        np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-14)
+    _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
+    _check_sketch_structure(g, sk)
+    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-14)
+    np.testing.assert_allclose(g["val_t"].cpu().numpy(), sk.val_t, rtol=1e-14)
     np.testing.assert_allclose(g["row_fac"].cpu().numpy(), sk.prob.la, rtol=1e-15)
 
 
@@ -147,9 +136,8 @@ def test_sample_uot_dense_budget(api):
     p.s = 0.5 * p.n * p.m
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
     g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
-    nd = _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
-    if nd == 0:
-        _check_sketch_structure(g, sk)
+    _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
+    _check_sketch_structure(g, sk)
 
 
 def test_sample_uot_plain_cost(api):
@@ -159,10 +147,9 @@ def test_sample_uot_plain_cost(api):
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p, cost="plain"))
     g = api.ss_sample(_prob(api, p), **_kw(p), cost="plain", precision="f64")
     assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
-    nd = _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
-    if nd == 0:
-        _check_sketch_structure(g, sk)
-        np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-13)
+    _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
+    _check_sketch_structure(g, sk)
+    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-13)
 
 
 # ---------------------------------------------------------------- Sinkhorn loop

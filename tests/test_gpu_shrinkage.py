@@ -2,8 +2,9 @@
 (Sec. 5, g = 1) between the HIP path and the CPU FP64 oracle.
 
 Only the probability stage changes, so the bars are the sampling ones: for OT
-the mask, CSR and CSC bit for bit and the row factors exactly; for UOT
-differing mask bits only on the decision boundary |U - p*| <= 1e-12 p*; the
+the mask, CSR and CSC bit for bit and the row factors exactly; for UOT the
+mask and CSR/CSC bit for bit as well (a failure names the differing positions
+and their distance to the keep boundary) and the values within 1e-14; the
 Sinkhorn iterates on the same sketch within 1e-10 relative (FP64)."""
 import math
 
@@ -13,6 +14,7 @@ import torch
 
 from oracle import sparsink_oracle as O
 from paper_2306_06581_amd import workloads as W
+from maskcheck import assert_mask_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -86,17 +88,10 @@ def test_sample_uot_shrink(api, lam, g):
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p, shrink=g))
     out = api.ss_sample(_prob(api, p), **_kw(p), shrink=g, precision="f64")
     assert out["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
-    gm = _mask_np(out["mask"])
-    diff = gm ^ sk.mask
-    if diff.any():
-        bits = np.unpackbits(diff.view(np.uint8), axis=1, bitorder="little")[:, : p.m]
-        rr, cc = np.nonzero(bits)
-        u = O.uniform01(rr, cc, p.problem_index, p.seed)
-        pst = np.array([sk.prob.pstar(np.array([r]), np.array([c]))[0, 0] for r, c in zip(rr, cc)])
-        assert np.all(np.abs(u - pst) <= 1e-12 * pst), (rr, cc)
-    else:
-        _structure_equal(out, sk)
-        np.testing.assert_allclose(out["val"].cpu().numpy(), sk.val, rtol=1e-14)
+    assert_mask_equal(_mask_np(out["mask"]), sk.mask, p, sk.prob)
+    _structure_equal(out, sk)
+    np.testing.assert_allclose(out["val"].cpu().numpy(), sk.val, rtol=1e-14)
+    np.testing.assert_allclose(out["val_t"].cpu().numpy(), sk.val_t, rtol=1e-14)
 
 
 @pytest.mark.parametrize("g", [0.5, 1.0])

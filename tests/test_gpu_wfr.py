@@ -1,8 +1,8 @@
 """Parity of the Wasserstein-Fisher-Rao cost (UOT background section; the
 paper's UOT simulation) between the HIP path, through the C ABI, and the CPU
-FP64 oracle: sampling (UOT bars: mask bits equal except on the decision
-boundary, no structural zero ever kept), the sparse and dense FP64 iterates
-within 1e-10, and the reduced-precision estimates within 1e-4."""
+FP64 oracle: sampling (mask and CSR bit for bit, values within 1e-13, no
+structural zero ever kept), the sparse and dense FP64 iterates within 1e-10,
+and the reduced-precision estimates within 1e-4."""
 import math
 
 import numpy as np
@@ -11,6 +11,7 @@ import torch
 
 from oracle import sparsink_oracle as O
 from paper_2306_06581_amd import workloads as W
+from maskcheck import assert_mask_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -51,19 +52,12 @@ def test_sample_wfr(api, pattern, ratio):
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
     g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
     assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
-    gm = g["mask"].cpu().numpy().view(np.uint64)
-    diff = gm ^ sk.mask
-    if diff.any():
-        bits = np.unpackbits(diff.view(np.uint8), axis=1, bitorder="little")[:, : p.m]
-        rr, cc = np.nonzero(bits)
-        u = O.uniform01(rr, cc, p.problem_index, p.seed)
-        pst = np.array([sk.prob.pstar(np.array([r]), np.array([c]))[0, 0] for r, c in zip(rr, cc)])
-        assert np.all(np.abs(u - pst) <= 1e-12 * pst), (rr, cc)
-    else:
-        assert g["nnz"] == sk.nnz
-        assert np.array_equal(g["col_idx"].cpu().numpy(), sk.col_idx)
-        assert np.array_equal(g["row_ptr"].cpu().numpy(), sk.row_ptr)
-        np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-13)
+    assert_mask_equal(g["mask"].cpu().numpy().view(np.uint64), sk.mask, p, sk.prob)
+    assert g["nnz"] == sk.nnz
+    for k in ("row_ptr", "col_idx", "col_ptr", "row_idx"):
+        assert np.array_equal(g[k].cpu().numpy(), getattr(sk, k)), k
+    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-13)
+    np.testing.assert_allclose(g["val_t"].cpu().numpy(), sk.val_t, rtol=1e-13)
     # no kept entry lies at or beyond the blocking distance pi eta
     rows = np.repeat(np.arange(p.n), np.diff(g["row_ptr"].cpu().numpy()))
     cols = g["col_idx"].cpu().numpy()

@@ -242,6 +242,10 @@ def test_two_by_two_closed_form():
     T = r.sinkhorn.u[:, None] * K * r.sinkhorn.v[None, :]
     expect = np.array([[t, a1 - t], [b1 - t, 1 - a1 - b1 + t]])
     assert np.allclose(T, expect, rtol=1e-12, atol=1e-15)
+    # the stop test fired on its own: Sinkhorn's linear convergence reaches the
+    # rounding floor within a few dozen iterations, and a wrong residual (one
+    # that does not vanish at the closed-form plan) would run to max_iter
+    assert r.sinkhorn.converged and r.sinkhorn.iters < 200
 
 
 @pytest.mark.parametrize("eps", [1e-1, 1e-2, 1e-3])
@@ -313,6 +317,7 @@ def test_uot_single_point_closed_form():
     t = r.sinkhorn.u[0] * math.exp(-C / eps) * r.sinkhorn.v[0]
     assert t == pytest.approx((0.7 * 1.9) ** (lam / (2 * lam + eps)) * math.exp(-C / (2 * lam + eps)),
                               rel=1e-12)
+    assert r.sinkhorn.converged and r.sinkhorn.iters < 200
 
 
 def test_uot_matches_direct_convex_minimisation():
@@ -337,6 +342,7 @@ def test_uot_matches_direct_convex_minimisation():
     opt = O.Options(eps=eps, s=1e9, lam=lam, tol=1e-14, max_iter=100000, cost="plain")
     r = O.dense_sinkhorn(x, y, a, b, opt)
     assert r.estimate.estimate == pytest.approx(res.fun, rel=1e-8, abs=1e-10)
+    assert r.sinkhorn.converged and r.sinkhorn.iters < 500
 
 
 def test_uot_large_lambda_approaches_ot():
@@ -382,9 +388,11 @@ def test_estimate_error_shrinks_with_budget():
     for factor in (2.0, 32.0):
         e = []
         for seed in range(3):
+            # log domain: at the small budget some rows keep only entries whose
+            # K~ underflows, and linear scalings would overflow there
             r = O.spar_sink(p.x, p.y, p.a, p.b,
                             O.Options(eps=p.eps, s=factor * 400 * math.log(400), tol=1e-10,
-                                      seed=seed, max_iter=2000))
+                                      seed=seed, max_iter=2000, log_domain=True))
             e.append(abs(r.estimate.sparse_objective - dense.estimate.estimate))
         errs.append(np.mean(e))
     assert errs[1] < errs[0]
@@ -400,3 +408,97 @@ def test_thread_pool_scans_match_the_serial_scans():
     z4 = O.uot_probabilities(p.a, p.b, p.x, p.y, p.s, p.lam, p.eps, 1.0 / c1, chunk=37,
                              workers=4).z
     assert z1 == z4
+
+
+# ---------------------------------------------------------------- stop residual
+def _plan(K, u, v):
+    """T = diag(u) K diag(v) for a dense array or a scipy sparse matrix."""
+    if hasattr(K, "multiply"):
+        return K.multiply(u[:, None]).multiply(v[None, :]).tocsr()
+    return u[:, None] * K * v[None, :]
+
+
+def _residual_from_plan(T, u, v, a, b, lam, eps, ra, ca):
+    """The stop residual recomputed from the plan's own marginals.
+
+    OT (Alg. 1): |T 1 - a|_1 + |T^T 1 - b|_1.  UOT (Alg. 2): the first-order
+    conditions of eq. (ruot) at a plan T = diag(u) K diag(v) read
+    lam log((T1)_i / a_i) + eps log u_i = 0, i.e. u_i^(eps/lam) (T1)_i = a_i
+    (likewise for columns); the residual is the L1 defect of that identity.
+    """
+    r = np.asarray(T.sum(axis=1)).ravel()
+    c = np.asarray(T.sum(axis=0)).ravel()
+    if math.isfinite(lam):
+        r = r * u ** (eps / lam)
+        c = c * v ** (eps / lam)
+    return float(np.abs(r - a)[ra].sum() + np.abs(c - b)[ca].sum())
+
+
+@pytest.mark.parametrize("lam", [math.inf, 0.7])
+@pytest.mark.parametrize("log_domain", [False, True])
+def test_stop_residual_is_the_plan_marginal_defect_dense(lam, log_domain):
+    p = W.uot_mix3(60, seed=21, eps=0.1)
+    opt = O.Options(eps=0.1, s=1e9, lam=lam, tol=0.0, max_iter=7, log_domain=log_domain)
+    r = O.dense_sinkhorn(p.x, p.y, p.a, p.b, opt)
+    C = scipy.spatial.distance.cdist(p.x, p.y, "sqeuclidean") / r.cmax
+    u, v = r.sinkhorn.u, r.sinkhorn.v
+    T = _plan(np.exp(-C / 0.1), u, v)
+    ones = np.ones(60, bool)
+    want = _residual_from_plan(T, u, v, p.a, p.b, lam, 0.1, ones, ones)
+    assert len(r.sinkhorn.hist) == 7
+    assert r.sinkhorn.hist[-1] == pytest.approx(want, rel=1e-9)
+    assert want > 1e-6        # still far from the fixed point after 7 iterations
+
+
+@pytest.mark.parametrize("lam", [math.inf, 1.0])
+@pytest.mark.parametrize("log_domain", [False, True])
+def test_stop_residual_is_the_plan_marginal_defect_sparse(lam, log_domain):
+    # on the sketch, over the lines with entries, with the marginals the loop uses
+    p = W.uot_mix3(300, seed=22, eps=0.05)
+    opt = O.Options(eps=0.05, s=p.s, lam=lam, tol=0.0, max_iter=9, seed=3,
+                    log_domain=log_domain)
+    r = O.spar_sink(p.x, p.y, p.a, p.b, opt)
+    sk = r.sketch
+    a_eff, b_eff, ra, ca, _, _ = O.apply_empty_policy(p.a, p.b, np.diff(sk.row_ptr),
+                                                       np.diff(sk.col_ptr), opt)
+    u, v = r.sinkhorn.u, r.sinkhorn.v
+    T = _plan(sk.csr(), u, v)
+    want = _residual_from_plan(T, u, v, a_eff, b_eff, lam, 0.05, ra, ca)
+    assert r.sinkhorn.hist[-1] == pytest.approx(want, rel=1e-8)
+    assert want > 1e-8
+
+
+def test_stop_residual_vanishes_at_the_uot_closed_form():
+    # n = m = 1: u^(eps/lam) T = a holds at the optimum of eq. (ruot), and the
+    # loop stops there by its residual test (not by max_iter)
+    x, y = np.array([[0.0, 0.0]]), np.array([[0.6, 0.8]])
+    a, b = np.array([0.7]), np.array([1.9])
+    lam, eps = 0.8, 0.3
+    r = O.dense_sinkhorn(x, y, a, b, O.Options(eps=eps, s=1e9, lam=lam, tol=1e-13,
+                                               max_iter=10000, cost="plain"))
+    assert r.sinkhorn.converged and r.sinkhorn.iters < 200
+    u, v = r.sinkhorn.u[0], r.sinkhorn.v[0]
+    t = u * math.exp(-1.0 / eps) * v
+    assert abs(u ** (eps / lam) * t - 0.7) + abs(v ** (eps / lam) * t - 1.9) <= 1e-13
+    assert r.sinkhorn.err <= 1e-13
+
+
+def test_overflowing_scaling_raises():
+    # K = exp(-712) is subnormal: u = a / K overflows; the library reports
+    # SS_E_NONFINITE there and the oracle raises instead of iterating on NaN
+    x, y = np.array([[0.0]]), np.array([[1.0]])
+    a = b = np.array([0.5])
+    with pytest.raises(O.NonFiniteError):
+        O.dense_sinkhorn(x, y, a, b, O.Options(eps=1.0 / 712.0, s=1e9, cost="plain",
+                                               tol=1e-12, max_iter=10))
+
+
+def test_thread_pool_sketch_matches_the_serial_sketch():
+    p = W.uot_mix3(500, seed=32, eps=0.05)
+    for lam in (math.inf, 1.0):
+        opt = O.Options(eps=p.eps, s=p.s, lam=lam, seed=5)
+        s1 = O.build_sketch(p.x, p.y, p.a, p.b, opt)
+        s4 = O.build_sketch(p.x, p.y, p.a, p.b, opt, chunk=37, workers=4)
+        for k in ("mask", "row_ptr", "col_idx", "val", "logval", "col_ptr", "row_idx", "val_t"):
+            assert np.array_equal(getattr(s1, k), getattr(s4, k)), k
+        assert s1.cmax == s4.cmax
