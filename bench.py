@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--eps", type=float, default=0.05)
+    ap.add_argument("--s-factor", type=float, default=8.0,
+                    help="budget s = factor * n ln n of the headline workload")
     ap.add_argument("--precision", default="f32_log")
     ap.add_argument("--dense-precision", default="auto")
     ap.add_argument("--dense-runs", type=int, default=1)
@@ -437,15 +439,19 @@ def main():
     from paper_2306_06581_amd import workloads as W
 
     torch.cuda.set_device(0)
-    p = W.uot_mix3(args.n, seed=0, eps=args.eps)
+    p = W.uot_mix3(args.n, seed=0, eps=args.eps, s_factor=args.s_factor)
     prob = A.Problem(p.x, p.y, p.a, p.b)
     kw = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, tol=1e-6, max_iter=5000,
               precision=args.precision)
     if args.kernel_only:
         ms_launch = A.ss_time_iterations(prob, args.timing_iters, eps=p.eps, s=p.s, lam=p.lam,
                                          seed=p.seed, precision=args.precision)
-        print(json.dumps({"kernel": "k_iterate", "ms_per_launch": ms_launch,
-                          "launches": 4 * args.timing_iters}))
+        r = A.spar_sink_uot(prob, **dict(kw, max_iter=1), raise_on_error=False)
+        by = iteration_bytes_per_launch(args.precision, r.nnz, p.n, p.m)
+        print(json.dumps({"kernel": "k_iterate", "n": p.n, "s_factor": args.s_factor,
+                          "nnz": r.nnz, "ms_per_launch": ms_launch,
+                          "launches": 4 * args.timing_iters, "bytes_per_launch": by,
+                          "GBps": by / (ms_launch * 1e-3) / 1e9}))
         return
 
     for _ in range(args.warmup):

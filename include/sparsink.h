@@ -133,13 +133,17 @@ typedef struct ss_options {
  * dropped_mass_a/b  mass of a / b on empty rows / columns.
  * nnz, empty_rows, empty_cols  size of K~ and its empty lines (with a_i>0 / b_j>0).
  * iters       t of the returned iterate.   status  same as the return value.
- * t_*_ms      stage times measured with HIP events on `stream`. */
+ * t_*_ms      stage times measured with HIP events on `stream`.
+ * warm_start  the start given by init_log_u / init_log_v: -1 none given;
+ *             1 used; 0 (spar_sink_batched only) judged worse than the plain
+ *             start u = v = 1 and replaced by it (see spar_sink_batched). */
 typedef struct ss_result {
     double estimate, transport, neg_entropy, kl_a, kl_b, sparse_objective;
     double marginal_err, cmax, z_norm, dropped_mass_a, dropped_mass_b;
     int64_t nnz, empty_rows, empty_cols;
     int32_t iters, status;
     float t_prep_ms, t_sample_ms, t_iter_ms, t_obj_ms;
+    int32_t warm_start, reserved;
 } ss_result;
 
 /* Caller-allocated device arrays receiving the sparse sketch (ss_sample).
@@ -257,7 +261,14 @@ int ss_batch_workspace_size(const ss_batch *batch, const ss_options *opts, size_
  * (spar_sink_ot's path, the same sketch) from its iterate for the remaining
  * max_iter - 64 iterations (its outs[k] is then that solve's result with
  * iters counted from the start); with more such problems the persistent
- * launch is run again from the start to max_iter.  `schedule` NULL picks
+ * launch is run again from the start to max_iter.  A warm start
+ * (opts->init_log_u / init_log_v, e.g. from ss_warmstart_predict; zero-init
+ * Sinkhorn is its fallback) is judged per problem in its first u-update
+ * against the plain start u = v = 1: it is kept only when every start value
+ * and its u^1 are finite and its L1 row marginal error sum |u0 (K~v0) - a| is
+ * no larger than the plain start's sum |K~1 - a|; otherwise the problem
+ * continues from the plain start and its iterates are those of a solve
+ * without a warm start (outs[k].warm_start = 0).  `schedule` NULL picks
  * the schedule with ss_autotune_batched (cached per process for batches of
  * the same precision and size class).  outs: host array [count]; each entry
  * is filled as by spar_sink_ot (z_norm 0; stage times are those of the whole

@@ -72,6 +72,8 @@ class Result:
     t_sample_ms: float
     t_iter_ms: float
     t_obj_ms: float
+    warm_start: int = -1
+    reserved: int = 0
     u: Optional[torch.Tensor] = None
     v: Optional[torch.Tensor] = None
     err_hist: Optional[torch.Tensor] = None

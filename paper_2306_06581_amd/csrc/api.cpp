@@ -658,6 +658,7 @@ void fill_result(const Ctx& c, const IterState& hs, ss_result* R, int64_t nnz) {
     R->empty_rows = (int64_t)s[ST_EMPTY_ROWS];
     R->empty_cols = (int64_t)s[ST_EMPTY_COLS];
     R->iters = hs.stop_iter;
+    R->warm_start = (O->init_log_u || O->init_log_v) ? 1 : -1;
 }
 
 // time_iters > 0: after sampling, run exactly time_iters iterations (tol = 0)
@@ -1617,6 +1618,7 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
         R.empty_cols = (int64_t)S.empty_cols;
         R.iters = S.iters;
         R.status = S.status;
+        R.warm_start = S.warm;
         R.t_prep_ms = t_tune;
         R.t_sample_ms = t_sample;
         R.t_iter_ms = t_iter;
@@ -1667,6 +1669,7 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
             R.t_prep_ms = outs[k].t_prep_ms;
             R.t_sample_ms = outs[k].t_sample_ms;
             R.t_obj_ms = outs[k].t_obj_ms;
+            R.warm_start = outs[k].warm_start;  // the batch loop's judgement of the start
             outs[k] = R;
         }
         th.mark(1, c.st);

@@ -10,6 +10,15 @@
 // is reduced by a group of L lanes; the sparse entries stream from HBM with
 // 16-bit local indices, the gathered scaling comes from LDS.
 //
+// A warm start (init_log_u / init_log_v) is judged against the plain start
+// u = v = 1 in the problem's first u-update: the same pass forms K~v0 and K~1,
+// so it yields both candidates for u^1 and the L1 row marginal error of both
+// starting points, sum |u0_i (K~v0)_i - a_i| and sum |(K~1)_i - a_i| (over
+// rows with entries).  The start is kept only when it is finite, its u^1 is
+// finite and its error is no larger than the plain start's; otherwise the
+// problem continues from the plain start's u^1, so its iterates are exactly
+// those of a solve without a warm start.
+//
 // The stop test is the one of the single-problem solver: err(t) is the L1
 // marginal error of the iterate (u^t, v^t) on K~ -- the column part is formed
 // in the v-update of iteration t, the row part in the u-update of iteration
@@ -70,6 +79,57 @@ __device__ __forceinline__ double b_half(const int64_t* __restrict__ ptr,
     return res;
 }
 
+// The first u-update of a warm-started problem: one pass over the rows forms
+// w = K~ v0 and w1 = K~ 1 (the plain start's product, added in the same order
+// as the fma of b_half with a gathered 1, so the plain u^1 is bit-identical to
+// a cold solve's).  Writes the warm u^1 to uw and the plain u^1 over u0 (row r
+// is read and written by the same lane only).  Returns this thread's shares of
+// sum |u0_r w_r - a_r| and sum |w1_r - a_r| over rows with entries; *badw and
+// *badp flag a non-finite warm or plain u^1.
+template <int PREC, int L>
+__device__ __forceinline__ void b_first_judged(const int64_t* __restrict__ ptr,
+                                               const uint16_t* __restrict__ idx,
+                                               const typename BTypes<PREC>::V* __restrict__ val,
+                                               int64_t nl, const typename BTypes<PREC>::V* v0,
+                                               typename BTypes<PREC>::V* u0,
+                                               typename BTypes<PREC>::V* uw,
+                                               const double* __restrict__ marg, double* rw,
+                                               double* rp, int* badw, int* badp) {
+    typedef typename BTypes<PREC>::V V;
+    const int lane = threadIdx.x % L;
+    const int g = threadIdx.x / L, ng = blockDim.x / L;
+    double sw = 0.0, sp = 0.0;
+    for (int64_t r = g; r < nl; r += ng) {
+        const int64_t k0 = ptr[r], k1 = ptr[r + 1];
+        V acc = 0, acc1 = 0;
+        for (int64_t k = k0 + lane; k < k1; k += L) {
+            const V e = val[k];
+            acc = fma(e, v0[idx[k]], acc);
+            acc1 = fma(e, (V)1, acc1);
+        }
+        acc = group_sum<L>(acc);
+        acc1 = group_sum<L>(acc1);
+        if (lane == 0) {
+            const double w = (double)acc, w1 = (double)acc1;
+            const double m = marg[r];
+            const bool ne = k1 > k0;
+            const V yw = (V)((ne && w > 0.0) ? m / w : 0.0);
+            const V yp = (V)((ne && w1 > 0.0) ? m / w1 : 0.0);
+            const double ur = (double)u0[r];
+            uw[r] = yw;
+            u0[r] = yp;
+            if (!isfinite((double)yw)) *badw = 1;
+            if (!isfinite((double)yp)) *badp = 1;
+            if (ne) {
+                sw += fabs(ur * w - m);
+                sp += fabs(w1 - m);
+            }
+        }
+    }
+    *rw = sw;
+    *rp = sp;
+}
+
 template <int PREC, int L>
 __global__ __launch_bounds__(1024) void k_b_iterate(BIterArgs A) {
     typedef typename BTypes<PREC>::V V;
@@ -78,7 +138,7 @@ __global__ __launch_bounds__(1024) void k_b_iterate(BIterArgs A) {
     V* ub = ua + A.nmax;
     V* vv = ub + A.nmax;
     __shared__ int s_q;
-    __shared__ double sh[16];
+    __shared__ double sh[32];
     // a sketch larger than its arrays was not stored: nothing to iterate
     if (A.row_ptr[A.rows] > A.cap || A.col_ptr[A.cols] > A.cap) return;
     const V* val = (const V*)A.val;
@@ -91,20 +151,52 @@ __global__ __launch_bounds__(1024) void k_b_iterate(BIterArgs A) {
         if (q >= A.count) break;
         const int k = A.order[q];
         const BProb P = A.prob[k];
-        for (int64_t i = threadIdx.x; i < P.n; i += blockDim.x)
-            ua[i] = A.init_log_u ? (V)exp(A.init_log_u[P.xo + i]) : (V)1;
-        for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x)
-            vv[j] = A.init_log_v ? (V)exp(A.init_log_v[P.yo + j]) : (V)1;
-        __syncthreads();
+        // a start with a NaN or +inf log-scaling (or one whose exponential
+        // overflows) is not used
+        int bad_init = 0;
+        for (int64_t i = threadIdx.x; i < P.n; i += blockDim.x) {
+            const double l = A.init_log_u ? A.init_log_u[P.xo + i] : 0.0;
+            const V e = (V)exp(l);
+            if (isnan(l) || !isfinite((double)e)) bad_init = 1;
+            ua[i] = e;
+        }
+        for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x) {
+            const double l = A.init_log_v ? A.init_log_v[P.yo + j] : 0.0;
+            const V e = (V)exp(l);
+            if (isnan(l) || !isfinite((double)e)) bad_init = 1;
+            vv[j] = e;
+        }
+        const bool warm = A.init_log_u || A.init_log_v;
+        bad_init = __syncthreads_or(bad_init);
         V* u = ua;
         V* un = ub;
         double res_col = 0.0, err = INFINITY;
-        int iters = 0, status = SS_NOT_CONVERGED;
+        int iters = 0, status = SS_NOT_CONVERGED, kept = warm ? 1 : -1;
         for (int t = 1;; ++t) {
             int bad = 0;
-            double r = b_half<0, PREC, L>(A.row_ptr + P.xo, A.col_idx, val, P.n, vv, u, un,
-                                          A.a_eff + P.xo, t, &bad);
-            r = block_sum(r, sh);
+            double r;
+            if (warm && t == 1) {
+                double rw, rp;
+                int badw = 0, badp = 0;
+                b_first_judged<PREC, L>(A.row_ptr + P.xo, A.col_idx, val, P.n, vv, ua, ub,
+                                        A.a_eff + P.xo, &rw, &rp, &badw, &badp);
+                block_sum2(rw, rp, sh);
+                badw = __syncthreads_or(badw);
+                badp = __syncthreads_or(badp);
+                // !(rw <= rp) also holds when rw is NaN
+                kept = (bad_init || badw || !(rw <= rp)) ? 0 : 1;
+                bad = kept ? badw : badp;
+                // the kept u^1 is the one the swap below makes current
+                if (!kept) {
+                    u = ub;
+                    un = ua;
+                }
+                r = 0.0;
+            } else {
+                r = b_half<0, PREC, L>(A.row_ptr + P.xo, A.col_idx, val, P.n, vv, u, un,
+                                       A.a_eff + P.xo, t, &bad);
+                r = block_sum(r, sh);
+            }
             if (__syncthreads_or(bad)) {
                 status = SS_E_NONFINITE;
                 iters = t - 1;
@@ -147,6 +239,7 @@ __global__ __launch_bounds__(1024) void k_b_iterate(BIterArgs A) {
             A.stat[k].iters = iters;
             A.stat[k].err = err;
             A.stat[k].status = status;
+            A.stat[k].warm = kept;
         }
         __syncthreads();
     }

@@ -396,6 +396,7 @@ struct BStat {
     double transport, negent, sparseobj, err;
     int64_t nnz;
     int32_t iters, status;
+    int32_t warm, pad;  // warm start: 1 kept, 0 replaced by the plain start, -1 none given
 };
 
 struct BatchArgs {

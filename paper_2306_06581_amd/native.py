@@ -54,7 +54,7 @@ class SsResult(ctypes.Structure):
                 ("nnz", c_int64), ("empty_rows", c_int64), ("empty_cols", c_int64),
                 ("iters", c_int32), ("status", c_int32),
                 ("t_prep_ms", c_float), ("t_sample_ms", c_float), ("t_iter_ms", c_float),
-                ("t_obj_ms", c_float)]
+                ("t_obj_ms", c_float), ("warm_start", c_int32), ("reserved", c_int32)]
 
 
 class SsSparse(ctypes.Structure):

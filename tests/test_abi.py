@@ -52,7 +52,8 @@ int main(void) {
   printf("ss_batch %zu\nss_schedule %zu\n", sizeof(ss_batch), sizeof(ss_schedule));
   P(ss_batch, s) P(ss_batch, x) P(ss_batch, b) P(ss_schedule, block_threads)
   P(ss_problem, x) P(ss_options, seed) P(ss_options, init_log_u) P(ss_options, err_hist) P(ss_options, shrink) P(ss_options, eta)
-  P(ss_result, nnz) P(ss_result, iters) P(ss_result, t_obj_ms) P(ss_sparse, capacity)
+  P(ss_result, nnz) P(ss_result, iters) P(ss_result, t_obj_ms) P(ss_result, warm_start)
+  P(ss_sparse, capacity)
   P(ss_sparse, z_norm) P(ss_ibp_problem, x) P(ss_ibp_problem, w) P(ss_ibp_result, nnz)
   P(ss_ibp_result, t_iter_ms) P(ss_divergence, nnz) P(ss_divergence, status)
   printf("ss_divergence %zu\n", sizeof(ss_divergence));
@@ -85,6 +86,7 @@ def test_struct_layout_matches_header():
     assert N.SsResult.nnz.offset == lay["ss_result.nnz"]
     assert N.SsResult.iters.offset == lay["ss_result.iters"]
     assert N.SsResult.t_obj_ms.offset == lay["ss_result.t_obj_ms"]
+    assert N.SsResult.warm_start.offset == lay["ss_result.warm_start"]
     assert N.SsSparse.capacity.offset == lay["ss_sparse.capacity"]
     assert N.SsSparse.z_norm.offset == lay["ss_sparse.z_norm"]
     assert ctypes.sizeof(N.SsBatch) == lay["ss_batch"]

@@ -153,12 +153,66 @@ def test_trained_network_saves_iterations(api):
     lu, lv = net.predict(Bf, eps=0.05)
     cold = _solve(api, Bf, tol=1e-6, max_iter=1000, precision="f32")
     warm = _solve(api, Bf, tol=1e-6, max_iter=1000, precision="f32", init_log_u=lu, init_log_v=lv)
-    ok = [i for i in range(len(fresh)) if cold[i].status == 0 and warm[i].status == 0]
+    ok = [i for i in range(len(fresh)) if cold[i].status == 0]
     assert len(ok) >= 60
+    # every problem the plain start solves is solved from the learned start
+    assert all(warm[i].status == 0 for i in ok), [warm[i].status for i in ok]
+    kept = sum(warm[i].warm_start == 1 for i in ok)
     it_cold = np.mean([cold[i].iters for i in ok])
     it_warm = np.mean([warm[i].iters for i in ok])
-    print(f"mean iterations to 1e-6: plain start {it_cold:.2f}, learned start {it_warm:.2f}")
+    print(f"mean iterations to 1e-6: plain start {it_cold:.2f}, learned start {it_warm:.2f} "
+          f"(prediction kept for {kept} of {len(ok)})")
     assert it_warm < 0.9 * it_cold
     # the warm start changes where the loop starts, not what it converges to
     for i in ok:
         assert abs(warm[i].estimate - cold[i].estimate) <= 1e-4 * abs(cold[i].estimate)
+
+
+def _same_as_plain(cold, warm):
+    """A start replaced by the plain one gives the plain solve bit for bit."""
+    for k, (c, w) in enumerate(zip(cold, warm)):
+        assert c.warm_start == -1 and w.warm_start == 0, k
+        assert (w.status, w.iters, w.nnz) == (c.status, c.iters, c.nnz), k
+        assert w.estimate == c.estimate and w.marginal_err == c.marginal_err, k
+        assert w.sparse_objective == c.sparse_objective, k
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_corrupted_network_falls_back_to_plain_start(api, precision):
+    # zero-init Sinkhorn is the warm start's fallback: a network whose weights
+    # are corrupted (a NaN output bias makes every prediction NaN) must leave
+    # every problem exactly where the plain start takes it
+    probs = W.batch_ot(12, seed=2100, n_lo=200, n_hi=900)
+    B = api.Batch.from_problems(probs)
+    flat = api.WarmStartNet(seed=7).weights().copy()
+    flat[-1] = np.nan
+    lu, lv = api.WarmStartNet(flat).predict(B, eps=0.05)
+    assert torch.isnan(lu).all() and torch.isnan(lv).all()
+    kw = dict(tol=1e-6, max_iter=1000, precision=precision)
+    cold = _solve(api, B, **kw)
+    warm = _solve(api, B, **kw, init_log_u=lu, init_log_v=lv)
+    _same_as_plain(cold, warm)
+    # overflowing starts (exp(+800) is +inf in FP64 and FP32) likewise
+    big = torch.full_like(lu, 800.0)
+    _same_as_plain(cold, _solve(api, B, **kw, init_log_u=big, init_log_v=lv.nan_to_num(0.0)))
+
+
+def test_poor_finite_start_is_judged_worse_than_plain(api):
+    # a finite start far from the solution (log-scalings with unit-scale noise
+    # times 30) has a larger first row marginal error than u = v = 1 and is
+    # replaced; a start at the solution is kept and stops at once
+    probs = W.batch_ot(8, seed=2200, n_lo=200, n_hi=900)
+    B = api.Batch.from_problems(probs)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    rows, cols = int(B.row_off[-1]), int(B.col_off[-1])
+    lu = (30.0 * torch.randn(rows, generator=g, dtype=torch.float64)).cuda()
+    lv = (30.0 * torch.randn(cols, generator=g, dtype=torch.float64)).cuda()
+    kw = dict(tol=1e-8, max_iter=2000, precision="f64")
+    cold = _solve(api, B, **kw, return_scalings=True)
+    _same_as_plain(cold, _solve(api, B, **kw, init_log_u=lu, init_log_v=lv))
+    su = torch.cat([torch.log(r.u) for r in cold])
+    sv = torch.cat([torch.log(r.v) for r in cold])
+    warm = _solve(api, B, **kw, init_log_u=su, init_log_v=sv)
+    for c, w in zip(cold, warm):
+        assert w.warm_start == 1 and w.status == 0 and w.iters <= 1
+        assert abs(w.estimate - c.estimate) <= 1e-9 * abs(c.estimate)
