@@ -191,6 +191,26 @@ int spar_sink_ot(const ss_problem *problem, const ss_options *opts, void *ws,
 int spar_sink_uot(const ss_problem *problem, const ss_options *opts, void *ws,
                   size_t ws_bytes, void *stream, ss_result *result);
 
+/* Bytes of the static scratch array behind spar_sink_ot_noalloc (per GPU). */
+#define SS_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* spar_sink_ot without allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as spar_sink_ot,
+ * minus the workspace: scratch is a static device array of
+ * SS_NOALLOC_SCRATCH_BYTES that each GPU holds from the first call there
+ * until the process ends.  The call allocates no device or pinned host
+ * memory and creates no stream, event or graph: the loop runs as plain
+ * launches on `stream` (which must belong to the current device) and the
+ * t_*_ms fields read 0.  A problem whose ss_workspace_size exceeds
+ * SS_NOALLOC_SCRATCH_BYTES is rejected with SS_E_WORKSPACE (n = m = 4096 at
+ * s = 8 n ln n in FP64 fits).  Every call on one GPU shares that GPU's
+ * array and leaves its contents behind; calls that overlap on one GPU
+ * (other threads, other streams) race and must be serialised by the
+ * caller. */
+int spar_sink_ot_noalloc(const ss_problem *problem, const ss_options *opts, void *stream,
+                         ss_result *result);
+
 /* Alg. 1 (lambda = +INFINITY) or Alg. 2 on the full kernel K = exp(-C/eps),
  * recomputed from the coordinates in every half-step (never stored).  Same
  * options, stop rules and estimate as the sparse solvers (nnz = n*m). */

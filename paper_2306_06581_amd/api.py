@@ -162,6 +162,29 @@ def spar_sink_uot(prob: Problem, **kw) -> Result:
     return _solve("spar_sink_uot", prob, **kw)
 
 
+def spar_sink_ot_noalloc(prob: Problem, *, eps, s=1.0, tol=1e-6, max_iter=1000, seed=0,
+                         precision="f64", cost="maxnorm", stop_rule="marginal",
+                         empty_policy="auto", block_threads=0, shrink=0.0,
+                         return_scalings=False, raise_on_error=True, stream=None) -> Result:
+    """Alg. 3 through the allocation-free entry point: the library's static
+    per-GPU scratch replaces the workspace."""
+    u_out = v_out = None
+    if return_scalings:
+        u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+        v_out = torch.empty(prob.m, dtype=torch.float64, device="cuda")
+    opts = make_options(eps, s, math.inf, tol, max_iter, seed, precision, cost, stop_rule,
+                        empty_policy, block_threads, 0, None, None, u_out, v_out, None, shrink)
+    res = N.SsResult()
+    rc = N.lib.spar_sink_ot_noalloc(ctypes.byref(prob.c), ctypes.byref(opts), _stream(stream),
+                                    ctypes.byref(res))
+    if rc < 0 and raise_on_error:
+        raise N.SparSinkError(rc, "spar_sink_ot_noalloc")
+    out = Result(status=rc, **{k: getattr(res, k) for k, _ in N.SsResult._fields_
+                               if k != "status"})
+    out.u, out.v = u_out, v_out
+    return out
+
+
 def dense_sinkhorn(prob: Problem, **kw) -> Result:
     """Alg. 1 / Alg. 2 with the full kernel recomputed on the fly."""
     return _solve("dense_sinkhorn", prob, **kw)

@@ -255,15 +255,18 @@ int check_ws(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes
 }
 
 struct Timer {
-    hipEvent_t ev[5];
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     bool ok = false;
-    Timer() {
+    // enabled = false: no events are created and every time reads 0
+    explicit Timer(bool enabled = true) {
+        if (!enabled) return;
         ok = true;
         for (auto& e : ev)
             if (hipEventCreate(&e) != hipSuccess) ok = false;
     }
     ~Timer() {
-        for (auto& e : ev) (void)hipEventDestroy(e);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
     void mark(int k, hipStream_t st) {
         if (ok) (void)hipEventRecord(ev[k], st);
@@ -672,9 +675,11 @@ struct GradSink {
     double cx, cy;
 };
 
+// noalloc: no HIP object is created (no events, graphs or streams) and the
+// loop runs as plain launches; the workspace is whatever the caller passed.
 int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes,
                    void* stream, ss_result* R, bool uot, int time_iters = 0,
-                   double* ms_out = nullptr, const GradSink* gs = nullptr) {
+                   double* ms_out = nullptr, const GradSink* gs = nullptr, bool noalloc = false) {
     int rc = check_args(P, O, false);
     if (rc != SS_OK) return rc;
     if (!R) return fail(SS_E_INVALID_ARG, "result must not be NULL");
@@ -689,7 +694,7 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     rc = check_ws(P, O, ws, ws_bytes, &c.L);
     if (rc != SS_OK) return rc;
     memset(R, 0, sizeof *R);
-    Timer tm;
+    Timer tm(!noalloc);
     tm.mark(0, c.st);
     rc = stage_start(c);
     if (rc != SS_OK) return rc;
@@ -795,9 +800,16 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         a.role = 1;
         va[k] = a;
     }
-    auto iter = [&](int k, hipStream_t s) -> hipError_t {
-        hipError_t e = launch_iterate(prec, pl[0].block, pl[0].grid, ua[k & 1], s);
-        if (e == hipSuccess) e = launch_iterate(prec, pl[1].block, pl[1].grid, va[k & 1], s);
+    // one pointer captured: the std::function below stores it in place
+    struct LoopLaunch {
+        int prec;
+        const IterPlan* pl;
+        const IterArgs* ua;
+        const IterArgs* va;
+    } const ll = {prec, pl, ua, va};
+    auto iter = [q = &ll](int k, hipStream_t s) -> hipError_t {
+        hipError_t e = launch_iterate(q->prec, q->pl[0].block, q->pl[0].grid, q->ua[k & 1], s);
+        if (e == hipSuccess) e = launch_iterate(q->prec, q->pl[1].block, q->pl[1].grid, q->va[k & 1], s);
         return e;
     };
     if (time_iters > 0) {
@@ -809,7 +821,7 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         return time_graph(iter, time_iters, u[0], v[0], ug[0], vg[0], prec, n, m, O, d_state, c.st,
                           ms_out);
     }
-    const int G = O->graph_iters == 0 ? 16 : O->graph_iters;
+    const int G = noalloc ? -1 : O->graph_iters == 0 ? 16 : O->graph_iters;
     IterState hs;
     memset(&hs, 0, sizeof hs);
     rc = run_loop(iter, G, O->max_iter, O->tol, d_state, &hs, c.st);
@@ -1500,6 +1512,37 @@ int ss_autotune_batched(const ss_batch* B, const ss_options* O, void* ws, size_t
 
 }  // extern "C"
 
+// Scratch of spar_sink_ot_noalloc: a static device array, one copy per GPU
+// the library runs on, held until the process ends.  In host code its name is
+// only a host-side stand-in; the array's device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device (with that device current, on the
+// entry point's first call there) and used for every kernel argument.
+static __device__ __align__(256) unsigned char scratch[SS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// *ws = the current device's copy of `scratch`.
+static int noalloc_scratch(void** ws) {
+    int dev = -1;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(SS_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SS_E_HIP, "device %d is beyond the %d the scratch table holds", dev, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (r != hipSuccess || !p)
+            return fail(SS_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(r));
+        if ((uintptr_t)p % 256 != 0) return fail(SS_E_HIP, "scratch is not 256-byte aligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *ws = g_scratch_ptr[dev];
+    return SS_OK;
+}
+
 // Straggler hand-off: iterations of the batch loop before stragglers are
 // counted, and the most stragglers handed to the single-problem solver (one
 // problem there takes every compute unit for (iters - kHandoffIters) x ~10
@@ -1774,6 +1817,22 @@ int spar_sink_ot(const ss_problem* P, const ss_options* O, void* ws, size_t ws_b
 int spar_sink_uot(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes,
                   void* stream, ss_result* R) {
     return spar_sink_impl(P, O, ws, ws_bytes, stream, R, true);
+}
+
+int spar_sink_ot_noalloc(const ss_problem* P, const ss_options* O, void* stream, ss_result* R) {
+    void* ws = nullptr;
+    int rc = noalloc_scratch(&ws);
+    if (rc != SS_OK) return rc;
+    size_t need = 0;
+    rc = ss_workspace_size(P, O, &need);
+    if (rc != SS_OK) return rc;
+    if (need > (size_t)SS_NOALLOC_SCRATCH_BYTES)
+        return fail(SS_E_WORKSPACE,
+                    "the problem needs %zu bytes of scratch; spar_sink_ot_noalloc has %zu "
+                    "(use spar_sink_ot with a workspace)",
+                    need, (size_t)SS_NOALLOC_SCRATCH_BYTES);
+    return spar_sink_impl(P, O, ws, (size_t)SS_NOALLOC_SCRATCH_BYTES, stream, R, false, 0,
+                          nullptr, nullptr, true);
 }
 
 int ss_time_iterations(const ss_problem* P, const ss_options* O, void* ws, size_t ws_bytes,

@@ -76,6 +76,7 @@ class SsSchedule(ctypes.Structure):
 
 
 BATCH_MAX_SIDE = 4096
+NOALLOC_SCRATCH_BYTES = 32 << 20
 MLP_PARAMS = 133889
 
 
@@ -115,6 +116,8 @@ SIGNATURES = {
                              c_void_p, POINTER(SsResult)]),
     "spar_sink_uot": (c_int, [POINTER(SsProblem), POINTER(SsOptions), c_void_p, c_size_t,
                               c_void_p, POINTER(SsResult)]),
+    "spar_sink_ot_noalloc": (c_int, [POINTER(SsProblem), POINTER(SsOptions), c_void_p,
+                                     POINTER(SsResult)]),
     "dense_sinkhorn": (c_int, [POINTER(SsProblem), POINTER(SsOptions), c_void_p, c_size_t,
                                c_void_p, POINTER(SsResult)]),
     "ss_time_iterations": (c_int, [POINTER(SsProblem), POINTER(SsOptions), c_void_p, c_size_t,
