@@ -156,6 +156,12 @@ typedef struct ss_result {
  * col_ptr (m+1), row_idx (ascending within a column), val_t   -- CSC of K~.
  * row_fac (n), col_fac (m): OT: alpha_i = s sqrt(a_i) / (S_a S_b) and sqrt(b_j),
  *         so p*_ij = min(1, alpha_i * col_fac_j); UOT: th_u log a_i, th_u log b_j.
+ * z_in (host, input): UOT only; 0 = the library computes the normaliser
+ *         Z = sum_ij q_ij of eq. (pij-uot) itself; > 0 = this value is used as Z
+ *         (the parity surface: given the same Z, every keep decision and
+ *         stored value is a fixed sequence of IEEE operations, so an
+ *         independent implementation of the same definitions reproduces the
+ *         mask, CSR and CSC bit for bit).  Ignored for OT.
  * On return nnz, cmax and z_norm are filled (host fields). */
 typedef struct ss_sparse {
     uint64_t *mask;
@@ -169,6 +175,7 @@ typedef struct ss_sparse {
     int64_t capacity;
     int64_t nnz;
     double cmax, z_norm;
+    double z_in;
 } ss_sparse;
 
 /* ---------------------------------------------------------------- calls */

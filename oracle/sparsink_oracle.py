@@ -38,6 +38,13 @@ Choices where the paper is silent (all restated in the design notes):
 * UOT sampling weight: q_ij = exp(th*(log a_i + log b_j) - C_ij/(2lam+eps)),
   th = lam/(2lam+eps) (the identity K^(eps/(2lam+eps)) = exp(-C/(2lam+eps)));
   Z = sum q; p* = min(1, (s/Z) q).
+* Every exponential, logarithm and cosine that decides a sampled entry or
+  forms a stored value (q, log a, log b, the WFR cost, K = exp(-C/eps),
+  log p*) is the fixed operation sequence of ``elementary.py`` (Cody-Waite
+  reduction and Taylor polynomials), so that an independent implementation
+  of the same sequence reproduces the mask and the values bit for bit; given
+  the same Z this holds for UOT as well.  The iterations and the estimate
+  use the platform's exp and log.
 * Empty rows/columns (no sampled entry): OT renormalises a and b over the
   non-empty support ("renormalize"); UOT sets u_i = 0 there ("zero"), the
   exact optimum of the sparse UOT problem for that row.
@@ -54,6 +61,8 @@ from dataclasses import dataclass
 
 import numpy as np
 import scipy.sparse as sp
+
+from .elementary import cos_spec, exp_spec, log_spec
 
 # --------------------------------------------------------------------------
 # Philox4x32-10 (Salmon et al., SC 2011), vectorised over counters.
@@ -224,7 +233,7 @@ def cost_from_sq(c, kind: str, inv_cmax: float, eta: float):
     z = np.sqrt(c) * (0.5 / eta)
     inside = z < HALF_PI
     out = np.full(np.shape(z), np.inf)
-    out[inside] = -2.0 * np.log(np.cos(z[inside]))
+    out[inside] = -2.0 * log_spec(cos_spec(z[inside]))
     return out
 
 
@@ -273,12 +282,15 @@ class ProbUOT:
     cost: str = "maxnorm"
     eta: float = 1.0
 
-    def q(self, rows, cols):
+    def exponent(self, rows, cols):
+        """(la_i + lb_j) - C_ij / (2 lam + eps), the log of q_ij."""
         cij = cost_from_sq(sq_dist(self.x[rows], self.y[cols]), self.cost, self.inv_cmax,
                            self.eta)
         with np.errstate(invalid="ignore"):
-            e = (self.la[rows][:, None] + self.lb[cols][None, :]) - cij * self.inv_tau
-        return np.exp(e)
+            return (self.la[rows][:, None] + self.lb[cols][None, :]) - cij * self.inv_tau
+
+    def q(self, rows, cols):
+        return exp_spec(self.exponent(rows, cols))
 
     def pstar(self, rows, cols):
         return np.minimum(1.0, self.kappa * self.q(rows, cols) + self.c0)
@@ -288,17 +300,24 @@ def uot_probabilities(a, b, x, y, s, lam, eps, inv_cmax, chunk: int = 256,
                       shrink: float = 0.0, workers: int = 1, cost: str = "maxnorm",
                       eta: float = 1.0) -> ProbUOT:
     """eq. (pij-uot) with K^(eps/(2lam+eps)) written as exp(-C/(2lam+eps)),
-    mixed with the uniform probability with weight `shrink`."""
+    mixed with the uniform probability with weight `shrink`.
+
+    Z = sum_ij q_ij is a sum of nm terms whose rounding order neither side
+    fixes, so its last bits are not part of the specification; it is formed
+    here with the platform exponential of the same exponents (each term
+    within an ulp or two of exp_spec's, Z within ~1e-15 relative) because the
+    nm specified exponentials cost too much at n = 65536.  Every keep
+    decision and stored value takes Z as given: the library's ss_sample
+    accepts the oracle's Z (z_in) and then matches bit for bit."""
     tau = 2.0 * lam + eps
     th = lam / tau
-    with np.errstate(divide="ignore"):
-        la = th * np.log(np.asarray(a, dtype=np.float64))
-        lb = th * np.log(np.asarray(b, dtype=np.float64))
+    la = th * log_spec(np.asarray(a, dtype=np.float64))
+    lb = th * log_spec(np.asarray(b, dtype=np.float64))
     pr = ProbUOT(la=la, lb=lb, inv_tau=1.0 / tau, inv_cmax=inv_cmax, z=0.0, kappa=0.0,
                  x=np.asarray(x, np.float64), y=np.asarray(y, np.float64), cost=cost, eta=eta)
     cols = np.arange(len(b))
     rowsums = _map_chunks(
-        lambda r0: pr.q(np.arange(r0, min(len(a), r0 + chunk)), cols).sum(axis=1),
+        lambda r0: np.exp(pr.exponent(np.arange(r0, min(len(a), r0 + chunk)), cols)).sum(axis=1),
         range(0, len(a), chunk), workers)
     pr.z = float(np.sum(np.concatenate(rowsums)))
     w, pr.c0 = shrink_terms(s, shrink, len(a), len(b))
@@ -393,9 +412,9 @@ def build_sketch(x, y, a, b, opt: Options, chunk: int = 256, prob=None,
     cvals = np.array([sq_dist(x[i:i + 1], y[j:j + 1])[0, 0] for i, j in zip(ri, ci)]) \
         if ri.size < 4096 else _pair_sq_dist(x, y, ri, ci)
     cost = cost_from_sq(cvals, opt.cost, inv_cmax, opt.eta)
-    kval = np.exp(-(cost / opt.eps))
+    kval = exp_spec(-(cost / opt.eps))
     val = kval / ps
-    logval = -(cost / opt.eps) - np.log(ps)
+    logval = -(cost / opt.eps) - log_spec(ps)
     row_ptr = np.zeros(n + 1, np.int64)
     np.cumsum(np.bincount(ri, minlength=n), out=row_ptr[1:])
     # CSC: stable order by (column, row).
@@ -682,7 +701,7 @@ def dense_sinkhorn(x, y, a, b, opt: Options) -> SolveResult:
     b = np.asarray(b, np.float64)
     cmax, inv_cmax = cost_scale(x, y, opt)
     cost = cost_from_sq(sq_dist(x, y), opt.cost, inv_cmax, opt.eta)
-    K = np.exp(-(cost / opt.eps))
+    K = exp_spec(-(cost / opt.eps))
     n, m = K.shape
     if opt.log_domain:
         sk = _dense_as_sketch(cost, opt, cmax, inv_cmax)
@@ -705,8 +724,8 @@ def _dense_as_sketch(cost, opt, cmax, inv_cmax) -> Sketch:
     row_ptr = np.arange(0, n * m + 1, m, dtype=np.int64)
     col_ptr = np.arange(0, n * m + 1, n, dtype=np.int64)
     return Sketch(n=n, m=m, mask=np.zeros((n, 0), np.uint64), row_ptr=row_ptr,
-                  col_idx=np.tile(np.arange(m), n).astype(np.int32), val=np.exp(logval).ravel(),
+                  col_idx=np.tile(np.arange(m), n).astype(np.int32), val=exp_spec(logval).ravel(),
                   logval=logval.ravel(), cost=cost.ravel(), pstar=np.ones(n * m),
                   col_ptr=col_ptr, row_idx=np.tile(np.arange(n), m).astype(np.int32),
-                  val_t=np.exp(logval.T).ravel(), logval_t=logval.T.ravel(), cmax=cmax,
+                  val_t=exp_spec(logval.T).ravel(), logval_t=logval.T.ravel(), cmax=cmax,
                   inv_cmax=inv_cmax, prob=None)

@@ -208,8 +208,9 @@ def ss_time_iterations(prob: Problem, iters: int = 64, *, eps, s=1.0, lam=math.i
 
 def ss_sample(prob: Problem, *, eps, s, lam=math.inf, seed=0, precision="f64", cost="maxnorm",
               shrink=0.0, eta=1.0, capacity: Optional[int] = None, want_mask=True,
-              stream=None) -> dict:
-    """Step 1 of Alg. 3/4: returns the mask words, CSR, CSC and p* factors."""
+              z_in: float = 0.0, stream=None) -> dict:
+    """Step 1 of Alg. 3/4: returns the mask words, CSR, CSC and p* factors.
+    z_in > 0 (UOT): use it as the normaliser Z of eq. (pij-uot)."""
     opts = make_options(eps, s, lam, seed=seed, precision=precision, cost=cost, shrink=shrink,
                         eta=eta)
     nbytes = workspace_size(prob, opts)
@@ -230,7 +231,7 @@ def ss_sample(prob: Problem, *, eps, s, lam=math.inf, seed=0, precision="f64", c
     }
     sp = N.SsSparse(*[_ptr(out[k]) for k in ("mask", "row_ptr", "col_idx", "val", "col_ptr",
                                              "row_idx", "val_t", "row_fac", "col_fac")],
-                    cap, 0, 0.0, 0.0)
+                    cap, 0, 0.0, 0.0, float(z_in))
     rc = N.lib.ss_sample(ctypes.byref(prob.c), ctypes.byref(opts), ctypes.byref(sp),
                          ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
                          _stream(stream))

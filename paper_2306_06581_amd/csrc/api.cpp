@@ -405,6 +405,8 @@ struct Ctx {
     // until the sampling stage synchronises)
     std::vector<uint8_t> zexps;
     std::vector<double> zcoef;
+    // UOT: a normaliser given by the caller of ss_sample (0: the library's own)
+    double z_in = 0.0;
 };
 
 // Degree K of the normaliser's expansion: the remainder of the exponential
@@ -553,6 +555,7 @@ int stage_sample(Ctx& c) {
             HIP_TRY(launch_uot_z(pp, n, m, pp.col_bnd, c.stats[ST_CMAX],
                                  at<double>(ws, c.L.partials), tree, stats, st));
         }
+        if (c.z_in > 0.0) HIP_TRY(launch_fill_f64(stats + ST_Z, 1, c.z_in, st));
         HIP_TRY(launch_uot_bounds(pp.col_fac, m, O->s, pp.shrink_w, stats, (double*)pp.col_bnd,
                                   st));
     }
@@ -1768,12 +1771,15 @@ int ss_sample(const ss_problem* P, const ss_options* O, ss_sparse* out, void* ws
     int rc = check_args(P, O, false);
     if (rc != SS_OK) return rc;
     if (!out) return fail(SS_E_INVALID_ARG, "out must not be NULL");
+    if (!(out->z_in >= 0.0) || !isfinite(out->z_in))
+        return fail(SS_E_INVALID_ARG, "out->z_in must be 0 or a positive finite normaliser");
     Ctx c;
     c.P = P;
     c.O = O;
     c.ws = ws;
     c.st = (hipStream_t)stream;
     c.uot = isfinite(O->lambda);
+    c.z_in = c.uot ? out->z_in : 0.0;
     rc = check_ws(P, O, ws, ws_bytes, &c.L);
     if (rc != SS_OK) return rc;
     rc = stage_start(c);

@@ -1,6 +1,7 @@
 // Device-side helpers shared by the Spar-Sink kernels (gfx950, wave64).
 #pragma once
 
+#include "elemfn.hpp"
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -110,6 +111,14 @@ __device__ __forceinline__ double cost_value(double c, int kind, double scale, d
     if (kind != kCostWfr) return c * scale;
     const double z = sqrt(c) * w;
     return z >= kHalfPi ? INFINITY : -2.0 * log(cos(z));
+}
+
+// cost_value with the specified logarithm and cosine (elemfn.hpp): the form
+// used where the cost decides a sampled entry or its stored value.
+__device__ __forceinline__ double cost_spec(double c, int kind, double scale, double w) {
+    if (kind != kCostWfr) return c * scale;
+    const double z = sqrt(c) * w;
+    return z >= kHalfPi ? INFINITY : -2.0 * log_spec(cos_spec(z));
 }
 
 // ---------------------------------------------------------------------------

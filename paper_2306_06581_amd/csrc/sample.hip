@@ -302,19 +302,20 @@ hipError_t launch_ot_prep(const double* a, const double* b, int64_t n, int64_t m
 
 // ------------------------------------------------------------------ UOT prep
 // la_i = th_u log a_i, lb_j = th_u log b_j (th_u = lam/(2lam+eps)); ea_i = exp(la_i),
-// eb_j = exp(lb_j).
+// eb_j = exp(lb_j); with the specified logarithm and exponential (elemfn.hpp),
+// since la and lb enter the keep decisions.
 __global__ void k_uot_logs(const double* a, const double* b, int64_t n, int64_t m, double thu,
                            double* la, double* lb, double* ea, double* eb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        const double l = thu * log(a[i]);
+        const double l = thu * log_spec(a[i]);
         la[i] = l;
-        ea[i] = exp(l);
+        ea[i] = exp_spec(l);
     }
     if (i < m) {
-        const double l = thu * log(b[i]);
+        const double l = thu * log_spec(b[i]);
         lb[i] = l;
-        eb[i] = exp(l);
+        eb[i] = exp_spec(l);
     }
 }
 
@@ -329,10 +330,11 @@ hipError_t launch_uot_prep(const double* a, const double* b, int64_t n, int64_t 
 }
 
 // q_ij = exp((la_i + lb_j) - C_ij inv_tau): eq. (pij-uot) numerator, from the
-// squared distance c_ij.
+// squared distance c_ij, with the specified exponential and cost (it decides
+// the entry).
 __device__ __forceinline__ double uot_q_of(const ProbParams& pp, double c, int64_t i, int64_t j) {
-    const double C = cost_value(c, pp.cost, pp.inv_cmax, pp.wfr_w);
-    return exp((pp.row_fac[i] + pp.col_fac[j]) - C * pp.inv_tau);
+    const double C = cost_spec(c, pp.cost, pp.inv_cmax, pp.wfr_w);
+    return exp_spec((pp.row_fac[i] + pp.col_fac[j]) - C * pp.inv_tau);
 }
 
 // The cost factor exp(-C_ij inv_tau) of q_ij bounded from above by 2^(-t) with
@@ -619,7 +621,7 @@ __global__ void k_uot_bounds(const double* lb, int64_t m, double s, double w,
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const double kappa = w * (s / stats[ST_Z]);
-    fb[j] = kappa * exp(lb[j]) * (1.0 + 0x1p-30);
+    fb[j] = kappa * exp_spec(lb[j]) * (1.0 + 0x1p-30);
 }
 
 hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrink_w,
@@ -1068,19 +1070,21 @@ hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* ptr, int64_t* scr
 // ------------------------------------------------------------------ fill
 // Value of K~_ij = K_ij / p*_ij in FP64 (eq. (pois)), K_ij = exp(-C_ij/eps)
 // with C recomputed from the coordinates; also its log, -C/eps - log p*.
+// The specified exponential, logarithm and cost (elemfn.hpp) make every
+// stored value a fixed sequence of IEEE operations.
 template <bool UOT, int D>
 __device__ __forceinline__ double entry_value(const ProbParams& pp, double kappa, int64_t i,
                                               int64_t j, double* logv) {
     const double c = sqdist<D>(pp.x + i * pp.d, pp.y + j * pp.d, pp.d);
-    const double C = cost_value(c, pp.cost, pp.inv_cmax, pp.wfr_w);
+    const double C = cost_spec(c, pp.cost, pp.inv_cmax, pp.wfr_w);
     const double Ce = C / pp.eps;
-    const double K = exp(-Ce);
+    const double K = exp_spec(-Ce);
     double P;
     if (UOT)
-        P = fmin(1.0, kappa * exp((pp.row_fac[i] + pp.col_fac[j]) - C * pp.inv_tau) + pp.shrink_c);
+        P = fmin(1.0, kappa * exp_spec((pp.row_fac[i] + pp.col_fac[j]) - C * pp.inv_tau) + pp.shrink_c);
     else
         P = fmin(1.0, pp.row_fac[i] * pp.col_fac[j] + pp.shrink_c);
-    *logv = -Ce - log(P);
+    *logv = -Ce - log_spec(P);
     return K / P;
 }
 

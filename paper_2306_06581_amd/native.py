@@ -62,7 +62,7 @@ class SsSparse(ctypes.Structure):
                 ("val", c_void_p), ("col_ptr", c_void_p), ("row_idx", c_void_p),
                 ("val_t", c_void_p), ("row_fac", c_void_p), ("col_fac", c_void_p),
                 ("capacity", c_int64), ("nnz", c_int64), ("cmax", c_double),
-                ("z_norm", c_double)]
+                ("z_norm", c_double), ("z_in", c_double)]
 
 
 class SsBatch(ctypes.Structure):

@@ -6,16 +6,18 @@ The oracle cannot build a whole sketch at these sizes, so it computes the
 global scalars exactly (cmax; for UOT the normaliser Z, eq. (pij-uot)) and
 then, for a sample of rows and of columns, every keep decision, every stored
 value and the fixed-point residual of the returned scalings on its own K~.
-Bars as elsewhere: mask bits, offsets and indices bit-exact (OT and UOT; a
-failure names each differing position and its distance |U - p*| / p* to the
-keep boundary); FP32 values within the rounding of FP32 storage; the sampled
-residual terms within the solver's reported error."""
+Bars as elsewhere: mask bits, offsets, indices and stored values bit-exact
+(for UOT given the oracle's normaliser through ss_sample's z_in; the
+library's own Z within 1e-12 of the oracle's; a differing bit is reported
+with its distance |U - p*| / p* to the keep boundary); the sampled residual
+terms within the solver's reported error."""
 import os
 
 import numpy as np
 import pytest
 import torch
 
+from oracle import elementary as EL
 from oracle import sparsink_oracle as O
 from paper_2306_06581_amd import workloads as W
 
@@ -60,8 +62,8 @@ class Lines:
         self.cost_r = O.sq_dist(p.x[rows], p.y) * inv_cmax
         self.cost_c = O.sq_dist(p.x, p.y[cols]).T * inv_cmax
         with np.errstate(divide="ignore"):
-            self.kt_r = np.where(self.keep_r, np.exp(-(self.cost_r / p.eps)) / self.pst_r, 0.0)
-            self.kt_c = np.where(self.keep_c, np.exp(-(self.cost_c / p.eps)) / self.pst_c, 0.0)
+            self.kt_r = np.where(self.keep_r, EL.exp_spec(-(self.cost_r / p.eps)) / self.pst_r, 0.0)
+            self.kt_c = np.where(self.keep_c, EL.exp_spec(-(self.cost_c / p.eps)) / self.pst_c, 0.0)
         self.eps = p.eps
 
 
@@ -76,19 +78,18 @@ def _check_lines(side, lines, keep, pst, u01, cost, eps, gbits, ptr, idx, val, p
         pos = np.nonzero(keep[k])[0]
         assert np.array_equal(idx[lo:hi], pos), (side, r)
         c, ps = cost[k, pos], pst[k, pos]
+        # the stored FP32 value is the rounding of the same FP64 operation
+        # sequence (specified exponential and logarithm) on both sides
         if precision == "f32_log":
-            ref = -(c / eps) - np.log(ps)
-            np.testing.assert_allclose(val[lo:hi], ref.astype(np.float32), rtol=1.2e-7,
-                                       atol=1e-6, err_msg=f"{side} {r}")
+            ref = -(c / eps) - EL.log_spec(ps)
         else:
-            ref = np.exp(-(c / eps)) / ps
-            np.testing.assert_allclose(val[lo:hi], ref.astype(np.float32), rtol=1.2e-7, atol=0,
-                                       err_msg=f"{side} {r}")
+            ref = EL.exp_spec(-(c / eps)) / ps
+        assert np.array_equal(val[lo:hi], ref.astype(np.float32)), (side, int(r))
 
 
-def _check_sample(api, p, L, precision, uot):
+def _check_sample(api, p, L, precision, uot, z_in=0.0):
     g = api.ss_sample(api.Problem(p.x, p.y, p.a, p.b, problem_index=p.problem_index),
-                      eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, precision=precision)
+                      eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, precision=precision, z_in=z_in)
     gbits_r = _gpu_bits(g["mask"], L.rows, p.m)
     _check_lines("row", L.rows, L.keep_r, L.pst_r, L.u_r, L.cost_r, p.eps, gbits_r,
                  g["row_ptr"].cpu().numpy(), g["col_idx"].cpu().numpy(), g["val"].cpu().numpy(),
@@ -132,9 +133,16 @@ def test_uot_headline_full_size(api):
     prob = O.uot_probabilities(p.a, p.b, p.x, p.y, p.s, p.lam, p.eps, inv_cmax, chunk=64,
                                workers=WORKERS)
     L = Lines(p, prob, inv_cmax, rows, cols)
-    g = _check_sample(api, p, L, "f32_log", True)
+    # the library's own normaliser against the oracle's exact sum
+    g = api.ss_sample(api.Problem(p.x, p.y, p.a, p.b, problem_index=p.problem_index),
+                      eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, precision="f32_log")
     assert g["cmax"] == cmax
     assert g["z_norm"] == pytest.approx(prob.z, rel=1e-12)
+    nnz_own = g["nnz"]
+    del g
+    # given the oracle's Z, the sampled lines match bit for bit
+    g = _check_sample(api, p, L, "f32_log", True, z_in=prob.z)
+    print(f"n=65536 UOT: nnz {g['nnz']} given the oracle's Z, {nnz_own} with the library's")
     del g
     r = api.spar_sink_uot(api.Problem(p.x, p.y, p.a, p.b, problem_index=p.problem_index),
                           eps=p.eps, s=p.s, lam=p.lam,
@@ -169,7 +177,7 @@ def test_ot_scale_full_size(api):
 def test_ot_scale_full_size_whole_sketch_and_estimate(api):
     """OT, n = m = 16384, d = 10, s = 8 n ln n, tol 1e-6: the oracle builds the
     whole sketch (2.7e8 pairs on a thread pool) and solves it, so the whole
-    mask, CSR and CSC are compared bit for bit, the FP64 values within 8 ulp,
+    mask, CSR and CSC are compared bit for bit, the FP64 values too,
     and the estimates of the FP64 and FP32 solves against the FP64 oracle's
     (FP64 within 1e-9 relative at the same stopping iteration; FP32 within
     the 1e-4 bar)."""
@@ -184,8 +192,8 @@ def test_ot_scale_full_size_whole_sketch_and_estimate(api):
     assert np.array_equal(g["mask"].cpu().numpy().view(np.uint64), sk.mask)
     for k in ("row_ptr", "col_idx", "col_ptr", "row_idx"):
         assert np.array_equal(g[k].cpu().numpy(), getattr(sk, k)), k
-    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=4e-16 * 8, atol=0)
-    np.testing.assert_allclose(g["val_t"].cpu().numpy(), sk.val_t, rtol=4e-16 * 8, atol=0)
+    assert np.array_equal(g["val"].cpu().numpy(), sk.val)
+    assert np.array_equal(g["val_t"].cpu().numpy(), sk.val_t)
     del g
     est, spo = o.estimate.estimate, o.estimate.sparse_objective
     r64 = api.spar_sink_ot(prob, eps=p.eps, s=p.s, seed=p.seed, tol=1e-6, max_iter=5000,

@@ -78,9 +78,10 @@ def test_sample_ot_bit_exact(api, name, make):
     assert np.array_equal(g["row_fac"].cpu().numpy(), sk.prob.alpha)
     assert np.array_equal(g["col_fac"].cpu().numpy(), sk.prob.rb)
     assert g["cmax"] == sk.cmax
-    # values: K / p* with K = exp(-C/eps) (host and device exp may differ by an ulp)
-    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=4e-16 * 8, atol=0)
-    np.testing.assert_allclose(g["val_t"].cpu().numpy(), sk.val_t, rtol=4e-16 * 8, atol=0)
+    # values: K / p* with K = exp(-C/eps) by the specified exponential on both
+    # sides, so the CSR and CSC values are bit-exact as well
+    assert np.array_equal(g["val"].cpu().numpy(), sk.val)
+    assert np.array_equal(g["val_t"].cpu().numpy(), sk.val_t)
 
 
 def test_sample_precisions_share_the_mask(api):
@@ -90,14 +91,37 @@ def test_sample_precisions_share_the_mask(api):
     glog = api.ss_sample(_prob(api, p), **_kw(p), precision="f32_log")
     for g in (g32, glog):
         _check_sketch_structure(g, sk)
-    # FP32 value = round-to-nearest of the FP64 value (allow the FP64 ulp wobble)
-    np.testing.assert_allclose(g32["val"].cpu().numpy(), sk.val.astype(np.float32), rtol=1.2e-7)
-    np.testing.assert_allclose(glog["val"].cpu().numpy(), sk.logval.astype(np.float32),
-                               rtol=1.2e-7, atol=1e-6)
+    # FP32 value = round-to-nearest of the (bit-exact) FP64 value; the log
+    # value likewise
+    assert np.array_equal(g32["val"].cpu().numpy(), sk.val.astype(np.float32))
+    assert np.array_equal(glog["val"].cpu().numpy(), sk.logval.astype(np.float32))
+    assert np.array_equal(glog["val_t"].cpu().numpy(), sk.logval_t.astype(np.float32))
 
 
 def _uot_mask_compare(g_mask, sk, p, rows):
     assert_mask_equal(g_mask[rows], sk.mask[rows], p, sk.prob, rows)
+
+
+def _uot_bit_exact(api, p, sk, **kw):
+    """ss_sample given the oracle's normaliser Z: every keep decision and
+    value is then the same IEEE operation sequence on both sides, so the
+    mask, CSR, CSC, values and p* factors must match bit for bit."""
+    g = api.ss_sample(_prob(api, p), **_kw(p), z_in=sk.prob.z, **kw)
+    assert g["z_norm"] == sk.prob.z
+    assert np.array_equal(_mask_np(g["mask"]), sk.mask)
+    _check_sketch_structure(g, sk)
+    assert np.array_equal(g["row_fac"].cpu().numpy(), sk.prob.la)
+    assert np.array_equal(g["col_fac"].cpu().numpy(), sk.prob.lb)
+    prec = kw.get("precision", "f64")
+    if prec == "f64":
+        ref, ref_t = sk.val, sk.val_t
+    elif prec == "f32":
+        ref, ref_t = sk.val.astype(np.float32), sk.val_t.astype(np.float32)
+    else:
+        ref, ref_t = sk.logval.astype(np.float32), sk.logval_t.astype(np.float32)
+    assert np.array_equal(g["val"].cpu().numpy(), ref)
+    assert np.array_equal(g["val_t"].cpu().numpy(), ref_t)
+    return g
 
 
 # lam = 1: the normaliser's short-range exponential (1/(2 lam + eps) <= 1/2);
@@ -106,13 +130,15 @@ def _uot_mask_compare(g_mask, sk, p, rows):
 def test_sample_uot(api, n, eps, lam):
     p = W.uot_mix3(n, seed=7, eps=eps, lam=lam)
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    # the library's own normaliser: Z within 1e-13, every mask bit equal
     g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
     assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
     _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
     _check_sketch_structure(g, sk)
     np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-14)
-    np.testing.assert_allclose(g["val_t"].cpu().numpy(), sk.val_t, rtol=1e-14)
-    np.testing.assert_allclose(g["row_fac"].cpu().numpy(), sk.prob.la, rtol=1e-15)
+    # given the oracle's Z: bit-exact in every precision
+    for prec in ("f64", "f32", "f32_log"):
+        _uot_bit_exact(api, p, sk, precision=prec)
 
 
 # Budgets at which most or all entries are kept: the mask kernel's per-wave
@@ -128,7 +154,7 @@ def test_sample_ot_dense_budgets(api, frac):
     _check_sketch_structure(g, sk)
     if frac > 1:
         assert sk.nnz == p.n * p.m
-    np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=4e-16 * 8, atol=0)
+    assert np.array_equal(g["val"].cpu().numpy(), sk.val)
 
 
 def test_sample_uot_dense_budget(api):
@@ -138,6 +164,7 @@ def test_sample_uot_dense_budget(api):
     g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
     _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
     _check_sketch_structure(g, sk)
+    _uot_bit_exact(api, p, sk, precision="f64")
 
 
 def test_sample_uot_plain_cost(api):
@@ -150,6 +177,7 @@ def test_sample_uot_plain_cost(api):
     _uot_mask_compare(_mask_np(g["mask"]), sk, p, np.arange(p.n))
     _check_sketch_structure(g, sk)
     np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-13)
+    _uot_bit_exact(api, p, sk, cost="plain", precision="f64")
 
 
 # ---------------------------------------------------------------- Sinkhorn loop

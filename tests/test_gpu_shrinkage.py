@@ -67,8 +67,8 @@ def test_sample_ot_shrink_bit_exact(api, g):
     _structure_equal(out, sk)
     assert np.array_equal(out["row_fac"].cpu().numpy(), sk.prob.alpha)
     assert np.array_equal(out["col_fac"].cpu().numpy(), sk.prob.rb)
-    np.testing.assert_allclose(out["val"].cpu().numpy(), sk.val, rtol=4e-16 * 8, atol=0)
-    np.testing.assert_allclose(out["val_t"].cpu().numpy(), sk.val_t, rtol=4e-16 * 8, atol=0)
+    assert np.array_equal(out["val"].cpu().numpy(), sk.val)
+    assert np.array_equal(out["val_t"].cpu().numpy(), sk.val_t)
     if g == 1.0:
         # Rand-Sink: every kept value is K_ij nm / s
         assert np.all(sk.pstar == p.s / (700.0 * 513.0))
@@ -92,6 +92,12 @@ def test_sample_uot_shrink(api, lam, g):
     _structure_equal(out, sk)
     np.testing.assert_allclose(out["val"].cpu().numpy(), sk.val, rtol=1e-14)
     np.testing.assert_allclose(out["val_t"].cpu().numpy(), sk.val_t, rtol=1e-14)
+    # given the oracle's normaliser: bit-exact
+    ex = api.ss_sample(_prob(api, p), **_kw(p), shrink=g, z_in=sk.prob.z, precision="f64")
+    assert np.array_equal(_mask_np(ex["mask"]), sk.mask)
+    _structure_equal(ex, sk)
+    for k in ("val", "val_t"):
+        assert np.array_equal(ex[k].cpu().numpy(), getattr(sk, k)), k
 
 
 @pytest.mark.parametrize("g", [0.5, 1.0])

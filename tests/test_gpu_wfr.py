@@ -58,6 +58,14 @@ def test_sample_wfr(api, pattern, ratio):
         assert np.array_equal(g[k].cpu().numpy(), getattr(sk, k)), k
     np.testing.assert_allclose(g["val"].cpu().numpy(), sk.val, rtol=1e-13)
     np.testing.assert_allclose(g["val_t"].cpu().numpy(), sk.val_t, rtol=1e-13)
+    # given the oracle's normaliser, the specified logarithm, cosine and
+    # exponential make mask, CSR, CSC, values and factors bit-exact
+    ge = api.ss_sample(_prob(api, p), **_kw(p), z_in=sk.prob.z, precision="f64")
+    assert np.array_equal(ge["mask"].cpu().numpy().view(np.uint64), sk.mask)
+    for k in ("row_ptr", "col_idx", "col_ptr", "row_idx", "val", "val_t"):
+        assert np.array_equal(ge[k].cpu().numpy(), getattr(sk, k)), k
+    assert np.array_equal(ge["row_fac"].cpu().numpy(), sk.prob.la)
+    assert np.array_equal(ge["col_fac"].cpu().numpy(), sk.prob.lb)
     # no kept entry lies at or beyond the blocking distance pi eta
     rows = np.repeat(np.arange(p.n), np.diff(g["row_ptr"].cpu().numpy()))
     cols = g["col_idx"].cpu().numpy()

@@ -11,6 +11,7 @@ import scipy.optimize
 import scipy.spatial.distance
 import scipy.special
 
+from oracle import elementary as EL
 from oracle import sparsink_oracle as O
 from paper_2306_06581_amd import workloads as W
 
@@ -201,7 +202,11 @@ def test_full_budget_gives_dense_kernel_and_dense_iterates():
     sk = O.build_sketch(p.x, p.y, p.a, p.b, opt)
     assert sk.nnz == 40 * 40 and np.all(sk.pstar == 1.0)
     C = O.sq_dist(p.x, p.y) * sk.inv_cmax
-    assert np.array_equal(sk.csr().toarray(), np.exp(-(C / p.eps)))
+    K = sk.csr().toarray()
+    # p* = 1 divides K by exactly 1: the stored values are the oracle's K
+    # (the specified exponential), which is the platform's within 2 ulp
+    assert np.array_equal(K, EL.exp_spec(-(C / p.eps)))
+    np.testing.assert_allclose(K, np.exp(-(C / p.eps)), rtol=4.5e-16, atol=0)
     rs = O.spar_sink(p.x, p.y, p.a, p.b, opt)
     rd = O.dense_sinkhorn(p.x, p.y, p.a, p.b, opt)
     assert rs.sinkhorn.iters == rd.sinkhorn.iters
@@ -484,13 +489,18 @@ def test_stop_residual_vanishes_at_the_uot_closed_form():
 
 
 def test_overflowing_scaling_raises():
-    # K = exp(-712) is subnormal: u = a / K overflows; the library reports
+    # a subnormal kernel entry: u = a / K overflows; the library reports
     # SS_E_NONFINITE there and the oracle raises instead of iterating on NaN
-    x, y = np.array([[0.0]]), np.array([[1.0]])
+    K = np.array([[5e-324]])
     a = b = np.array([0.5])
     with pytest.raises(O.NonFiniteError):
-        O.dense_sinkhorn(x, y, a, b, O.Options(eps=1.0 / 712.0, s=1e9, cost="plain",
+        O.sinkhorn(K, a, b, O.Options(eps=1.0, s=1e9, tol=1e-12, max_iter=10))
+    # exp(-C/eps) below e^-708 is 0 in the oracle (no subnormal kernel
+    # values): such an entry carries no weight and the line counts as empty
+    x, y = np.array([[0.0]]), np.array([[1.0]])
+    r = O.dense_sinkhorn(x, y, a, b, O.Options(eps=1.0 / 712.0, s=1e9, cost="plain",
                                                tol=1e-12, max_iter=10))
+    assert np.all(r.sinkhorn.u == 0.0)
 
 
 def test_thread_pool_sketch_matches_the_serial_sketch():
