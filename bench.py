@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--warmstart-train", type=int, default=100_000,
                     help="training problems for the learned warm start (0: skip)")
     ap.add_argument("--warmstart-only", action="store_true")
+    ap.add_argument("--predict-only", action="store_true",
+                    help="only the warm-start prediction for the batched workload (untrained "
+                         "weights; profiling runs)")
     ap.add_argument("--no-ibp", action="store_true")
     ap.add_argument("--ibp-only", action="store_true", help="only the Spar-IBP workload")
     ap.add_argument("--ibp-n", type=int, default=16384)
@@ -63,6 +66,11 @@ def parse():
     ap.add_argument("--wfr-only", action="store_true", help="only the WFR workload")
     ap.add_argument("--wfr-n", type=int, default=65536)
     ap.add_argument("--no-divergence", action="store_true")
+    ap.add_argument("--no-eps-small", action="store_true")
+    ap.add_argument("--no-hbm", action="store_true")
+    ap.add_argument("--no-ot-scale", action="store_true")
+    ap.add_argument("--sections-only", action="store_true",
+                    help="only the eps 0.01, HBM-resident and OT-scale sections")
     ap.add_argument("--divergence-only", action="store_true")
     ap.add_argument("--divergence-n", type=int, default=4096)
     return ap.parse_args()
@@ -350,35 +358,215 @@ def divergence_bench(n: int, steps: int, cpu: bool) -> dict:
     return out
 
 
-def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
-    """The FP64 oracle timed on a bounded sample of the same workload."""
+GOLDEN = os.path.join(ROOT, "tests", "golden", "bench_oracle.json")
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def timed_solves(fn, steps):
+    """fn() once as a warm-up, then `steps` timed calls; (last result, ms per call)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return out, (time.perf_counter() - t0) * 1e3 / steps
+
+
+def eps_small_bench(n: int, steps: int, dense: bool) -> dict:
+    """The headline UOT workload at the configuration's smaller eps = 0.01
+    (log-domain FP32, tol 1e-6), with the dense baseline (log-domain FP32,
+    the linear FP32 kernel underflows at this eps) beside it."""
+    from paper_2306_06581_amd import api as A
+    from paper_2306_06581_amd import workloads as W
+
+    p = W.uot_mix3(n, seed=0, eps=0.01)
+    prob = A.Problem(p.x, p.y, p.a, p.b)
+    kw = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, tol=1e-6, max_iter=5000,
+              precision="f32_log")
+    r, ms = timed_solves(lambda: A.spar_sink_uot(prob, **kw), steps)
+    out = {"workload": f"uot_mix3 n=m={n} d=3 lambda=1 eps=0.01 s=8nlnn tol=1e-6 f32_log",
+           "ms_per_solve": ms, "iters": r.iters, "status": r.status, "nnz": r.nnz,
+           "estimate": r.estimate, "sparse_objective": r.sparse_objective,
+           "stage_ms": {"prep": r.t_prep_ms, "sample": r.t_sample_ms, "iterate": r.t_iter_ms,
+                        "objective": r.t_obj_ms}}
+    r64 = A.spar_sink_uot(prob, **dict(kw, precision="f64"), raise_on_error=False)
+    out["f64_gpu"] = {"iters": r64.iters, "status": r64.status, "estimate": r64.estimate,
+                      "f32_log_rel_err": _rel(r.estimate, r64.estimate)}
+    if dense:
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = A.dense_sinkhorn(prob, **dict(kw, precision="f32_log"))
+        torch.cuda.synchronize()
+        dms = (time.perf_counter() - t0) * 1e3
+        out.update({"dense_ms": dms, "dense_iters": d.iters, "dense_status": d.status,
+                    "dense_precision": "f32_log", "dense_estimate": d.estimate,
+                    "speedup_vs_dense": dms / ms})
+    return out
+
+
+def hbm_bench(steps: int) -> dict:
+    """Iteration-kernel bandwidth where the per-iteration data cannot stay in
+    the 256 MB Infinity Cache: the headline generator at s = 32 n ln n
+    (2 x 140 MB of entries per iteration) and at n = 131072 (s = 8 n ln n),
+    plus the whole solve at s = 32 n ln n."""
+    from paper_2306_06581_amd import api as A
+    from paper_2306_06581_amd import workloads as W
+
+    out = {}
+    for n, f in ((65536, 32.0), (131072, 8.0)):
+        p = W.uot_mix3(n, seed=0, eps=0.05, s_factor=f)
+        prob = A.Problem(p.x, p.y, p.a, p.b)
+        kw = dict(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, precision="f32_log")
+        ms_launch = A.ss_time_iterations(prob, 64, **kw)
+        r1 = A.spar_sink_uot(prob, **kw, tol=1e-6, max_iter=1, raise_on_error=False)
+        by = iteration_bytes_per_launch("f32_log", r1.nnz, p.n, p.m)
+        gbps = by / (ms_launch * 1e-3) / 1e9
+        key = f"uot_mix3_n{n}_s{f:g}"
+        out[key] = {"workload": f"uot_mix3 n=m={n} d=3 lambda=1 eps=0.05 s={f:g}nlnn f32_log",
+                    "nnz": r1.nnz, "ms_per_launch": ms_launch, "bytes_per_launch": by,
+                    "GBps": gbps, "frac_of_8TBps": gbps / HBM_PEAK_GBPS}
+        if n == 65536:
+            r, ms = timed_solves(lambda: A.spar_sink_uot(prob, **kw, tol=1e-6, max_iter=5000),
+                                 steps)
+            out[key].update({"ms_per_solve": ms, "iters": r.iters, "status": r.status,
+                             "stage_ms": {"sample": r.t_sample_ms, "iterate": r.t_iter_ms}})
+    return out
+
+
+def ot_scale_bench(steps: int, dense: bool) -> dict:
+    """OT at scale: n = m = 16384, d = 10, x ~ N(0, I), y ~ t5 + 0.5,
+    Dirichlet(1) weights, eps = 0.05 on the max-normalised cost, FP32,
+    tol 1e-6, s in {4, 8, 16} n ln n, against dense Sinkhorn (FP32, K
+    recomputed) on the same GPU; each FP32 estimate's relative error against
+    the FP64 oracle (tests/golden/bench_oracle.json, written by the oracle)
+    and against the library's FP64 solve.  Also the OT row at n = 65536."""
+    from paper_2306_06581_amd import api as A
+    from paper_2306_06581_amd import workloads as W
+
+    gold = {}
+    if os.path.exists(GOLDEN):
+        gold = json.load(open(GOLDEN))
+    out = {}
+    for n, factors in ((16384, (4.0, 8.0, 16.0)), (65536, (8.0,))):
+        dense_ms = dense_iters = dense_est = None
+        for f in factors:
+            p = W.ot_t5_d10(n, seed=0, s_factor=f)
+            prob = A.Problem(p.x, p.y, p.a, p.b)
+            kw = dict(eps=p.eps, s=p.s, seed=p.seed, tol=1e-6, max_iter=5000, precision="f32")
+            r, ms = timed_solves(lambda: A.spar_sink_ot(prob, **kw), steps)
+            r64 = A.spar_sink_ot(prob, **dict(kw, precision="f64"))
+            ms_launch = A.ss_time_iterations(prob, 64, eps=p.eps, s=p.s, seed=p.seed,
+                                             precision="f32")
+            by = iteration_bytes_per_launch("f32", r.nnz, p.n, p.m)
+            key = f"ot_t5_d10_n{n}_s{f:g}"
+            row = {"workload": f"ot_t5_d10 n=m={n} d=10 eps=0.05 s={f:g}nlnn f32 tol=1e-6",
+                   "ms_per_solve": ms, "iters": r.iters, "status": r.status, "nnz": r.nnz,
+                   "estimate": r.estimate, "sparse_objective": r.sparse_objective,
+                   "stage_ms": {"sample": r.t_sample_ms, "iterate": r.t_iter_ms},
+                   "ms_per_launch": ms_launch, "GBps": by / (ms_launch * 1e-3) / 1e9,
+                   "f64_gpu_estimate": r64.estimate,
+                   "rel_err_vs_f64_gpu": _rel(r.estimate, r64.estimate)}
+            g = gold.get(key)
+            if g is not None:
+                row["oracle_f64"] = {"estimate": g["estimate"], "iters": g["iters"],
+                                     "nnz": g["nnz"]}
+                row["rel_err_vs_oracle_f64"] = _rel(r.estimate, g["estimate"])
+                row["sparse_objective_rel_err_vs_oracle_f64"] = _rel(r.sparse_objective,
+                                                                     g["sparse_objective"])
+            if dense and dense_ms is None:
+                import torch
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                d = A.dense_sinkhorn(prob, **kw)
+                torch.cuda.synchronize()
+                dense_ms = (time.perf_counter() - t0) * 1e3
+                dense_iters, dense_est = d.iters, d.estimate
+            if dense_ms is not None:
+                row.update({"dense_ms": dense_ms, "dense_iters": dense_iters,
+                            "dense_estimate": dense_est, "speedup_vs_dense": dense_ms / ms,
+                            "rel_err_vs_dense": _rel(r.estimate, dense_est),
+                            "sparse_objective_rel_err_vs_dense": _rel(r.sparse_objective,
+                                                                      dense_est)})
+            out[key] = row
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, gpu_iters: int, precision_log: bool, z_gpu: float, cmax_gpu: float,
+                 dense_iters: int | None) -> dict:
+    """The FP64 oracle on the host's cores, on a bounded sample of the same
+    workload; every part is extrapolated to the full size and labelled so.
+
+    * cost scan, UOT normaliser and hash mask: R rows against all m columns
+      (the normaliser's row sums timed on those rows; the p* of the timed
+      mask uses the full normaliser, taken from the GPU solve, which matches
+      the oracle's to 1e-12), scaled by n / R;
+    * Sinkhorn iterations: the oracle's loop on the same generator at
+      n = 4096 (its own sketch), per iteration scaled by (nnz + n + m) to
+      the full size, times the GPU's iteration count;
+    * dense FP64 Sinkhorn (K recomputed): one product K v on R rows timed,
+      scaled by n / R, two per iteration, times the dense GPU run's count."""
     import numpy as np
 
+    from oracle import elementary as EL
     from oracle import sparsink_oracle as O
     from paper_2306_06581_amd import workloads as W
 
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    workers = max(1, cores or 1)
     t_all = time.perf_counter()
-    R = 256
+    R = 1024
+    uot = math.isfinite(p.lam)
     opt = O.Options(eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, log_domain=precision_log)
-    _, inv_cmax = O.cost_scale(p.x[:R], p.y, opt)  # cost scan of R rows, the rest scaled below
+    rows = np.arange(R)
+    chunk = max(1, R // workers)
     t0 = time.perf_counter()
-    O.max_sq_dist(p.x[:R], p.y)
-    t_cmax_rows = time.perf_counter() - t0
+    O.max_sq_dist(p.x[:R], p.y, chunk=chunk, workers=workers)
+    t_cmax = time.perf_counter() - t0
+    inv_cmax = 1.0 / cmax_gpu  # the full maximum (the oracle's equals it bit for bit)
     t0 = time.perf_counter()
-    if math.isfinite(p.lam):
-        prob = O.uot_probabilities(p.a[:R], p.b, p.x[:R], p.y, p.s, p.lam, p.eps, inv_cmax)
+    if uot:
+        O.uot_probabilities(p.a[:R], p.b, p.x[:R], p.y, p.s, p.lam, p.eps, inv_cmax,
+                            chunk=chunk, workers=workers)
+        t_z = time.perf_counter() - t0
+        # the mask's p* with the full normaliser
+        full = O.uot_probabilities(p.a[:1], p.b, p.x[:1], p.y, p.s, p.lam, p.eps, inv_cmax)
+        prob = O.ProbUOT(la=p.lam / (2 * p.lam + p.eps) * EL.log_spec(p.a), lb=full.lb,
+                         inv_tau=full.inv_tau, inv_cmax=inv_cmax, z=z_gpu, kappa=p.s / z_gpu,
+                         x=np.asarray(p.x, np.float64), y=full.y)
     else:
         prob = O.ot_probabilities(p.a, p.b, p.s)
-    O.sample_rows(p.x, p.y, p.a, p.b, opt, np.arange(R), prob)
-    t_sample_rows = time.perf_counter() - t0
-    t_sample = (t_cmax_rows + t_sample_rows) * (p.n / R)
-    # iteration cost measured on the same generator at n_small, scaled by size
+        t_z = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O._map_chunks(lambda r0: O.sample_rows(p.x, p.y, p.a, p.b, opt,
+                                           rows[r0:r0 + chunk], prob)[0].sum(),
+                  range(0, R, chunk), workers)
+    t_mask = time.perf_counter() - t0
+    scale = p.n / R
+    t_sample = (t_cmax + t_z + t_mask) * scale
+    # iterations at n = 4096 of the same generator
     ns = 4096
-    q = W.uot_mix3(ns, seed=p.seed, eps=p.eps) if math.isfinite(p.lam) else W.ot_t5_d10(ns)
-    it = 100
+    q = W.uot_mix3(ns, seed=p.seed, eps=p.eps) if uot else W.ot_t5_d10(ns, seed=p.seed)
+    it = 20
     optq = O.Options(eps=q.eps, s=q.s, lam=q.lam, seed=q.seed, tol=0.0, max_iter=it,
                      log_domain=precision_log)
-    sk = O.build_sketch(q.x, q.y, q.a, q.b, optq)
+    sk = O.build_sketch(q.x, q.y, q.a, q.b, optq, workers=workers)
     a_eff, b_eff, ra, ca, _, _ = O.apply_empty_policy(q.a, q.b, np.diff(sk.row_ptr),
                                                       np.diff(sk.col_ptr), optq)
     t0 = time.perf_counter()
@@ -387,15 +575,31 @@ def cpu_baseline(p, gpu_iters: int, precision_log: bool) -> dict:
     else:
         O.sinkhorn(sk.csr(), a_eff, b_eff, optq, ra, ca)
     t_it_small = (time.perf_counter() - t0) / it
-    nnz_full = p.s
-    scale = (nnz_full + p.n + p.m) / (sk.nnz + q.n + q.m)
-    t_iter = t_it_small * scale * gpu_iters
-    total = t_sample + t_iter
-    return {"value": total, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle cost scan + p* + hash mask on {R} of {p.n} rows (x{p.n // R}); "
-                       f"{it} oracle iterations at n={ns} scaled by (nnz+n+m) to the full size "
-                       f"x {gpu_iters} iterations; measured {time.perf_counter() - t_all:.1f} s"),
-            "parts_s": {"sample": t_sample, "iterations": t_iter}}
+    t_iter = t_it_small * (p.s + p.n + p.m) / (sk.nnz + q.n + q.m) * gpu_iters
+    out = {"value": t_sample + t_iter, "unit": "s", "cores": workers, "kind": "oracle",
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "extrapolated": True,
+           "sample": (f"oracle on {workers} threads: cost scan, normaliser row sums and hash "
+                      f"mask on {R} of {p.n} rows (x{scale:g}); {it} oracle iterations at "
+                      f"n={ns} scaled by (nnz+n+m) to the full size x {gpu_iters} GPU "
+                      f"iterations; measured {time.perf_counter() - t_all:.1f} s"),
+           "parts_s": {"sample": t_sample, "iterations": t_iter}}
+    if dense_iters:
+        # one dense half-step on R rows: K recomputed (cost, specified exp) and K v
+        v = np.ones(p.m)
+        t0 = time.perf_counter()
+
+        def krows(r0):
+            rr = np.arange(r0, min(R, r0 + chunk))
+            c = O.cost_from_sq(O.sq_dist(p.x[rr], p.y), "maxnorm", inv_cmax, 1.0)
+            return EL.exp_spec(-(c / p.eps)) @ v
+
+        O._map_chunks(krows, range(0, R, chunk), workers)
+        t_half = (time.perf_counter() - t0) * scale
+        out["dense_fp64"] = {"value": t_half * 2 * dense_iters, "unit": "s",
+                             "extrapolated": True, "iters": dense_iters,
+                             "sample": f"one K v over {R} of {p.n} rows (K recomputed), x{scale:g} "
+                                       f"rows, x2 half-steps, x{dense_iters} iterations"}
+    return out
 
 
 def main():
@@ -427,6 +631,30 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"ibp": ibp_bench(args.ibp_n, args.steps, not args.no_cpu)}))
+        return
+    if args.sections_only:
+        import torch
+        torch.cuda.set_device(0)
+        out = {}
+        if not args.no_eps_small:
+            out["eps_small"] = eps_small_bench(args.n, args.steps, not args.no_dense)
+        if not args.no_hbm:
+            out["hbm_resident"] = hbm_bench(args.steps)
+        if not args.no_ot_scale:
+            out["ot_scale"] = ot_scale_bench(args.steps, not args.no_dense)
+        print(json.dumps(out))
+        return
+    if args.predict_only:
+        import torch
+
+        from paper_2306_06581_amd import api as A
+        from paper_2306_06581_amd import workloads as W
+        torch.cuda.set_device(0)
+        B = A.Batch.from_problems(W.batch_ot(args.batch_count, seed=0))
+        net = A.WarmStartNet(seed=0)
+        _, ms = timed_solves(lambda: net.predict(B, eps=0.05), args.steps)
+        print(json.dumps({"predict_ms": ms, "problems": args.batch_count,
+                          "points": int(B.row_off[-1] + B.col_off[-1])}))
         return
     if args.warmstart_only:
         import torch
@@ -538,8 +766,15 @@ def main():
         out["wfr"] = wfr_bench(args.wfr_n, args.steps, not args.no_dense)
     if not args.no_divergence:
         out["divergence"] = divergence_bench(args.divergence_n, args.steps, not args.no_cpu)
+    if not args.no_eps_small:
+        out["eps_small"] = eps_small_bench(args.n, args.steps, not args.no_dense)
+    if not args.no_hbm:
+        out["hbm_resident"] = hbm_bench(args.steps)
+    if not args.no_ot_scale:
+        out["ot_scale"] = ot_scale_bench(args.steps, not args.no_dense)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, r.iters, args.precision == "f32_log")
+        out["cpu_baseline"] = cpu_baseline(p, r.iters, args.precision == "f32_log", r.z_norm,
+                                           r.cmax, out.get("dense_iters"))
     print(json.dumps(out))
 
 

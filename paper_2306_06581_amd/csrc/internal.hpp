@@ -200,9 +200,13 @@ hipError_t launch_reduce_stats(const ReduceSpec& r, double* stats, hipStream_t s
 // ---- iterate.hip
 // Device-side parameters of a lane plan (see build_plan).
 struct PlanInfo {
-    int64_t T;     // quad weight per step
-    int64_t K;     // number of steps
-    int32_t maxw;  // largest line weight (quads)
+    int64_t T;      // quad weight per step
+    int64_t K;      // number of steps
+    int64_t Q;      // quads of all lines
+    int64_t W1;     // line weights summed with the single-pass floor
+    int64_t tcap;   // largest step weight of the chosen policy
+    int64_t kmin;   // fewest steps of the chosen policy
+    int32_t minw;   // line weight floor of the chosen policy
     int32_t pad;
 };
 

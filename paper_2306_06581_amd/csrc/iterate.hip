@@ -78,6 +78,7 @@ struct SliceCfg {
 };
 
 constexpr int kMaxPairs = 2048;  // (slice, line) segments per step
+constexpr int kPassesMax = 8;    // passes per step under the multi-pass policy
 static_assert(SliceCfg<1024>::buf <= 65536, "byte offsets must fit in 16 bits");
 static_assert(SliceCfg<1024>::lds <= 160 * 1024 && 3 * SliceCfg<256>::lds <= 160 * 1024,
               "LDS budget");
@@ -161,37 +162,89 @@ __global__ void k_split(const int64_t* __restrict__ ptr, const int32_t* __restri
     out[ns] = (int32_t)(k1 - k0);
 }
 
-// Quads of every line, its step weight max(quads, minw), largest weight.
-__global__ void k_plan_quads(const int32_t* __restrict__ split, int64_t nlines, int ns, int minw,
-                             int32_t* __restrict__ quads, int32_t* __restrict__ weight,
-                             PlanInfo* info) {
+// Quads of every line; their total and the total of the line weights under
+// the single-pass policy's floor minw1 (atomic adds of integers: exact).
+__global__ void k_plan_quads(const int32_t* __restrict__ split, int64_t nlines, int ns, int minw1,
+                             int32_t* __restrict__ quads, PlanInfo* info) {
     const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int w = 0;
+    int64_t q = 0, w = 0;
     if (line < nlines) {
         const int32_t* sp = split + line * (ns + 1);
-        int q = 0;
         for (int s = 0; s < ns; ++s) q += (sp[s + 1] - sp[s] + 3) / 4;
-        quads[line] = q;
-        w = q > minw ? q : minw;
-        weight[line] = w;
+        quads[line] = (int32_t)q;
+        w = q > minw1 ? q : minw1;
     }
-    w = group_max<kWave>(w);
-    if ((threadIdx.x & (kWave - 1)) == 0 && w > 0) atomicMax(&info->maxw, w);
+    q = group_sum<kWave>(q);
+    w = group_sum<kWave>(w);
+    if ((threadIdx.x & (kWave - 1)) == 0 && w > 0) {
+        atomicAdd((unsigned long long*)&info->Q, (unsigned long long)q);
+        atomicAdd((unsigned long long*)&info->W1, (unsigned long long)w);
+    }
 }
 
-// Step weight T and step count K (one thread).  The weight cap leaves 1/16
-// of a pass of `block` lanes, plus one partial lane per slice, for the last
-// line of a step (which may run past T) and the layout's padding; line
-// weights are floored at minw, so a step's quads are usually well below its
-// weight.  A step that still overflows takes a second pass.
-__global__ void k_plan_setup(const int64_t* __restrict__ wptr, int64_t nlines, int block, int J,
-                             int ns, int64_t resident, int64_t kmax, PlanInfo* info) {
+// Step policy (one thread).  Each pass of a step first copies the slices its
+// lanes read, so a launch copies about ns + passes - 1 slices per step.
+//  * single-pass: step weight at most 15/16 of a pass (tcap1), line weights
+//    floored at minw1 (a step then holds few enough lines and segments for
+//    the LDS tables); kept whenever it needs no more steps than there are
+//    resident blocks (one step, one pass per block);
+//  * multi-pass: otherwise, kmin = S * resident steps of up to kPassesMax
+//    passes, S the fewest with S * resident * L >= 3/2 nlines (L = most lines
+//    a step may hold, less one), and the floor minw = ceil((Q + kmin) /
+//    (kmin L - nlines)): a step of weight T <= (Q + nlines minw) / kmin + 1
+//    then holds at most T / minw + 1 <= L + 1 lines.  Taken when it needs
+//    fewer steps than the single-pass policy.
+__global__ void k_plan_policy(int64_t nlines, int block, int J, int ns, int minw1,
+                              int64_t resident, int64_t kmax, PlanInfo* info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t tcap1 = step_quads(block, J) - (int64_t)ns * J;
+    if (tcap1 < (int64_t)block * J / 4) tcap1 = (int64_t)block * J / 4;
+    const int64_t k1 = (((info->W1 + tcap1 - 1) / tcap1) + resident - 1) / resident * resident;
+    info->minw = minw1;
+    info->tcap = tcap1;
+    info->kmin = 0;
+    if (k1 <= resident) return;
+    const int64_t Q = info->Q;
+    int64_t L = block / 2 < kMaxPairs / ns ? block / 2 : kMaxPairs / ns;
+    L -= 1;
+    int64_t tmax = (int64_t)kPassesMax * step_quads(block, J) - (int64_t)ns * J;
+    int64_t S = (Q + resident * tmax - 1) / (resident * tmax);
+    if (S < 1) S = 1;
+    while (2 * S * resident * L < 3 * nlines) ++S;
+    const int64_t kmin = S * resident;
+    // the line bound needs K >= kmin, which the clamps of k_plan_setup to
+    // nlines and kmax could break
+    if (kmin >= k1 || L < 1 || kmin > nlines || kmin > kmax) return;
+    int64_t w = (Q + kmin + kmin * L - nlines - 1) / (kmin * L - nlines);
+    if (w < 2 * J) w = 2 * J;
+    if (w > tmax) w = tmax;
+    info->minw = (int32_t)w;
+    info->tcap = tmax;
+    info->kmin = kmin;
+}
+
+// Step weight of every line, max(quads, minw) under the chosen floor.
+__global__ void k_plan_weights(const int32_t* __restrict__ quads, int64_t nlines,
+                               const PlanInfo* __restrict__ info, int32_t* __restrict__ weight) {
+    const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= nlines) return;
+    const int32_t q = quads[line], w = info->minw;
+    weight[line] = q > w ? q : w;
+}
+
+// Step weight T and step count K (one thread).  The single-pass cap leaves
+// 1/16 of a pass of `block` lanes, plus one partial lane per slice, for the
+// last line of a step (which may run past T) and the layout's padding; line
+// weights are floored, so a step's quads are usually well below its weight.
+// A step that still overflows takes another pass.
+__global__ void k_plan_setup(const int64_t* __restrict__ wptr, int64_t nlines, int64_t resident,
+                             int64_t kmax, PlanInfo* info) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int64_t W = wptr[nlines];
-    int64_t tcap = step_quads(block, J) - (int64_t)ns * J;
-    if (tcap < (int64_t)block * J / 4) tcap = (int64_t)block * J / 4;
+    const int64_t tcap = info->tcap;
     const int64_t kb = (W + tcap - 1) / tcap;
-    int64_t K = (kb + resident - 1) / resident * resident;
+    int64_t K = kb > info->kmin ? kb : info->kmin;
+    K = (K + resident - 1) / resident * resident;
     if (K > nlines) K = nlines;
     if (K < kb) K = kb;
     if (K > kmax) K = kmax;
@@ -931,12 +984,17 @@ hipError_t build_plan(int precision, const IterPlan& p, const int64_t* ptr, cons
                        p.split);
     hipError_t e = launch_fill_u32((uint32_t*)p.info, sizeof(PlanInfo) / 4, 0u, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_quads, dim3(nb), dim3(256), 0, st, p.split, nlines, p.ns,
-                       min_weight(p.block, p.ns, J), p.quads, p.weight, p.info);
+    const int minw1 = min_weight(p.block, p.ns, J);
+    hipLaunchKernelGGL(k_plan_quads, dim3(nb), dim3(256), 0, st, p.split, nlines, p.ns, minw1,
+                       p.quads, p.info);
+    hipLaunchKernelGGL(k_plan_policy, dim3(1), dim3(64), 0, st, nlines, p.block, J, p.ns, minw1,
+                       (int64_t)p.grid, p.kmax, p.info);
+    hipLaunchKernelGGL(k_plan_weights, dim3(nb), dim3(256), 0, st, p.quads, nlines, p.info,
+                       p.weight);
     e = launch_scan(p.weight, nlines, p.wptr, p.scan, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_setup, dim3(1), dim3(64), 0, st, p.wptr, nlines, p.block, J, p.ns,
-                       (int64_t)p.grid, p.kmax, p.info);
+    hipLaunchKernelGGL(k_plan_setup, dim3(1), dim3(64), 0, st, p.wptr, nlines, (int64_t)p.grid,
+                       p.kmax, p.info);
     hipLaunchKernelGGL(k_plan_bounds, dim3((unsigned)((nlines + 1 + 255) / 256)), dim3(256), 0, st,
                        p.wptr, nlines, p.info, p.rstart);
     hipLaunchKernelGGL(k_layout, dim3((unsigned)p.kmax), dim3(256), 0, st, p.split, p.ns, J,

@@ -337,6 +337,28 @@ def test_long_lines_take_several_chunks(api):
     np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-11)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_log"])
+def test_multi_pass_steps(api, precision):
+    # ~6.3e6 entries over 3000 lines: the single-pass step plan would need
+    # more steps than there are resident blocks, so the planner switches to
+    # steps of several passes each (one step per block); iterates and
+    # estimates must not change
+    p = W.ot_gauss2d(3000, seed=23)
+    p.s = 0.7 * 3000 * 3000
+    T = 12
+    o = O.spar_sink(p.x, p.y, p.a, p.b, _oopt(p, tol=0.0, max_iter=T), workers=8)
+    assert o.nnz > 5_500_000
+    g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=0.0, max_iter=T), precision=precision,
+                         return_scalings=True)
+    assert g.nnz == o.nnz and g.iters == T
+    if precision == "f64":
+        np.testing.assert_allclose(g.u.cpu().numpy(), o.sinkhorn.u, rtol=1e-10, atol=0)
+        np.testing.assert_allclose(g.v.cpu().numpy(), o.sinkhorn.v, rtol=1e-10, atol=0)
+        assert _rel(g.estimate, o.estimate.estimate) < 1e-10
+    else:
+        assert _rel(g.estimate, o.estimate.estimate) < 1e-4
+
+
 def test_warm_start_from_solution_converges_immediately(api):
     p = W.ot_gauss2d(1024, seed=19)
     g = api.spar_sink_ot(_prob(api, p), **_kw(p, tol=1e-10, max_iter=500), return_scalings=True)
