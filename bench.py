@@ -77,6 +77,8 @@ def parse():
 
 
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_iterate_uot_mix3_n65536_f32_log_traffic.txt")
+PROFILE_TRAFFIC_S32 = os.path.join(ROOT, "profiles",
+                                   "k_iterate_uot_mix3_n65536_s32_f32_log_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2306_06581_amd", "csrc", "iterate.hip")
 
 
@@ -97,14 +99,14 @@ def iteration_bytes_per_launch(precision: str, nnz: int, n: int, m: int) -> floa
     return (u + v) / 2.0
 
 
-def measured_traffic(bytes_launch: float):
+def measured_traffic(bytes_launch: float, path: str = PROFILE_TRAFFIC):
     """HBM bytes per iteration launch from the committed PMC summary, scaled
     by the copy calibration; None when the summary is missing or the kernel
     source changed since the counters were taken."""
     import hashlib
     try:
         kv = {}
-        for line in open(PROFILE_TRAFFIC):
+        for line in open(path):
             parts = line.split()
             if len(parts) == 2 and not line.startswith("#"):
                 kv[parts[0]] = parts[1]
@@ -432,6 +434,14 @@ def hbm_bench(steps: int) -> dict:
         out[key] = {"workload": f"uot_mix3 n=m={n} d=3 lambda=1 eps=0.05 s={f:g}nlnn f32_log",
                     "nnz": r1.nnz, "ms_per_launch": ms_launch, "bytes_per_launch": by,
                     "GBps": gbps, "frac_of_8TBps": gbps / HBM_PEAK_GBPS}
+        if n == 65536 and f == 32.0:
+            tr = measured_traffic(by, PROFILE_TRAFFIC_S32)
+            out[key]["roofline"] = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS,
+                                    "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                                    "traffic": tr["bytes"] if tr else None,
+                                    "kernel": "k_iterate (sparse iteration)"}
+            if tr:
+                out[key]["roofline"]["traffic_detail"] = tr
         if n == 65536:
             r, ms = timed_solves(lambda: A.spar_sink_uot(prob, **kw, tol=1e-6, max_iter=5000),
                                  steps)
@@ -770,6 +780,10 @@ def main():
         out["eps_small"] = eps_small_bench(args.n, args.steps, not args.no_dense)
     if not args.no_hbm:
         out["hbm_resident"] = hbm_bench(args.steps)
+        # the same kernel where its data cannot stay in the Infinity Cache
+        out["roofline_hbm_resident"] = dict(
+            out["hbm_resident"]["uot_mix3_n65536_s32"].get("roofline", {}),
+            workload=out["hbm_resident"]["uot_mix3_n65536_s32"]["workload"])
     if not args.no_ot_scale:
         out["ot_scale"] = ot_scale_bench(args.steps, not args.no_dense)
     if not args.no_cpu:

@@ -185,7 +185,8 @@ class Options:
     max_iter: int = 1000
     seed: int = 0
     problem_index: int = 0
-    cost: str = "maxnorm"          # "maxnorm" (C = c / max c) or "plain" (C = c)
+    cost: str = "maxnorm"          # "maxnorm" (C = c / max c), "plain" (C = c),
+                                   # "euclid" (C = sqrt c), "wfr"
     empty_policy: str = "auto"     # auto | renormalize | zero | fail
     stop_rule: str = "marginal"    # marginal | delta
     log_domain: bool = False
@@ -223,11 +224,15 @@ HALF_PI = math.pi / 2
 
 def cost_from_sq(c, kind: str, inv_cmax: float, eta: float):
     """C from squared Euclidean distances c.  "maxnorm" / "plain": c * inv_cmax.
+    "euclid": the Euclidean distance sqrt(c) (the distance the generative-
+    modelling section names; correctly rounded square root).
     "wfr": the Wasserstein-Fisher-Rao cost of the UOT background section,
     C = -log cos_+^2(d / (2 eta)) with the Euclidean distance d = sqrt(c) and
     cos_+(z) = cos(min(z, pi/2)); written -2 log cos(z) with
     z = sqrt(c) * (0.5 / eta), and +inf (K = 0) where z >= pi/2, which the
     section states for d >= pi eta."""
+    if kind == "euclid":
+        return np.sqrt(c)
     if kind != "wfr":
         return c * inv_cmax
     z = np.sqrt(c) * (0.5 / eta)
