@@ -49,7 +49,8 @@ enum {
 };
 
 enum { SS_F64 = 0, SS_F32 = 1, SS_F32_LOG = 2 };                 /* ss_options.precision */
-enum { SS_COST_SQEUCLID_MAXNORM = 0, SS_COST_SQEUCLID = 1, SS_COST_WFR = 2 }; /* ss_options.cost */
+enum { SS_COST_SQEUCLID_MAXNORM = 0, SS_COST_SQEUCLID = 1, SS_COST_WFR = 2,
+       SS_COST_EUCLID = 3 }; /* ss_options.cost */
 enum { SS_STOP_MARGINAL_L1 = 0, SS_STOP_SCALING_DELTA_L1 = 1 };   /* ss_options.stop_rule */
 enum { SS_EMPTY_AUTO = 0, SS_EMPTY_RENORMALIZE = 1, SS_EMPTY_ZERO = 2, SS_EMPTY_FAIL = 3 };
 
@@ -82,6 +83,10 @@ typedef struct ss_problem {
  *                      log-sum-exp with FP32 exponentials.
  * cost         SS_COST_SQEUCLID_MAXNORM: C = |x-y|^2 / max |x-y|^2.
  *              SS_COST_SQEUCLID:         C = |x-y|^2.
+ *              SS_COST_EUCLID:           C = |x-y| (the Euclidean distance the
+ *                      generative-modelling section names between samples);
+ *                      OT sampling only (lambda = +INFINITY): spar_sink_ot,
+ *                      spar_sink_ot_noalloc, ss_sample and the divergence.
  *              SS_COST_WFR: the Wasserstein-Fisher-Rao cost of the UOT
  *                      background section, C = -log cos_+^2(|x-y| / (2 eta)),
  *                      evaluated as -2 log cos(|x-y| * (1 / (2 eta))) and

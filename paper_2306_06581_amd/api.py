@@ -609,11 +609,12 @@ class DivergenceResult:
 
 
 def sinkhorn_divergence(prob: Problem, *, eps, s, tol=1e-6, max_iter=1000, seed=0,
-                        precision="f64", shrink=0.0, graph_iters=0, return_grad=True,
-                        stream=None, raise_on_error=True) -> DivergenceResult:
+                        precision="f64", shrink=0.0, graph_iters=0, cost="plain",
+                        return_grad=True, stream=None, raise_on_error=True) -> DivergenceResult:
     """eq. (sink-div) from three Spar-Sink OT solves, with the envelope
-    gradients in x and y (squared Euclidean cost, unnormalised)."""
-    opts = make_options(eps, s, math.inf, tol, max_iter, seed, precision, "plain", "marginal",
+    gradients in x and y; cost "plain" (|x - y|^2) or "euclid" (|x - y|),
+    both unnormalised."""
+    opts = make_options(eps, s, math.inf, tol, max_iter, seed, precision, cost, "marginal",
                         "auto", 0, graph_iters, shrink=shrink)
     out = ctypes.c_size_t(0)
     rc = N.lib.ss_divergence_workspace_size(ctypes.byref(prob.c), ctypes.byref(opts),

@@ -213,8 +213,15 @@ int check_args(const ss_problem* P, const ss_options* O, bool dense) {
     if (O->precision < SS_F64 || O->precision > SS_F32_LOG)
         return fail(SS_E_INVALID_ARG, "unknown precision %d", O->precision);
     if (O->cost != SS_COST_SQEUCLID_MAXNORM && O->cost != SS_COST_SQEUCLID &&
-        O->cost != SS_COST_WFR)
+        O->cost != SS_COST_WFR && O->cost != SS_COST_EUCLID)
         return fail(SS_E_INVALID_ARG, "unknown cost %d", O->cost);
+    if (O->cost == SS_COST_EUCLID) {
+        // the dense kernels and the UOT probability's bounds and normaliser
+        // are written for the squared distances
+        if (dense) return fail(SS_E_INVALID_ARG, "dense_sinkhorn takes the squared Euclidean or WFR cost");
+        if (isfinite(O->lambda))
+            return fail(SS_E_INVALID_ARG, "the Euclidean cost takes OT sampling (lambda = +INFINITY)");
+    }
     if (O->cost == SS_COST_WFR) {
         if (!(O->eta > 0.0) || !isfinite(O->eta))
             return fail(SS_E_INVALID_ARG, "the WFR cost needs a finite eta > 0");
@@ -867,9 +874,13 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     oa.role = 1;
     HIP_TRY(launch_objective(prec, oa, c.st));
     if (gs) {
-        // squared Euclidean cost: dC_ij/dx_i = 2 inv_cmax (x_i - y_j), and the
+        // squared Euclidean cost: dC_ij/dx_i = 2 inv_cmax (x_i - y_j); Euclidean
+        // cost: (x_i - y_j) / |x_i - y_j| (0 where the points coincide); the
         // column side symmetrically
+        const bool eu = O->cost == SS_COST_EUCLID;
+        const double gscale = eu ? 1.0 : 2.0 * c.inv_cmax;
         GradArgs ga;
+        ga.euclid = eu ? 1 : 0;
         ga.ptr = at<int64_t>(ws, c.L.row_ptr);
         ga.idx = at<int32_t>(ws, c.L.col_idx);
         ga.val = at<void>(ws, c.L.val);
@@ -879,7 +890,7 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         ga.xl = P->x;
         ga.xo = P->y;
         ga.d = P->d;
-        ga.coef = 2.0 * c.inv_cmax * gs->cx;
+        ga.coef = gscale * gs->cx;
         ga.out = gs->gx;
         HIP_TRY(launch_plan_grad(prec, ga, c.st));
         ga.ptr = at<int64_t>(ws, c.L.col_ptr);
@@ -890,7 +901,7 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
         ga.zs = u[p];
         ga.xl = P->y;
         ga.xo = P->x;
-        ga.coef = 2.0 * c.inv_cmax * gs->cy;
+        ga.coef = gscale * gs->cy;
         ga.out = gs->gy;
         HIP_TRY(launch_plan_grad(prec, ga, c.st));
     }
@@ -2352,8 +2363,9 @@ int check_divergence(const ss_problem* P, const ss_options* O) {
     int rc = check_args(P, O, false);
     if (rc != SS_OK) return rc;
     if (isfinite(O->lambda)) return fail(SS_E_INVALID_ARG, "the divergence is built from OT terms");
-    if (O->cost != SS_COST_SQEUCLID)
-        return fail(SS_E_INVALID_ARG, "the divergence needs the unnormalised squared Euclidean cost");
+    if (O->cost != SS_COST_SQEUCLID && O->cost != SS_COST_EUCLID)
+        return fail(SS_E_INVALID_ARG,
+                    "the divergence needs an unnormalised cost (SS_COST_EUCLID or SS_COST_SQEUCLID)");
     // the self terms are n x n and m x m problems with the same options
     const ss_problem pxx = {P->n, P->n, P->d, P->problem_index, P->x, P->x, P->a, P->a};
     const ss_problem pyy = {P->m, P->m, P->d, P->problem_index, P->y, P->y, P->b, P->b};

@@ -105,9 +105,11 @@ __device__ __forceinline__ double sqdist(const double* __restrict__ xi, const do
 // -2 log cos(z), z = sqrt(c) * w, w = 1 / (2 eta), and +inf (K = 0) where
 // z >= pi/2.
 constexpr int kCostWfr = 2;
+constexpr int kCostEuclid = 3;
 constexpr double kHalfPi = 1.5707963267948966;
 
 __device__ __forceinline__ double cost_value(double c, int kind, double scale, double w) {
+    if (kind == kCostEuclid) return sqrt(c);
     if (kind != kCostWfr) return c * scale;
     const double z = sqrt(c) * w;
     return z >= kHalfPi ? INFINITY : -2.0 * log(cos(z));
@@ -116,6 +118,7 @@ __device__ __forceinline__ double cost_value(double c, int kind, double scale, d
 // cost_value with the specified logarithm and cosine (elemfn.hpp): the form
 // used where the cost decides a sampled entry or its stored value.
 __device__ __forceinline__ double cost_spec(double c, int kind, double scale, double w) {
+    if (kind == kCostEuclid) return sqrt(c);  // correctly rounded
     if (kind != kCostWfr) return c * scale;
     const double z = sqrt(c) * w;
     return z >= kHalfPi ? INFINITY : -2.0 * log_spec(cos_spec(z));

@@ -325,6 +325,7 @@ struct GradArgs {
     const double* xl;     // coordinates of the line side
     const double* xo;     // coordinates of the other side
     int d;
+    int euclid;           // 1: C = |x - y| (entries weighted by 1 / |x - y|)
     double coef;
     double* out;
 };

@@ -86,42 +86,125 @@ __device__ __forceinline__ void opp_feature(const MlpArgs& A, const WSide& S, in
 }
 
 // ---------------------------------------------------------------- inputs
-// C_s = max |x_i - y_j|^2 per problem (FP32, a feature scale): block (k, c)
-// scans rows [64 c, 64 c + 64) of problem k (staged in LDS) against all its
-// columns (each loaded once by one thread); the
-// maximum is order-free, so one atomic max per block (non-negative floats
-// order like their bit patterns) gives the same value in any order.
-constexpr int kPrepRows = 64;
+// C_s = max |x_i - y_j|^2 per problem (FP32, a feature scale), one block of
+// 1024 threads per problem, exact with pruning: with c the centre of the
+// bounding box of all points, R = max_j |y_j - c| and r_i = |x_i - c|, every
+// pair of row i has |x_i - y_j| <= r_i + R.  The row with the largest r_i
+// gives a lower bound L (its exact maximum); only rows with
+// (r_i + R)^2 (1 + 2^-16) >= L can hold a larger pair (the margin covers the
+// FP32 rounding of the bounds and of the pair distances), and they are
+// scanned exactly.  Pair distances are formed as in a full scan,
+// (d0 d0 + d1 d1) + d2 d2 from FP32 coordinates, and the maximum is
+// order-free, so the result equals the full scan's.
+constexpr int kCmaxThreads = 1024;
 
-__global__ __launch_bounds__(256) void k_ws_cmax(MlpArgs A, int chunks) {
-    __shared__ float smax[4];
-    __shared__ float xs[kPrepRows][3];
-    const int k = blockIdx.x / chunks, c = blockIdx.x % chunks;
+__device__ __forceinline__ float ws_d2(float a0, float a1, float a2, float b0, float b1,
+                                       float b2) {
+    const float d0 = a0 - b0, d1 = a1 - b1, d2 = a2 - b2;
+    return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
+__device__ __forceinline__ float block_max_f(float v, float* sh) {
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float r = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmaxf(r, sh[w]);
+    return r;
+}
+
+__global__ __launch_bounds__(kCmaxThreads) void k_ws_cmax(MlpArgs A) {
+    __shared__ float sh[16];
+    __shared__ float rx[kBatchMaxSide];
+    __shared__ float xsurv[kBatchMaxSide][3];
+    __shared__ int nrows;
+    const int k = blockIdx.x, t = threadIdx.x;
     const WSide S = A.sides[2 * k];
     const int64_t n = S.npts, m = S.nopp;
     const double* x = A.x + 3 * S.pts_off;
     const double* y = A.y + 3 * S.opp_off;
-    const int64_t i0 = (int64_t)c * kPrepRows;
-    if (i0 >= n) return;  // the whole block
-    const int nr = (int)(n - i0 < kPrepRows ? n - i0 : kPrepRows);
-    // the block's rows in LDS; each column is loaded once and meets every row
-    if (threadIdx.x < nr * 3) xs[threadIdx.x / 3][threadIdx.x % 3] = (float)x[3 * i0 + threadIdx.x];
-    __syncthreads();
-    float mx = 0.0f;
-    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
-        const float y0 = (float)y[3 * j], y1 = (float)y[3 * j + 1], y2 = (float)y[3 * j + 2];
-        for (int r = 0; r < nr; ++r) {
-            const float d0 = xs[r][0] - y0, d1 = xs[r][1] - y1, d2 = xs[r][2] - y2;
-            mx = fmaxf(mx, d0 * d0 + d1 * d1 + d2 * d2);
+    // bounding box of x and y (min and max are order-free)
+    float c[3];
+    for (int d = 0; d < 3; ++d) {
+        float lo = INFINITY, hi = -INFINITY;
+        for (int64_t i = t; i < n; i += blockDim.x) {
+            const float v = (float)x[3 * i + d];
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+        for (int64_t j = t; j < m; j += blockDim.x) {
+            const float v = (float)y[3 * j + d];
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+        hi = block_max_f(hi, sh);
+        lo = -block_max_f(-lo, sh);
+        c[d] = 0.5f * (lo + hi);
+    }
+    float ry = 0.0f;
+    for (int64_t j = t; j < m; j += blockDim.x)
+        ry = fmaxf(ry, ws_d2((float)y[3 * j], (float)y[3 * j + 1], (float)y[3 * j + 2], c[0], c[1],
+                             c[2]));
+    const float R = sqrtf(block_max_f(ry, sh));
+    float best = -1.0f;
+    int besti = 0;
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        const float r = sqrtf(ws_d2((float)x[3 * i], (float)x[3 * i + 1], (float)x[3 * i + 2], c[0],
+                                    c[1], c[2]));
+        rx[i] = r;
+        if (r > best) {
+            best = r;
+            besti = (int)i;
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = mx;
+    // the row of the largest r_i (any of the largest: the bound only needs one)
+    const float bmax = block_max_f(best, sh);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const float b = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
-        atomicMax((unsigned int*)(A.xform + 4 * k + 3), __float_as_uint(b));
+    if (t == 0) nrows = n;
+    __syncthreads();
+    if (best == bmax) atomicMin(&nrows, besti);
+    __syncthreads();
+    const int64_t istar = nrows;
+    const float a0 = (float)x[3 * istar], a1 = (float)x[3 * istar + 1], a2 = (float)x[3 * istar + 2];
+    float lm = 0.0f;
+    for (int64_t j = t; j < m; j += blockDim.x)
+        lm = fmaxf(lm, ws_d2(a0, a1, a2, (float)y[3 * j], (float)y[3 * j + 1], (float)y[3 * j + 2]));
+    const float L = block_max_f(lm, sh);
+    // rows that may hold a larger pair (list order is free: the maximum is)
+    __syncthreads();
+    if (t == 0) nrows = 0;
+    __syncthreads();
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        const float ub = (rx[i] + R) * (rx[i] + R) * (1.0f + 0x1p-16f);
+        if (ub >= L && i != istar) {
+            const int q = atomicAdd(&nrows, 1);
+            xsurv[q][0] = (float)x[3 * i];
+            xsurv[q][1] = (float)x[3 * i + 1];
+            xsurv[q][2] = (float)x[3 * i + 2];
+        }
     }
+    __syncthreads();
+    const int nr = nrows;
+    // each thread's columns in registers, the surviving rows from LDS
+    constexpr int CPT = kBatchMaxSide / kCmaxThreads;
+    float b[CPT][3];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int64_t j = t + (int64_t)u * blockDim.x;
+        const int64_t jj = j < m ? j : m - 1;  // past the end: repeats column m - 1
+        b[u][0] = (float)y[3 * jj];
+        b[u][1] = (float)y[3 * jj + 1];
+        b[u][2] = (float)y[3 * jj + 2];
+    }
+    float mx = L;
+    for (int q = 0; q < nr; ++q) {
+        const float a0 = xsurv[q][0], a1 = xsurv[q][1], a2 = xsurv[q][2];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) mx = fmaxf(mx, ws_d2(a0, a1, a2, b[u][0], b[u][1], b[u][2]));
+    }
+    mx = block_max_f(mx, sh);
+    if (t == 0) A.xform[4 * k + 3] = mx;
 }
 
 // One block per problem: the mean of all its points (fixed order) and the
@@ -152,8 +235,12 @@ __global__ __launch_bounds__(256) void k_ws_prep(MlpArgs A) {
 }
 
 // ---------------------------------------------------------------- embedding
+// Opposite points per LDS stage of the embedding.
+constexpr int kEmbChunk = 1024;
+
 __global__ __launch_bounds__(256) void k_ws_embed(MlpArgs A) {
     __shared__ float e_s[kH];
+    __shared__ float4 fs[kEmbChunk];
     const int s = blockIdx.x, t = threadIdx.x;
     const WSide S = A.sides[s];
     const __bf16* wb = (const __bf16*)A.wbf;
@@ -163,14 +250,27 @@ __global__ __launch_bounds__(256) void k_ws_embed(MlpArgs A) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) pw[c] = bf(wb, OFF_P + 4 * t + c);
     float acc = 0.0f;
+    // the opposite points' features are formed once per stage (not once per
+    // hidden unit) and read from LDS by every unit, in point order
+    for (int64_t j0 = 0; j0 < S.nopp; j0 += kEmbChunk) {
+        const int cnt = (int)(S.nopp - j0 < kEmbChunk ? S.nopp - j0 : kEmbChunk);
+        __syncthreads();  // the previous stage is read
+        for (int q = t; q < cnt; q += blockDim.x) {
+            float f[4];
+            opp_feature(A, S, j0 + q, f);
+            fs[q] = make_float4(f[0], f[1], f[2], f[3]);
+        }
+        __syncthreads();
 #pragma unroll 4
-    for (int64_t j = 0; j < S.nopp; ++j) {
-        float f[4];
-        opp_feature(A, S, j, f);
-        float z = pb;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) z = fmaf(pw[c], f[c], z);
-        acc += fmaxf(z, 0.0f);
+        for (int q = 0; q < cnt; ++q) {
+            const float4 f = fs[q];
+            float z = pb;
+            z = fmaf(pw[0], f.x, z);
+            z = fmaf(pw[1], f.y, z);
+            z = fmaf(pw[2], f.z, z);
+            z = fmaf(pw[3], f.w, z);
+            acc += fmaxf(z, 0.0f);
+        }
     }
     const float e = acc / (float)S.nopp;
     e_s[t] = e;
@@ -399,6 +499,126 @@ __global__ __launch_bounds__(256) void k_ws_head(MlpArgs A) {
     }
 }
 
+// Forward head for prediction: the same arithmetic as k_ws_head<false>, with
+// W2 held in registers instead of LDS.  Wave wv owns output columns
+// [64 wv, 64 wv + 64); its B fragments of W2 (4 column tiles x 8 k-steps of
+// 8 BF16 each, 128 VGPRs) are loaded once per block, so a 16-point tile
+// reads only its h1 rows from LDS and the matrix cores, not LDS bandwidth,
+// bound the tile (32 MFMA 16x16x32 per wave).  A block takes a contiguous
+// range of tiles, so the owning side is found once and then advanced, and
+// the next tile's coordinates are loaded while the current one computes.
+__global__ __launch_bounds__(256, 2) void k_ws_head_fwd(MlpArgs A) {
+    __shared__ __align__(16) __bf16 h1s[kTile * kPad];
+    __shared__ float xs[kTile][3];
+    __shared__ float psum[4][kTile];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const __bf16* wb = (const __bf16*)A.wbf;
+    const int64_t t0 = A.ntiles * blockIdx.x / gridDim.x;
+    const int64_t t1 = A.ntiles * (blockIdx.x + 1) / gridDim.x;
+    if (t0 >= t1) return;
+    bf16x8 bw[4][kH / 32];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int n = 64 * wv + 16 * ct + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < kH / 32; ++ks)
+            bw[ct][ks] = *(const bf16x8*)(wb + OFF_W2 + n * kH + 32 * ks + 8 * (lane >> 4));
+    }
+    float c2v[4], w3v[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int n = 64 * wv + 16 * ct + (lane & 15);
+        c2v[ct] = bf(wb, OFF_c2 + n);
+        w3v[ct] = bf(wb, OFF_w3 + n);
+    }
+    const float w1t[3] = {bf(wb, OFF_W1 + 3 * tid), bf(wb, OFF_W1 + 3 * tid + 1),
+                          bf(wb, OFF_W1 + 3 * tid + 2)};
+    const float c3 = bf(wb, OFF_c3);
+    // the side of the first tile
+    int lo = 0, hi = A.nsides - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.sides[mid].tile0 <= t0) lo = mid; else hi = mid - 1;
+    }
+    WSide S = A.sides[lo];
+    float g = A.gvec[(int64_t)lo * kH + tid];
+    // coordinate (row tid / 3, axis tid % 3) of a tile, loaded one tile ahead
+    auto coord = [&](int64_t tile, const WSide& Sx) -> float {
+        const int64_t i0 = (tile - Sx.tile0) * kTile;
+        const int r = tid / 3, c = tid % 3;
+        if (tid >= kTile * 3 || i0 + r >= Sx.npts) return 0.0f;
+        const float* xf = A.xform + 4 * Sx.prob;
+        return ((float)side_pts(A, Sx)[3 * (Sx.pts_off + i0 + r) + c] - xf[c]) * xf[3];
+    };
+    float xnext = coord(t0, S);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t i0 = (tile - S.tile0) * kTile;
+        const int nrow = (int)(S.npts - i0 < kTile ? S.npts - i0 : kTile);
+        __syncthreads();  // the previous tile's h1s and psum are read
+        if (tid < kTile * 3) xs[tid / 3][tid % 3] = xnext;
+        __syncthreads();
+        for (int r = 0; r < kTile; ++r) {
+            float z1 = g;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) z1 = fmaf(w1t[c], xs[r][c], z1);
+            h1s[r * kPad + tid] = (__bf16)(r < nrow ? fmaxf(z1, 0.0f) : 0.0f);
+        }
+        // the next tile's side and coordinates, in flight during the products
+        WSide Sn = S;
+        int lon = lo;
+        if (tile + 1 < t1) {
+            while (lon + 1 < A.nsides && A.sides[lon + 1].tile0 <= tile + 1) ++lon;
+            if (lon != lo) Sn = A.sides[lon];
+            xnext = coord(tile + 1, Sn);
+        }
+        __syncthreads();
+        floatx4 acc[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kH / 32; ++ks) {
+            const bf16x8 a = *(const bf16x8*)(h1s + (lane & 15) * kPad + 32 * ks + 8 * (lane >> 4));
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[ct][ks], acc[ct], 0, 0, 0);
+        }
+        float rowp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rowp[r] = fmaf(fmaxf(acc[ct][r] + c2v[ct], 0.0f), w3v[ct], rowp[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float v = rowp[r];
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 4, 64);
+            v += __shfl_xor(v, 8, 64);
+            rowp[r] = v;
+        }
+        if ((lane & 15) == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) psum[wv][4 * (lane >> 4) + r] = rowp[r];
+        }
+        __syncthreads();
+        if (tid < nrow) {
+            const float psi = ((psum[0][tid] + psum[1][tid]) + (psum[2][tid] + psum[3][tid])) + c3;
+            A.psi[S.pt0 + i0 + tid] = psi;
+            if (A.out_u || A.out_v) {
+                double* out = S.which == 0 ? A.out_u : A.out_v;
+                const double* w = S.which == 0 ? A.a : A.b;
+                if (out) out[S.pts_off + i0 + tid] = log(w[S.pts_off + i0 + tid]) + (double)psi;
+            }
+        }
+        if (lon != lo) {
+            lo = lon;
+            S = Sn;
+            g = A.gvec[(int64_t)lo * kH + tid];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- centring
 __global__ __launch_bounds__(256) void k_ws_centre(MlpArgs A) {
     __shared__ double sh[16];
@@ -617,14 +837,12 @@ hipError_t launch_mlp_predict(const MlpArgs& a, hipStream_t st) {
     const int nprob = a.nsides / 2;
     hipError_t e = launch_fill_u32((uint32_t*)a.xform, (int64_t)nprob * 4, 0u, st);
     if (e != hipSuccess) return e;
-    if (a.cost == 0) {
-        const int chunks = (kBatchMaxSide + kPrepRows - 1) / kPrepRows;
-        hipLaunchKernelGGL(k_ws_cmax, dim3(nprob * chunks), dim3(256), 0, st, a, chunks);
-    }
+    if (a.cost == 0) hipLaunchKernelGGL(k_ws_cmax, dim3(nprob), dim3(kCmaxThreads), 0, st, a);
     hipLaunchKernelGGL(k_ws_prep, dim3(nprob), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_ws_embed, dim3(a.nsides), dim3(256), 0, st, a);
-    const int grid = a.ntiles < a.nblk ? (int)a.ntiles : a.nblk;
-    hipLaunchKernelGGL(k_ws_head<false>, dim3(grid), dim3(256), kHeadLds, st, a);
+    const int64_t grid2 = 2 * (int64_t)a.nblk;  // two blocks per compute unit
+    const int grid = a.ntiles < grid2 ? (int)a.ntiles : (int)grid2;
+    hipLaunchKernelGGL(k_ws_head_fwd, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -131,7 +131,9 @@ static void run_obj_d(int precision, const ObjArgs& a, hipStream_t st) {
 // Envelope gradient of the sparse problem's value (the divergence of the
 // generative-modelling section): 16 lanes per line stride its entries, T~ as
 // in the estimate, a fixed xor tree per coordinate, then one read-modify-write
-// of the line's d outputs (lines are disjoint, launches on one stream).
+// of the line's d outputs (lines are disjoint, launches on one stream).  With
+// the Euclidean cost an entry's term is weighted by 1 / |x_i - y_j| (0 where
+// the points coincide).
 template <int PREC, int D>
 __global__ __launch_bounds__(256) void k_plan_grad(GradArgs A) {
     const int tid = threadIdx.x, sub = tid % kObjLanes;
@@ -148,9 +150,18 @@ __global__ __launch_bounds__(256) void k_plan_grad(GradArgs A) {
         for (int k = 0; k < D; ++k) acc[k] = 0.0;
         for (int64_t e = k0 + sub; e < k1; e += kObjLanes) {
             const int64_t o = A.idx[e];
-            const double t = plan_entry<PREC>(yl, ylog, A.val, e, A.zs, o);
+            double t = plan_entry<PREC>(yl, ylog, A.val, e, A.zs, o);
+            double df[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) acc[k] += t * (xl[k] - A.xo[o * D + k]);
+            for (int k = 0; k < D; ++k) df[k] = xl[k] - A.xo[o * D + k];
+            if (A.euclid) {
+                double q = df[0] * df[0];
+#pragma unroll
+                for (int k = 1; k < D; ++k) q = q + df[k] * df[k];
+                t = q > 0.0 ? t / sqrt(q) : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] += t * df[k];
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -162,7 +173,15 @@ __global__ __launch_bounds__(256) void k_plan_grad(GradArgs A) {
             double acc = 0.0;
             for (int64_t e = k0 + sub; e < k1; e += kObjLanes) {
                 const int64_t o = A.idx[e];
-                const double t = plan_entry<PREC>(yl, ylog, A.val, e, A.zs, o);
+                double t = plan_entry<PREC>(yl, ylog, A.val, e, A.zs, o);
+                if (A.euclid) {
+                    double q = 0.0;
+                    for (int kk = 0; kk < d; ++kk) {
+                        const double u = xl[kk] - A.xo[o * d + kk];
+                        q = q + u * u;
+                    }
+                    t = q > 0.0 ? t / sqrt(q) : 0.0;
+                }
                 acc += t * (xl[k] - A.xo[o * d + k]);
             }
             const double g = group_sum<kObjLanes>(acc);

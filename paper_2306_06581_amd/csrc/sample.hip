@@ -1149,7 +1149,9 @@ __global__ __launch_bounds__(256) void k_fill_val(ProbParams pp, const double* _
     const double kappa = UOT ? pp.shrink_w * (pp.s / stats[ST_Z]) : 0.0;
     ProbParams lp = pp;
     if constexpr (!WFR)
-        lp.cost = pp.cost == SS_COST_SQEUCLID ? SS_COST_SQEUCLID : SS_COST_SQEUCLID_MAXNORM;
+        lp.cost = pp.cost == SS_COST_SQEUCLID ? SS_COST_SQEUCLID
+                  : pp.cost == SS_COST_EUCLID ? SS_COST_EUCLID
+                                              : SS_COST_SQEUCLID_MAXNORM;
     const int64_t e0 = ptr[line];
     const int64_t e1 = ptr[line + 1] < cap ? ptr[line + 1] : cap;
     for (int64_t e = e0 + lane; e < e1; e += 2 * kWave) {

@@ -26,7 +26,7 @@ SS_E_EMPTY = -5
 SS_E_CAPACITY = -6
 
 PRECISION = {"f64": 0, "f32": 1, "f32_log": 2}
-COST = {"maxnorm": 0, "plain": 1, "wfr": 2}
+COST = {"maxnorm": 0, "plain": 1, "wfr": 2, "euclid": 3}
 STOP = {"marginal": 0, "delta": 1}
 EMPTY = {"auto": 0, "renormalize": 1, "zero": 2, "fail": 3}
 

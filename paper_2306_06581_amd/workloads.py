@@ -41,7 +41,9 @@ takes an explicit ``n`` so tests can use small or ragged shapes):
 * ``latent_pair``  -- the Sinkhorn-divergence regulariser of the generative-
   modelling section: a batch of n latent codes in R^d (a fixed non-Gaussian
   warp of Gaussian draws, standing in for encoder outputs) against n draws of
-  the standard Gaussian prior, uniform weights, eps = 0.01, s = 10 s0(n).
+  the standard Gaussian prior, uniform weights, eps = 0.01 (the section's
+  value; the default, which callers may override), s = 10 s0(n).  The cost
+  (the section's Euclidean distance, or its square) is the solver's option.
 """
 from __future__ import annotations
 

@@ -92,3 +92,28 @@ def test_envelope_gradient_of_the_sketched_divergence(which, seed):
     assert all(t.sinkhorn.converged for t in (r.xy, r.xx, r.yy))
     assert r.xy.nnz < 40 * 36
     _fd_check(opt, x, a, y, b, which, "value_sparse", 1e-5)
+
+
+@pytest.mark.parametrize("which", ["x", "y"])
+def test_envelope_gradient_with_the_euclidean_cost(which):
+    # the section's distance between samples, C = |x - y|: the gradient term
+    # of an entry is T~ (x_i - y_j) / |x_i - y_j|; checked against finite
+    # differences of independent solves, dense (every p* = 1) and sketched
+    x, a, y, b = _measures(20, 18, 3, 9)
+    full = dict(FULL, cost="euclid")
+    _fd_check(O.Options(**full), x, a, y, b, which, "value", 1e-6)
+    opt = O.Options(eps=0.4, s=0.5 * 20 * 18, shrink=0.5, cost="euclid", tol=1e-13,
+                    max_iter=50000, seed=2)
+    r = D.sinkhorn_divergence(x, a, y, b, opt)
+    assert all(t.sinkhorn.converged for t in (r.xy, r.xx, r.yy)) and r.xy.nnz < 20 * 18
+    _fd_check(opt, x, a, y, b, which, "value_sparse", 1e-5)
+
+
+def test_euclidean_cost_is_the_distance():
+    # C = sqrt of the squared distance, with the self term's zero on the diagonal
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((7, 4))
+    c = O.cost_from_sq(O.sq_dist(x, x), "euclid", 1.0, 1.0)
+    ref = np.linalg.norm(x[:, None, :] - x[None, :, :], axis=-1)
+    np.testing.assert_allclose(c, ref, rtol=4e-16, atol=0)
+    assert np.all(np.diag(c) == 0.0)
