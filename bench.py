@@ -614,6 +614,11 @@ def cpu_baseline(p, gpu_iters: int, precision_log: bool, z_gpu: float, cmax_gpu:
     return out
 
 
+def progress(msg: str) -> None:
+    """A line on stderr as each section ends (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -768,26 +773,35 @@ def main():
                             "spar_sink_rel_err_vs_dense": rel(r.estimate),
                             "spar_sink_sparse_objective_rel_err_vs_dense":
                                 rel(r.sparse_objective)}
+    progress(f"headline {ms_step:.3f} ms per solve")
     if not args.no_batched:
         out["batched"] = batched_bench(args.batch_count, args.steps)
+        progress("batched")
     if args.warmstart_train > 0:
         out["warmstart"] = warmstart_bench(args.warmstart_train, args.batch_count)
+        progress("warmstart")
     if not args.no_ibp:
         out["ibp"] = ibp_bench(args.ibp_n, args.steps, not args.no_cpu)
+        progress("ibp")
     if not args.no_wfr:
         out["wfr"] = wfr_bench(args.wfr_n, args.steps, not args.no_dense)
+        progress("wfr")
     if not args.no_divergence:
         out["divergence"] = divergence_bench(args.divergence_n, args.steps, not args.no_cpu)
+        progress("divergence")
     if not args.no_eps_small:
         out["eps_small"] = eps_small_bench(args.n, args.steps, not args.no_dense)
+        progress("eps_small")
     if not args.no_hbm:
         out["hbm_resident"] = hbm_bench(args.steps)
+        progress("hbm_resident")
         # the same kernel where its data cannot stay in the Infinity Cache
         out["roofline_hbm_resident"] = dict(
             out["hbm_resident"]["uot_mix3_n65536_s32"].get("roofline", {}),
             workload=out["hbm_resident"]["uot_mix3_n65536_s32"]["workload"])
     if not args.no_ot_scale:
         out["ot_scale"] = ot_scale_bench(args.steps, not args.no_dense)
+        progress("ot_scale")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, r.iters, args.precision == "f32_log", r.z_norm,
                                            r.cmax, out.get("dense_iters"))
