@@ -1300,9 +1300,9 @@ int batch_start(BCtx& c, const ss_batch* B, const ss_options* O, void* ws, size_
 
 // ------------------------------------------------------------------ warm start
 struct WLayout {
-    size_t sides, xform, emb, gvec, psi, dpsi, h1g, dz2g, dgp, blkp, w2p, sidep, dgs, grad, loss;
+    size_t sides, tiles, tpts, tlw, emb_side, embp, xform, emb, gvec, psi, dpsi, h1g, dz2g, dgp, blkp, w2p, sidep, dgs, grad, loss;
     size_t total;
-    int nsides, nblk, nchunk;
+    int nsides, nblk, nchunk, nemb;
     int64_t ntiles, npts;
 };
 
@@ -1323,7 +1323,7 @@ constexpr int kWsTile = 16, kWsChunk = 2048, kWsH = 256;
 
 void ws_sides(const ss_batch* B, std::vector<WSide>* out) {
     out->clear();
-    int64_t ro = 0, co = 0, tile = 0, pt = 0;
+    int64_t ro = 0, co = 0, tile = 0, pt = 0, emb = 0;
     for (int k = 0; k < B->count; ++k) {
         for (int side = 0; side < 2; ++side) {
             WSide S;
@@ -1336,6 +1336,10 @@ void ws_sides(const ss_batch* B, std::vector<WSide>* out) {
             S.tile0 = tile;
             S.ntiles = (S.npts + kWsTile - 1) / kWsTile;
             S.pt0 = pt;
+            S.emb0 = emb;
+            S.nemb = (int32_t)((S.nopp + kWsEmbPart - 1) / kWsEmbPart);
+            S.pad = 0;
+            emb += S.nemb;
             tile += S.ntiles;
             pt += S.npts;
             out->push_back(S);
@@ -1352,6 +1356,7 @@ WLayout wplan(const ss_batch* B) {
     L.nsides = (int)sides.size();
     L.ntiles = sides.back().tile0 + sides.back().ntiles;
     L.npts = sides.back().pt0 + sides.back().npts;
+    L.nemb = (int)(sides.back().emb0 + sides.back().nemb);
     L.nblk = kMaxLoopBlocks;  // bound; the launch uses the compute-unit count
     L.nchunk = (int)((L.npts + kWsChunk - 1) / kWsChunk);
     size_t off = 0;
@@ -1361,6 +1366,11 @@ WLayout wplan(const ss_batch* B) {
         return o;
     };
     L.sides = take(sides.size() * sizeof(WSide));
+    L.tiles = take((size_t)L.ntiles * sizeof(WTile));
+    L.tpts = take((size_t)L.ntiles * kWsTile * 4 * 4);
+    L.tlw = take((size_t)L.ntiles * kWsTile * 8);
+    L.emb_side = take((size_t)L.nemb * 4);
+    L.embp = take((size_t)L.nemb * kWsH * 4);
     L.xform = take((size_t)B->count * 4 * 4);
     L.emb = take((size_t)L.nsides * kWsH * 4);
     L.gvec = take((size_t)L.nsides * kWsH * 4);
@@ -1399,6 +1409,12 @@ int ws_args(const ss_mlp* M, const ss_batch* B, double eps, int cost, void* ws, 
     const int grid = mlp_head_grid();
     if (grid <= 0) return fail(SS_E_HIP, "no device");
     a->sides = at<WSide>(ws, L->sides);
+    a->tiles = at<WTile>(ws, L->tiles);
+    a->tpts = at<float>(ws, L->tpts);
+    a->tlw = at<double>(ws, L->tlw);
+    a->nemb = L->nemb;
+    a->emb_side = at<int32_t>(ws, L->emb_side);
+    a->embp = at<float>(ws, L->embp);
     a->nsides = L->nsides;
     a->ntiles = L->ntiles;
     a->npts = L->npts;

@@ -486,12 +486,34 @@ struct WSide {
     int64_t nopp, opp_off;   // opposite measure
     int64_t tile0, ntiles;   // head tiles of this side
     int64_t pt0;             // first position in the list of all sides' points
+    int64_t emb0;            // first embedding chunk (of kWsEmbPart opposite points)
+    int32_t nemb;            // embedding chunks
     int32_t which;           // 0: points from x / a (u side), 1: from y / b (v side)
     int32_t prob;            // problem index
+    int32_t pad;
+};
+
+// Opposite points per block of the embedding's partial sums.
+constexpr int kWsEmbPart = 512;
+
+// One 16-point head tile: where its points and outputs sit.
+struct WTile {
+    int64_t pt;              // first position in the list of all sides' points
+    int64_t row;             // first row in the side's concatenated point array
+    int32_t side;            // side index
+    int32_t nrow;            // points in the tile (16 except at a side's end)
+    int32_t which;           // as WSide::which
+    int32_t pad;
 };
 
 struct MlpArgs {
     const WSide* sides;
+    WTile* tiles;            // [tile]
+    int nemb;                // embedding chunks over all sides
+    int32_t* emb_side;       // [chunk]: its side
+    float* embp;             // [chunk][256]: partial ReLU sums of the embedding
+    float* tpts;             // [tile][16][4]: points in kernel units, 4th 0, tail 0
+    double* tlw;             // [tile][16]: log of the point's mass, tail 0
     int nsides;
     int64_t ntiles, npts;
     int nblk;                // head blocks (<= resident)

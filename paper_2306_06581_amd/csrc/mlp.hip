@@ -16,17 +16,21 @@
 // squared error mean_M (d - mean_M d)^2, d = psi - (log y* - log w), over the
 // points M with a finite target; the batch loss is the mean over all sides.
 //
-// Kernels (all sums in a fixed order; no atomics):
-//   k_ws_cmax       (problem, row chunk) blocks: max squared distance
+// Kernels (all sums in a fixed order; no atomics on values):
+//   k_ws_cmax       one block per problem: max squared distance (pruned)
 //   k_ws_prep       one block per problem: centre and kernel length
-//   k_ws_embed      one block per side: e, g
-//   k_ws_head<T>    persistent blocks over 16-point tiles of all sides.  W2
+//   k_ws_embed_part (side, chunk of opposite points) blocks: partial phi sums
+//                   on the FP32 matrix cores
+//   k_ws_embed      one block per side: e, g; the side's tile tables
+//   k_ws_head_fwd   forward head for prediction: both layers transposed on the
+//                   matrix cores, W2 in registers, loads a group ahead
+//   k_ws_head_train persistent blocks over 16-point tiles of all sides.  W2
 //                   stays in LDS (padded rows); h2 = ReLU(h1 W2^T + c2) on
-//                   MFMA 16x16x32 BF16.  Forward: psi (and log w + psi).
-//                   Training: recomputes the forward, dz2 = dpsi w3 [z2 > 0],
-//                   dh1 = dz2 W2 (MFMA, W2^T from global), dz1 = dh1 [h1 > 0];
-//                   per-block sums of dW1, dc2, dw3, dc3, per-tile sums of dg;
-//                   h1 and dz2 rows go to scratch for dW2.
+//                   MFMA 16x16x32 BF16.  Recomputes the forward,
+//                   dz2 = dpsi w3 [z2 > 0], dh1 = dz2 W2 (MFMA, W2^T from
+//                   global), dz1 = dh1 [h1 > 0]; per-block sums of dW1, dc2,
+//                   dw3, dc3, per-tile sums of dg; h1 and dz2 rows go to
+//                   scratch for dW2.
 //   k_ws_centre     one block per side: loss, dL/dpsi
 //   k_ws_dw2        dW2 = sum_i dz2_i^T h1_i: chunks of points, MFMA, partials
 //   k_ws_embed_bwd  one block per side: dg, de = U^T dg, dP, dp partials
@@ -213,6 +217,11 @@ __global__ __launch_bounds__(256) void k_ws_prep(MlpArgs A) {
     __shared__ double sh[16];
     const int k = blockIdx.x;
     const WSide S = A.sides[2 * k];
+    // the side of each embedding chunk of this problem's two sides
+    for (int h = 0; h < 2; ++h) {
+        const WSide& Sh = A.sides[2 * k + h];
+        for (int c = threadIdx.x; c < Sh.nemb; c += blockDim.x) A.emb_side[Sh.emb0 + c] = 2 * k + h;
+    }
     const int64_t n = S.npts, m = S.nopp;
     const double* x = A.x + 3 * S.pts_off;
     const double* y = A.y + 3 * S.opp_off;
@@ -235,61 +244,195 @@ __global__ __launch_bounds__(256) void k_ws_prep(MlpArgs A) {
 }
 
 // ---------------------------------------------------------------- embedding
-// Opposite points per LDS stage of the embedding.
-constexpr int kEmbChunk = 1024;
+// columns of U per LDS stage of g = U e + c1
+constexpr int kEmbUCols = 64;
 
+// Partial sums of phi over one chunk of kWsEmbPart opposite points of a side
+// (chunks keep the blocks' work equal whatever the sides' sizes).
+// phi_j = ReLU(P f_j + p) as (hidden unit) x (point) tiles on the FP32 MFMA
+// 16x16x4 (k = the 4 features): wave wv owns units [64 wv, 64 wv + 64);
+// A fragments P[unit][feature], the bias p as the accumulator input; lane
+// (lr, lg) of a product holds units 16 ut + 4 lg + r of point lr and sums
+// their ReLUs over its points; the 16 point classes are then added in class
+// order.
+__global__ __launch_bounds__(256, 4) void k_ws_embed_part(MlpArgs A) {
+    __shared__ __align__(16) float4 fs[kWsEmbPart];
+    __shared__ float red[16][kH];
+    const int c = blockIdx.x, t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6, lr = lane & 15, lg = lane >> 4;
+    const int s = A.emb_side[c];
+    const WSide S = A.sides[s];
+    const __bf16* wb = (const __bf16*)A.wbf;
+    const int64_t j0 = (c - S.emb0) * (int64_t)kWsEmbPart;
+    const int cnt = (int)(S.nopp - j0 < kWsEmbPart ? S.nopp - j0 : kWsEmbPart);
+    {
+        float f[kWsEmbPart / 256][4];
+#pragma unroll
+        for (int k = 0; k < kWsEmbPart / 256; ++k)
+            if (t + 256 * k < cnt) opp_feature(A, S, j0 + t + 256 * k, f[k]);
+#pragma unroll
+        for (int k = 0; k < kWsEmbPart / 256; ++k)
+            if (t + 256 * k < cnt) fs[t + 256 * k] = make_float4(f[k][0], f[k][1], f[k][2], f[k][3]);
+    }
+    float pa[4];
+    floatx4 pb[4], acc[4];
+#pragma unroll
+    for (int ut = 0; ut < 4; ++ut) {
+        const int u = 64 * wv + 16 * ut;
+        pa[ut] = bf(wb, OFF_P + 4 * (u + lr) + lg);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            pb[ut][r] = bf(wb, OFF_p + u + 4 * lg + r);
+            acc[ut][r] = 0.0f;
+        }
+    }
+    __syncthreads();
+    // two 16-point tiles per step: eight independent products; points past
+    // the chunk's end add zero
+    for (int p0 = 0; p0 < cnt; p0 += 32) {
+        float fb[2];
+        bool live[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            live[h] = p0 + 16 * h + lr < cnt;
+            fb[h] = ((const float*)fs)[4 * (p0 + 16 * h + lr) + lg];
+        }
+        floatx4 d[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int ut = 0; ut < 4; ++ut)
+                d[h][ut] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[ut], fb[h], pb[ut], 0, 0, 0);
+        if (p0 + 32 <= cnt) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int ut = 0; ut < 4; ++ut)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[ut][r] += fmaxf(d[h][ut][r], 0.0f);
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int ut = 0; ut < 4; ++ut)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc[ut][r] += live[h] ? fmaxf(d[h][ut][r], 0.0f) : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int ut = 0; ut < 4; ++ut)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[lr][64 * wv + 16 * ut + 4 * lg + r] = acc[ut][r];
+    __syncthreads();
+    float sum = 0.0f;
+    for (int q = 0; q < 16; ++q) sum += red[q][t];
+    A.embp[(int64_t)c * kH + t] = sum;
+}
+
+// One block per side: e = (chunk sums in chunk order) / m, g = U e + c1, and
+// the side's tile tables for the forward head.  Every loop issues its loads
+// together before using them (a side has at most 8 chunks and 4096 points).
 __global__ __launch_bounds__(256) void k_ws_embed(MlpArgs A) {
     __shared__ float e_s[kH];
-    __shared__ float4 fs[kEmbChunk];
+    __shared__ __align__(16) __bf16 us[kH][kEmbUCols + 8];
     const int s = blockIdx.x, t = threadIdx.x;
     const WSide S = A.sides[s];
     const __bf16* wb = (const __bf16*)A.wbf;
-    // unit t's weights in registers (phi_pre's arithmetic, in its order)
-    const float pb = bf(wb, OFF_p + t);
-    float pw[4];
+    constexpr int kMaxChunks = (kBatchMaxSide + kWsEmbPart - 1) / kWsEmbPart;
+    float ps[kMaxChunks];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) pw[c] = bf(wb, OFF_P + 4 * t + c);
-    float acc = 0.0f;
-    // the opposite points' features are formed once per stage (not once per
-    // hidden unit) and read from LDS by every unit, in point order
-    for (int64_t j0 = 0; j0 < S.nopp; j0 += kEmbChunk) {
-        const int cnt = (int)(S.nopp - j0 < kEmbChunk ? S.nopp - j0 : kEmbChunk);
-        __syncthreads();  // the previous stage is read
-        for (int q = t; q < cnt; q += blockDim.x) {
-            float f[4];
-            opp_feature(A, S, j0 + q, f);
-            fs[q] = make_float4(f[0], f[1], f[2], f[3]);
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int q = 0; q < cnt; ++q) {
-            const float4 f = fs[q];
-            float z = pb;
-            z = fmaf(pw[0], f.x, z);
-            z = fmaf(pw[1], f.y, z);
-            z = fmaf(pw[2], f.z, z);
-            z = fmaf(pw[3], f.w, z);
-            acc += fmaxf(z, 0.0f);
-        }
-    }
-    const float e = acc / (float)S.nopp;
+    for (int c = 0; c < kMaxChunks; ++c)
+        ps[c] = c < S.nemb ? A.embp[(S.emb0 + c) * kH + t] : 0.0f;
+    float sum = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c)
+        if (c < S.nemb) sum += ps[c];
+    const float e = sum / (float)S.nopp;
     e_s[t] = e;
     A.emb[(int64_t)s * kH + t] = e;
-    __syncthreads();
+    // g = U e + c1: U staged in LDS by column chunks (16-byte row pieces),
+    // each unit accumulating its row in column order
     float g = bf(wb, OFF_c1 + t);
-    for (int c = 0; c < kH; ++c) g = fmaf(bf(wb, OFF_U + t * kH + c), e_s[c], g);
+    constexpr int kPieces = kH * kEmbUCols / 8;  // 16-byte pieces per chunk
+    for (int c0 = 0; c0 < kH; c0 += kEmbUCols) {
+        bf16x8 pc[kPieces / 256];
+#pragma unroll
+        for (int k = 0; k < kPieces / 256; ++k) {
+            const int i = t + 256 * k, u = i / (kEmbUCols / 8), q = 8 * (i % (kEmbUCols / 8));
+            pc[k] = *(const bf16x8*)(wb + OFF_U + u * kH + c0 + q);
+        }
+        __syncthreads();  // e_s written / the previous chunk read
+#pragma unroll
+        for (int k = 0; k < kPieces / 256; ++k) {
+            const int i = t + 256 * k, u = i / (kEmbUCols / 8), q = 8 * (i % (kEmbUCols / 8));
+            *(bf16x8*)&us[u][q] = pc[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kEmbUCols; q += 8) {
+            const bf16x8 r = *(const bf16x8*)&us[t][q];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) g = fmaf((float)r[c], e_s[c0 + q + c], g);
+        }
+    }
     A.gvec[(int64_t)s * kH + t] = g;
+    // this side's own points in kernel units and the logs of their masses,
+    // tile-padded with zeros, and its tile records, for the forward head
+    // (the arithmetic of the head's coordinate transform, done once per point)
+    const float* xf = A.xform + 4 * S.prob;
+    const double* __restrict__ pts = side_pts(A, S) + 3 * S.pts_off;
+    const double* __restrict__ w = (S.which == 0 ? A.a : A.b) + S.pts_off;
+    float4* __restrict__ tp = (float4*)A.tpts + S.tile0 * kTile;
+    double* __restrict__ tl = A.tlw + S.tile0 * kTile;
+    const int npad = (int)(S.ntiles * kTile);
+    constexpr int kPer = 4;  // points per thread per round, loads first
+    for (int i0 = 0; i0 < npad; i0 += 256 * kPer) {
+        double q[kPer][4];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = i0 + t + 256 * k;
+            const bool live = i < S.npts;
+            q[k][0] = live ? pts[3 * i + 0] : 0.0;
+            q[k][1] = live ? pts[3 * i + 1] : 0.0;
+            q[k][2] = live ? pts[3 * i + 2] : 0.0;
+            q[k][3] = live ? w[i] : 1.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = i0 + t + 256 * k;
+            if (i >= npad) continue;
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            double lw = 0.0;
+            if (i < S.npts) {
+                v.x = ((float)q[k][0] - xf[0]) * xf[3];
+                v.y = ((float)q[k][1] - xf[1]) * xf[3];
+                v.z = ((float)q[k][2] - xf[2]) * xf[3];
+                lw = log(q[k][3]);
+            }
+            tp[i] = v;
+            tl[i] = lw;
+        }
+    }
+    for (int64_t k = t; k < S.ntiles; k += blockDim.x) {
+        WTile rec;
+        rec.pt = S.pt0 + k * kTile;
+        rec.row = S.pts_off + k * kTile;
+        rec.side = s;
+        rec.nrow = (int)(S.npts - k * kTile < kTile ? S.npts - k * kTile : kTile);
+        rec.which = S.which;
+        rec.pad = 0;
+        A.tiles[S.tile0 + k] = rec;
+    }
 }
 
 // ---------------------------------------------------------------- head
-template <bool TRAIN>
-__global__ __launch_bounds__(256) void k_ws_head(MlpArgs A) {
+__global__ __launch_bounds__(256) void k_ws_head_train(MlpArgs A) {
     extern __shared__ __align__(16) unsigned char dsm[];
     __bf16* w2s = (__bf16*)dsm;                 // [kH][kPad]  W2 rows (out n, in k)
     __bf16* h1s = w2s + kH * kPad;              // [kTile][kPad]
     __bf16* dz2s = h1s + kTile * kPad;          // [kTile][kPad] (training)
     __shared__ float xs[kTile][3];
-    __shared__ float psum[4][kTile];
     __shared__ float dps[kTile];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const __bf16* wb = (const __bf16*)A.wbf;
@@ -302,7 +445,6 @@ __global__ __launch_bounds__(256) void k_ws_head(MlpArgs A) {
     float bw1[3] = {0.f, 0.f, 0.f}, bc2 = 0.f, bw3 = 0.f, bc3 = 0.f;
     const float w1t[3] = {bf(wb, OFF_W1 + 3 * tid), bf(wb, OFF_W1 + 3 * tid + 1),
                           bf(wb, OFF_W1 + 3 * tid + 2)};
-    const float c3 = bf(wb, OFF_c3);
     __syncthreads();
     for (int64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
         // the side owning this tile
@@ -320,7 +462,7 @@ __global__ __launch_bounds__(256) void k_ws_head(MlpArgs A) {
             const float* xf = A.xform + 4 * S.prob;
             xs[r][c] = r < nrow ? ((float)z[3 * (S.pts_off + i0 + r) + c] - xf[c]) * xf[3] : 0.0f;
         }
-        if (TRAIN && tid < kTile) dps[tid] = tid < nrow ? A.dpsi[S.pt0 + i0 + tid] : 0.0f;
+        if (tid < kTile) dps[tid] = tid < nrow ? A.dpsi[S.pt0 + i0 + tid] : 0.0f;
         __syncthreads();
         // h1 rows (thread = hidden unit)
         const float g = A.gvec[(int64_t)lo * kH + tid];
@@ -346,46 +488,15 @@ __global__ __launch_bounds__(256) void k_ws_head(MlpArgs A) {
                 acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[ct], 0, 0, 0);
             }
         }
-        // h2 = ReLU(z2 + c2); psi partial sums over this wave's columns
-        float rowp[4] = {0.f, 0.f, 0.f, 0.f};
+        // h2 = ReLU(z2 + c2) (psi itself comes from the forward head)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
             const int n = 64 * wv + 16 * ct + (lane & 15);
-            const float c2 = bf(wb, OFF_c2 + n), w3 = bf(wb, OFF_w3 + n);
+            const float c2 = bf(wb, OFF_c2 + n);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float h2 = fmaxf(acc[ct][r] + c2, 0.0f);
-                acc[ct][r] = h2;
-                rowp[r] = fmaf(h2, w3, rowp[r]);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            float v = rowp[r];
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 2, 64);
-            v += __shfl_xor(v, 4, 64);
-            v += __shfl_xor(v, 8, 64);
-            rowp[r] = v;
-        }
-        if ((lane & 15) == 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) psum[wv][4 * (lane >> 4) + r] = rowp[r];
+            for (int r = 0; r < 4; ++r) acc[ct][r] = fmaxf(acc[ct][r] + c2, 0.0f);
         }
         __syncthreads();
-        if (!TRAIN) {
-            if (tid < nrow) {
-                const float psi = ((psum[0][tid] + psum[1][tid]) + (psum[2][tid] + psum[3][tid])) + c3;
-                A.psi[S.pt0 + i0 + tid] = psi;
-                if (A.out_u || A.out_v) {
-                    double* out = S.which == 0 ? A.out_u : A.out_v;
-                    const double* w = S.which == 0 ? A.a : A.b;
-                    if (out) out[S.pts_off + i0 + tid] = log(w[S.pts_off + i0 + tid]) + (double)psi;
-                }
-            }
-            __syncthreads();
-            continue;
-        }
         // ---- backward of the tile
         float gc2[4] = {0.f, 0.f, 0.f, 0.f}, gw3[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -488,134 +599,200 @@ __global__ __launch_bounds__(256) void k_ws_head(MlpArgs A) {
         }
         __syncthreads();
     }
-    if (TRAIN) {
-        float* part = A.blkp + (int64_t)blockIdx.x * kBlkPart;
-        part[3 * tid + 0] = bw1[0];
-        part[3 * tid + 1] = bw1[1];
-        part[3 * tid + 2] = bw1[2];
-        part[768 + tid] = bc2;
-        part[1024 + tid] = bw3;
-        if (tid == 0) part[1280] = bc3;
-    }
+    float* part = A.blkp + (int64_t)blockIdx.x * kBlkPart;
+    part[3 * tid + 0] = bw1[0];
+    part[3 * tid + 1] = bw1[1];
+    part[3 * tid + 2] = bw1[2];
+    part[768 + tid] = bc2;
+    part[1024 + tid] = bw3;
+    if (tid == 0) part[1280] = bc3;
 }
 
-// Forward head for prediction: the same arithmetic as k_ws_head<false>, with
-// W2 held in registers instead of LDS.  Wave wv owns output columns
-// [64 wv, 64 wv + 64); its B fragments of W2 (4 column tiles x 8 k-steps of
-// 8 BF16 each, 128 VGPRs) are loaded once per block, so a 16-point tile
-// reads only its h1 rows from LDS and the matrix cores, not LDS bandwidth,
-// bound the tile (32 MFMA 16x16x32 per wave).  A block takes a contiguous
-// range of tiles, so the owning side is found once and then advanced, and
-// the next tile's coordinates are loaded while the current one computes.
+// Forward head for prediction: the forward arithmetic of k_ws_head_train per point,
+// arranged for the matrix cores.  Both layers are computed transposed, as
+// (hidden unit) x (point) tiles, so that a lane's accumulators hold several
+// hidden units of one point and the output layer reduces in registers:
+//  * first layer: W1 [x; 0] on the FP32 MFMA 16x16x4 (k = 3 is the zero
+//    fourth coordinate), plus the side's bias g, ReLU, BF16 rows into LDS;
+//  * second layer: W2 h1 on MFMA 16x16x32 BF16 with FP32 accumulation.  Wave
+//    wv owns hidden units [64 wv, 64 wv + 64); its A fragments of W2 (4 unit
+//    tiles x 8 k-steps of 8 BF16, 128 VGPRs) are loaded once per block;
+//  * output: w3 . ReLU(h2 + c2) summed over a lane's 16 units, the 16 partial
+//    sums of a point (4 waves x 4 lane groups) added in a fixed order.
+// A block takes a contiguous range of 16-point tiles and works through it in
+// groups of kSubT tiles (the rows of a group may come from several sides:
+// only the first layer's bias belongs to a side).  Points come in kernel
+// units from the tile-padded table k_ws_embed writes, so every load of a
+// group has an address known a group ahead: the tile records two groups
+// ahead, the coordinates and biases one group ahead, all in flight while
+// the matrix cores work.
+constexpr int kHeadGroup = 2;  // tiles per group: 2 fits 256 VGPRs at two waves per SIMD
+
+template <int kSubT>
 __global__ __launch_bounds__(256, 2) void k_ws_head_fwd(MlpArgs A) {
-    __shared__ __align__(16) __bf16 h1s[kTile * kPad];
-    __shared__ float xs[kTile][3];
-    __shared__ float psum[4][kTile];
+    constexpr int kRows = kSubT * kTile;  // points of a group
+    __shared__ __align__(16) __bf16 h1s[kRows * kPad];
+    __shared__ __align__(16) float xs[2][kRows][4];
+    __shared__ __align__(16) float gl[2][kSubT][kH];
+    __shared__ __align__(16) float cw[2][kH];  // c2, w3
+    __shared__ float psum[4][4][kRows];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
     const __bf16* wb = (const __bf16*)A.wbf;
     const int64_t t0 = A.ntiles * blockIdx.x / gridDim.x;
     const int64_t t1 = A.ntiles * (blockIdx.x + 1) / gridDim.x;
     if (t0 >= t1) return;
     bf16x8 bw[4][kH / 32];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int n = 64 * wv + 16 * ct + (lane & 15);
+    for (int ut = 0; ut < 4; ++ut) {
+        const int u = 64 * wv + 16 * ut + lr;
 #pragma unroll
         for (int ks = 0; ks < kH / 32; ++ks)
-            bw[ct][ks] = *(const bf16x8*)(wb + OFF_W2 + n * kH + 32 * ks + 8 * (lane >> 4));
+            bw[ut][ks] = *(const bf16x8*)(wb + OFF_W2 + u * kH + 32 * ks + 8 * lg);
     }
-    float c2v[4], w3v[4];
+    // first-layer A fragments: W1[unit][k], k = lane group (k = 3 is zero)
+    float w1f[4];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int n = 64 * wv + 16 * ct + (lane & 15);
-        c2v[ct] = bf(wb, OFF_c2 + n);
-        w3v[ct] = bf(wb, OFF_w3 + n);
+    for (int ut = 0; ut < 4; ++ut) {
+        const int u = 64 * wv + 16 * ut + lr;
+        w1f[ut] = lg < 3 ? bf(wb, OFF_W1 + 3 * u + lg) : 0.0f;
     }
-    const float w1t[3] = {bf(wb, OFF_W1 + 3 * tid), bf(wb, OFF_W1 + 3 * tid + 1),
-                          bf(wb, OFF_W1 + 3 * tid + 2)};
+    cw[0][tid] = bf(wb, OFF_c2 + tid);
+    cw[1][tid] = bf(wb, OFF_w3 + tid);
     const float c3 = bf(wb, OFF_c3);
-    // the side of the first tile
-    int lo = 0, hi = A.nsides - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (A.sides[mid].tile0 <= t0) lo = mid; else hi = mid - 1;
-    }
-    WSide S = A.sides[lo];
-    float g = A.gvec[(int64_t)lo * kH + tid];
-    // coordinate (row tid / 3, axis tid % 3) of a tile, loaded one tile ahead
-    auto coord = [&](int64_t tile, const WSide& Sx) -> float {
-        const int64_t i0 = (tile - Sx.tile0) * kTile;
-        const int r = tid / 3, c = tid % 3;
-        if (tid >= kTile * 3 || i0 + r >= Sx.npts) return 0.0f;
-        const float* xf = A.xform + 4 * Sx.prob;
-        return ((float)side_pts(A, Sx)[3 * (Sx.pts_off + i0 + r) + c] - xf[c]) * xf[3];
+    const float* tpts = A.tpts;
+    // loads of group `tile`: its side indices (from the tile records), its
+    // coordinates (thread tid < 4 kRows: row tid / 4, axis tid % 4), its
+    // biases (unit tid) and its output records (thread tid < kRows); tiles
+    // past the block's range read as side 0 / zero
+    auto side_at = [&](int64_t tile) { return tile < t1 ? A.tiles[tile].side : 0; };
+    auto coord_at = [&](int64_t tile) {
+        return tid < 4 * kRows && tile * kTile * 4 + tid < t1 * kTile * 4
+                   ? tpts[tile * kTile * 4 + tid] : 0.0f;
     };
-    float xnext = coord(t0, S);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t i0 = (tile - S.tile0) * kTile;
-        const int nrow = (int)(S.npts - i0 < kTile ? S.npts - i0 : kTile);
-        __syncthreads();  // the previous tile's h1s and psum are read
-        if (tid < kTile * 3) xs[tid / 3][tid % 3] = xnext;
-        __syncthreads();
-        for (int r = 0; r < kTile; ++r) {
-            float z1 = g;
+    auto rec_at = [&](int64_t tile, WTile* r) {
+        if (tid < kRows && tile + tid / kTile < t1) *r = A.tiles[tile + tid / kTile];
+    };
+    int sideN[kSubT];
+    WTile recN;
+    recN.nrow = 0;
+    // the first group's coordinates and biases go to buffer 0
+    {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) z1 = fmaf(w1t[c], xs[r][c], z1);
-            h1s[r * kPad + tid] = (__bf16)(r < nrow ? fmaxf(z1, 0.0f) : 0.0f);
-        }
-        // the next tile's side and coordinates, in flight during the products
-        WSide Sn = S;
-        int lon = lo;
-        if (tile + 1 < t1) {
-            while (lon + 1 < A.nsides && A.sides[lon + 1].tile0 <= tile + 1) ++lon;
-            if (lon != lo) Sn = A.sides[lon];
-            xnext = coord(tile + 1, Sn);
-        }
-        __syncthreads();
-        floatx4 acc[4];
+        for (int q = 0; q < kSubT; ++q) sideN[q] = side_at(t0 + q);
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < kSubT; ++q) gl[0][q][tid] = A.gvec[(int64_t)sideN[q] * kH + tid];
+        if (tid < kRows * 4) xs[0][tid >> 2][tid & 3] = coord_at(t0);
+    }
+    rec_at(t0, &recN);
+    // the second group's sides, coordinates and biases are in flight
 #pragma unroll
-        for (int ks = 0; ks < kH / 32; ++ks) {
-            const bf16x8 a = *(const bf16x8*)(h1s + (lane & 15) * kPad + 32 * ks + 8 * (lane >> 4));
+    for (int q = 0; q < kSubT; ++q) sideN[q] = side_at(t0 + kSubT + q);
+    float gN[kSubT];
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[ct][ks], acc[ct], 0, 0, 0);
-        }
-        float rowp[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < kSubT; ++q) gN[q] = A.gvec[(int64_t)sideN[q] * kH + tid];
+    float xN = coord_at(t0 + kSubT);
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
+    for (int q = 0; q < kSubT; ++q) sideN[q] = side_at(t0 + 2 * kSubT + q);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t tile = t0; tile < t1; tile += kSubT) {
+        // this group's output record (loaded a group ago) and mass logs (read
+        // after the products); the next group's record
+        const WTile rec = recN;
+        const bool store = tid < kRows && tile + tid / kTile < t1;
+        const double lw = store ? A.tlw[tile * kTile + tid] : 0.0;
+        rec_at(tile + kSubT, &recN);
+        // first layer, bias g as the accumulator input: rows past a side's
+        // end come from zero coordinates and are never stored (points do not
+        // mix)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) rowp[r] = fmaf(fmaxf(acc[ct][r] + c2v[ct], 0.0f), w3v[ct], rowp[r]);
-        }
+        for (int pt = 0; pt < kSubT; ++pt) {
+            const float xb = xs[buf][kTile * pt + lr][lg];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            float v = rowp[r];
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 2, 64);
-            v += __shfl_xor(v, 4, 64);
-            v += __shfl_xor(v, 8, 64);
-            rowp[r] = v;
-        }
-        if ((lane & 15) == 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) psum[wv][4 * (lane >> 4) + r] = rowp[r];
-        }
-        __syncthreads();
-        if (tid < nrow) {
-            const float psi = ((psum[0][tid] + psum[1][tid]) + (psum[2][tid] + psum[3][tid])) + c3;
-            A.psi[S.pt0 + i0 + tid] = psi;
-            if (A.out_u || A.out_v) {
-                double* out = S.which == 0 ? A.out_u : A.out_v;
-                const double* w = S.which == 0 ? A.a : A.b;
-                if (out) out[S.pts_off + i0 + tid] = log(w[S.pts_off + i0 + tid]) + (double)psi;
+            for (int ut = 0; ut < 4; ++ut) {
+                const float4 g = *(const float4*)&gl[buf][pt][64 * wv + 16 * ut + 4 * lg];
+                const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    w1f[ut], xb, floatx4{g.x, g.y, g.z, g.w}, 0, 0, 0);
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                bf16x4 h;
+                h[0] = (__bf16)fmaxf(d[0], 0.0f);
+                h[1] = (__bf16)fmaxf(d[1], 0.0f);
+                h[2] = (__bf16)fmaxf(d[2], 0.0f);
+                h[3] = (__bf16)fmaxf(d[3], 0.0f);
+                *(bf16x4*)(h1s + (kTile * pt + lr) * kPad + 64 * wv + 16 * ut + 4 * lg) = h;
             }
         }
-        if (lon != lo) {
-            lo = lon;
-            S = Sn;
-            g = A.gvec[(int64_t)lo * kH + tid];
+        __syncthreads();
+        // the next group's coordinates and biases into the other buffer (its
+        // previous contents were read before the barrier above), the loads
+        // for the group after it issued
+        if (tid < kRows * 4) xs[buf ^ 1][tid >> 2][tid & 3] = xN;
+#pragma unroll
+        for (int q = 0; q < kSubT; ++q) gl[buf ^ 1][q][tid] = gN[q];
+#pragma unroll
+        for (int q = 0; q < kSubT; ++q) gN[q] = A.gvec[(int64_t)sideN[q] * kH + tid];
+        xN = coord_at(tile + 2 * kSubT);
+#pragma unroll
+        for (int q = 0; q < kSubT; ++q) sideN[q] = side_at(tile + 3 * kSubT + q);
+        // second layer, c2 as the accumulator input
+        floatx4 acc[kSubT][4];
+#pragma unroll
+        for (int ut = 0; ut < 4; ++ut) {
+            const float4 c2 = *(const float4*)&cw[0][64 * wv + 16 * ut + 4 * lg];
+#pragma unroll
+            for (int pt = 0; pt < kSubT; ++pt) acc[pt][ut] = floatx4{c2.x, c2.y, c2.z, c2.w};
         }
+#pragma unroll
+        for (int ks = 0; ks < kH / 32; ++ks) {
+            bf16x8 hb[kSubT];
+#pragma unroll
+            for (int pt = 0; pt < kSubT; ++pt)
+                hb[pt] = *(const bf16x8*)(h1s + (kTile * pt + lr) * kPad + 32 * ks + 8 * lg);
+#pragma unroll
+            for (int pt = 0; pt < kSubT; ++pt)
+#pragma unroll
+                for (int ut = 0; ut < 4; ++ut)
+                    acc[pt][ut] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[ut][ks], hb[pt],
+                                                                          acc[pt][ut], 0, 0, 0);
+        }
+        // lane (lr, lg) holds units 64 wv + 16 ut + 4 lg + r of point lr
+        float part[kSubT];
+#pragma unroll
+        for (int pt = 0; pt < kSubT; ++pt) part[pt] = 0.0f;
+#pragma unroll
+        for (int ut = 0; ut < 4; ++ut) {
+            const float4 w3 = *(const float4*)&cw[1][64 * wv + 16 * ut + 4 * lg];
+#pragma unroll
+            for (int pt = 0; pt < kSubT; ++pt) {
+                float s = part[pt];
+                s = fmaf(fmaxf(acc[pt][ut][0], 0.0f), w3.x, s);
+                s = fmaf(fmaxf(acc[pt][ut][1], 0.0f), w3.y, s);
+                s = fmaf(fmaxf(acc[pt][ut][2], 0.0f), w3.z, s);
+                s = fmaf(fmaxf(acc[pt][ut][3], 0.0f), w3.w, s);
+                part[pt] = s;
+            }
+        }
+#pragma unroll
+        for (int pt = 0; pt < kSubT; ++pt) psum[wv][lg][kTile * pt + lr] = part[pt];
+        __syncthreads();
+        // psum is next written after the next group's first barrier, which
+        // wave 0 reaches only after these reads
+        if (store && tid % kTile < rec.nrow) {
+            float psi = 0.0f;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float pw = (psum[w][0][tid] + psum[w][1][tid]) +
+                                 (psum[w][2][tid] + psum[w][3][tid]);
+                psi += pw;
+            }
+            psi += c3;
+            const int r = tid % kTile;
+            A.psi[rec.pt + r] = psi;
+            double* out = rec.which == 0 ? A.out_u : A.out_v;
+            if (out) out[rec.row + r] = lw + (double)psi;
+        }
+        buf ^= 1;
     }
 }
 
@@ -807,14 +984,9 @@ __global__ __launch_bounds__(256) void k_ws_adam(float* __restrict__ w, float* _
 constexpr size_t kHeadLds = (size_t)(kH + 2 * kTile) * kPad * 2;
 
 hipError_t mlp_init() {
-    static hipError_t status = [] {
-        hipError_t e = hipFuncSetAttribute((const void*)&k_ws_head<false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kHeadLds);
-        const hipError_t e2 = hipFuncSetAttribute((const void*)&k_ws_head<true>,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)kHeadLds);
-        return e != hipSuccess ? e : e2;
-    }();
+    static hipError_t status = hipFuncSetAttribute((const void*)&k_ws_head_train,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)kHeadLds);
     return status;
 }
 
@@ -839,10 +1011,11 @@ hipError_t launch_mlp_predict(const MlpArgs& a, hipStream_t st) {
     if (e != hipSuccess) return e;
     if (a.cost == 0) hipLaunchKernelGGL(k_ws_cmax, dim3(nprob), dim3(kCmaxThreads), 0, st, a);
     hipLaunchKernelGGL(k_ws_prep, dim3(nprob), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_ws_embed_part, dim3(a.nemb), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_ws_embed, dim3(a.nsides), dim3(256), 0, st, a);
     const int64_t grid2 = 2 * (int64_t)a.nblk;  // two blocks per compute unit
     const int grid = a.ntiles < grid2 ? (int)a.ntiles : (int)grid2;
-    hipLaunchKernelGGL(k_ws_head_fwd, dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_ws_head_fwd<kHeadGroup>, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -856,7 +1029,7 @@ hipError_t launch_mlp_grad(const MlpArgs& a, hipStream_t st) {
     // blocks past the tile count never run: their partials must read as zero
     e = launch_fill_u32((uint32_t*)a.blkp, (int64_t)a.nblk * kBlkPart, 0u, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ws_head<true>, dim3(b.nblk), dim3(256), kHeadLds, st, b);
+    hipLaunchKernelGGL(k_ws_head_train, dim3(b.nblk), dim3(256), kHeadLds, st, b);
     hipLaunchKernelGGL(k_ws_dw2, dim3(a.nchunk), dim3(1024), 0, st, b);
     hipLaunchKernelGGL(k_ws_embed_bwd, dim3(a.nsides), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_ws_du, dim3(kH), dim3(256), 0, st, b);

@@ -79,6 +79,26 @@ def test_forward_matches_oracle(api):
             np.testing.assert_allclose(g, ref, rtol=2e-2, atol=2e-2 * max(1.0, np.abs(ref).max()))
 
 
+def test_forward_matches_oracle_many_tiles(api):
+    """Enough points that every head block works through several groups of
+    tiles, with groups spanning sides and ragged ends of blocks' ranges."""
+    rng = np.random.default_rng(7)
+    sizes = [(int(rng.integers(300, 2000)), int(rng.integers(300, 2000))) for _ in range(24)]
+    probs = _problems(8, sizes)
+    B = api.Batch.from_problems(probs)
+    net = api.WarmStartNet(seed=5)
+    par = _params(net.bf16_weights())
+    lu, lv = net.predict(B, eps=0.05)
+    lu, lv = lu.cpu().numpy(), lv.cpu().numpy()
+    for k, p in enumerate(probs):
+        ou, ov = WO.predict(par, p.x, p.a, p.y, p.b, eps=0.05)
+        gu = lu[B.row_off[k]:B.row_off[k + 1]] - np.log(p.a)
+        gv = lv[B.col_off[k]:B.col_off[k + 1]] - np.log(p.b)
+        for g, o, w in ((gu, ou, p.a), (gv, ov, p.b)):
+            ref = o - np.log(w)
+            np.testing.assert_allclose(g, ref, rtol=2e-2, atol=2e-2 * max(1.0, np.abs(ref).max()))
+
+
 def test_gradient_matches_oracle(api):
     probs = _problems(2, SIZES)
     B = api.Batch.from_problems(probs)
