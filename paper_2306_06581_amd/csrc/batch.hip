@@ -42,6 +42,13 @@ struct BTypes {
 // y_new = marg / w (0 on an empty line or w <= 0).  Returns this thread's
 // share of the residual: ROLE 0 |y_prev w - marg| (iterate t - 1, t >= 2),
 // ROLE 1 |y_new w - marg| (iterate t).
+// A lane's entries of a line are k0 + lane, k0 + lane + L, ... and are added
+// in that order; kBUnroll of them are loaded at once (a line of the batched
+// workloads, about 8 ln n entries, takes one pass), and the next line's
+// offsets are loaded while the current line streams, so a line costs about
+// one memory round trip instead of one per entry.
+constexpr int kBUnroll = 16;
+
 template <int ROLE, int PREC, int L>
 __device__ __forceinline__ double b_half(const int64_t* __restrict__ ptr,
                                          const uint16_t* __restrict__ idx,
@@ -54,10 +61,31 @@ __device__ __forceinline__ double b_half(const int64_t* __restrict__ ptr,
     const int lane = threadIdx.x % L;
     const int g = threadIdx.x / L, ng = blockDim.x / L;
     double res = 0.0;
+    int64_t k0 = 0, k1 = 0;
+    if (g < nl) {
+        k0 = ptr[g];
+        k1 = ptr[g + 1];
+    }
     for (int64_t r = g; r < nl; r += ng) {
-        const int64_t k0 = ptr[r], k1 = ptr[r + 1];
+        int64_t n0 = 0, n1 = 0;
+        if (r + ng < nl) {
+            n0 = ptr[r + ng];
+            n1 = ptr[r + ng + 1];
+        }
         V acc = 0;
-        for (int64_t k = k0 + lane; k < k1; k += L) acc = fma(val[k], xin[idx[k]], acc);
+        for (int64_t kb = k0 + lane; kb < k1; kb += kBUnroll * L) {
+            V ve[kBUnroll];
+            uint16_t ie[kBUnroll];
+#pragma unroll
+            for (int e = 0; e < kBUnroll; ++e) {
+                const int64_t k = kb + (int64_t)e * L;
+                ve[e] = k < k1 ? val[k] : (V)0;
+                ie[e] = k < k1 ? idx[k] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int e = 0; e < kBUnroll; ++e)
+                if (kb + (int64_t)e * L < k1) acc = fma(ve[e], xin[ie[e]], acc);
+        }
         acc = group_sum<L>(acc);
         if (lane == 0) {
             const double w = (double)acc;
@@ -75,6 +103,8 @@ __device__ __forceinline__ double b_half(const int64_t* __restrict__ ptr,
                 }
             }
         }
+        k0 = n0;
+        k1 = n1;
     }
     return res;
 }
