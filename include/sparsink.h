@@ -300,9 +300,11 @@ int ss_batch_workspace_size(const ss_batch *batch, const ss_options *opts, size_
  * and its u^1 are finite and its L1 row marginal error sum |u0 (K~v0) - a| is
  * no larger than the plain start's sum |K~1 - a|; otherwise the problem
  * continues from the plain start and its iterates are those of a solve
- * without a warm start (outs[k].warm_start = 0).  `schedule` NULL picks
- * the schedule with ss_autotune_batched (cached per process for batches of
- * the same precision and size class).  outs: host array [count]; each entry
+ * without a warm start (outs[k].warm_start = 0).  `schedule` NULL uses 8
+ * lanes per line and 1024 threads (the schedule ss_autotune_batched picks
+ * on MI355X for batches of a few hundred problems); the library keeps no
+ * tuning state, so a caller who wants tuning runs ss_autotune_batched once
+ * and passes its result.  outs: host array [count]; each entry
  * is filled as by spar_sink_ot (z_norm 0; stage times are those of the whole
  * batch).  Returns SS_OK when every problem converged, SS_NOT_CONVERGED when
  * some did not (see outs[k].status), or an error code for the whole batch. */

@@ -310,7 +310,8 @@ def spar_sink_batched(batch: Batch, *, eps, tol=1e-6, max_iter=1000, seed=0, pre
                       raise_on_error=True):
     """Alg. 3 for every problem of the batch; returns (status, [Result per problem]).
 
-    schedule: (lanes_per_line, block_threads) or None for the autotuned one.
+    schedule: (lanes_per_line, block_threads), or None for the library's default
+    (8, 1024); ss_autotune_batched picks one for a given batch.
     With return_scalings, each Result carries its u and v (FP64 device views)."""
     rows, cols = int(batch.row_off[-1]), int(batch.col_off[-1])
     u_out = torch.empty(rows, dtype=torch.float64, device="cuda") if return_scalings else None

@@ -8,7 +8,6 @@
 #include <string.h>
 
 #include <functional>
-#include <map>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -301,6 +300,71 @@ static IterState* pinned_state_slots() {
     return slots;
 }
 
+// Graph kinds with an executable cached per host thread and device.
+enum GraphKind { GK_LOOP = 0, GK_TIMING, GK_SAMPLE, GK_BATCH_LOOP, GK_OTHER, GK_COUNT };
+constexpr int kGraphDevices = 64;
+
+// Per host thread and device: the stream graphs are captured on and one
+// executable graph per kind, kept for the thread's life like the pinned loop
+// slots (never destroyed: they may outlive the runtime at process exit).  A
+// solve then creates no stream, and when its graph has the shape of the
+// previous one of its kind (same launches, new arguments) the executable is
+// updated in place instead of instantiated.
+struct ThreadGraphs {
+    hipStream_t cs;
+    hipGraphExec_t exec[GK_COUNT];
+};
+
+static ThreadGraphs* thread_graphs() {
+    thread_local ThreadGraphs tg[kGraphDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kGraphDevices) return nullptr;
+    ThreadGraphs& g = tg[dev];
+    if (!g.cs && hipStreamCreateWithFlags(&g.cs, hipStreamNonBlocking) != hipSuccess) {
+        g.cs = nullptr;
+        return nullptr;
+    }
+    return &g;
+}
+
+// Records `rec(stream)` into a graph on the thread's capture stream and
+// returns an executable for it in *exec: the thread's executable of `kind`
+// updated in place when the shapes match, else a new one that replaces it.
+// The caller must have waited for every earlier launch of that executable
+// (every entry point synchronises before it returns).
+hipError_t capture_exec(int kind, const std::function<hipError_t(hipStream_t)>& rec,
+                        hipGraphExec_t* exec) {
+    *exec = nullptr;
+    ThreadGraphs* tg = thread_graphs();
+    if (!tg) return hipErrorInvalidDevice;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(tg->cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t e1 = rec(tg->cs);
+        const hipError_t e2 = hipStreamEndCapture(tg->cs, &graph);
+        e = e1 != hipSuccess ? e1 : e2;
+    }
+    if (e == hipSuccess && tg->exec[kind]) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateSuccess;
+        if (hipGraphExecUpdate(tg->exec[kind], graph, &bad, &res) == hipSuccess &&
+            res == hipGraphExecUpdateSuccess) {
+            *exec = tg->exec[kind];
+        } else {
+            (void)hipGetLastError();  // a refused update is not an error of the solve
+            (void)hipGraphExecDestroy(tg->exec[kind]);
+            tg->exec[kind] = nullptr;
+        }
+    }
+    if (e == hipSuccess && !*exec) {
+        e = hipGraphInstantiate(&tg->exec[kind], graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) *exec = tg->exec[kind];
+        else tg->exec[kind] = nullptr;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    return e;
+}
+
 // Runs the Sinkhorn loop: `iter(k, stream)` enqueues iteration k (its
 // ping-pong parity is k & 1).  With graph_iters > 0 an even number of
 // iterations is captured once and replayed.  Replays are pipelined: replay
@@ -316,15 +380,12 @@ int run_loop(const std::function<hipError_t(int, hipStream_t)>& iter, int graph_
     if (graph_iters > 0) {
         int G = graph_iters + (graph_iters & 1);
         if (G > total + (total & 1)) G = total + (total & 1);
-        hipStream_t cs;
-        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        for (int k = 0; k < G && e == hipSuccess; ++k) e = iter(k, cs);
-        hipError_t e2 = hipStreamEndCapture(cs, &graph);
-        if (e == hipSuccess) e = e2;
-        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipError_t e = capture_exec(GK_LOOP, [&](hipStream_t cs) {
+            hipError_t er = hipSuccess;
+            for (int k = 0; k < G && er == hipSuccess; ++k) er = iter(k, cs);
+            return er;
+        }, &exec);
         int rc = SS_OK;
         if (e != hipSuccess) rc = fail(SS_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
         const int nrep = (total + G - 1) / G;
@@ -380,9 +441,6 @@ int run_loop(const std::function<hipError_t(int, hipStream_t)>& iter, int graph_
         }
         for (auto& x : ev)
             if (x) (void)hipEventDestroy(x);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        (void)hipStreamDestroy(cs);
         return rc;
     }
     const int poll = 8;
@@ -619,15 +677,12 @@ int time_graph(const std::function<hipError_t(int, hipStream_t)>& iter, int iter
                const ss_options* O, IterState* d_state, hipStream_t st, double* ms_out,
                int launches_per_iter = 2) {
     if (!ms_out) return fail(SS_E_INVALID_ARG, "ms_out must not be NULL");
-    hipStream_t cs;
-    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (int k = 0; k < iters && e == hipSuccess; ++k) e = iter(k, cs);
-    hipError_t e2 = hipStreamEndCapture(cs, &graph);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipError_t e = capture_exec(GK_TIMING, [&](hipStream_t cs) {
+        hipError_t er = hipSuccess;
+        for (int k = 0; k < iters && er == hipSuccess; ++k) er = iter(k, cs);
+        return er;
+    }, &exec);
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
@@ -644,9 +699,6 @@ int time_graph(const std::function<hipError_t(int, hipStream_t)>& iter, int iter
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cs);
     if (e != hipSuccess) return fail(SS_E_HIP, "timing graph failed: %s", hipGetErrorString(e));
     *ms_out = (double)ms / (double)(iters * launches_per_iter);
     return SS_OK;
@@ -1212,26 +1264,14 @@ hipError_t batch_iterate(const BCtx& c, const BIterArgs& ia, const ss_schedule& 
     return launch_batch_iterate(c.O->precision, sc.lanes_per_line, sc.block_threads, grid, ia, s);
 }
 
-// Captures fn into a graph on a private stream, replays it once on st and
-// waits for it.
-hipError_t run_captured(const std::function<hipError_t(hipStream_t)>& fn, hipStream_t st) {
-    hipStream_t cs;
-    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-    hipGraph_t graph = nullptr;
+// Captures fn into a graph (the thread's executable of `kind`), replays it
+// once on st and waits for it.
+hipError_t run_captured(int kind, const std::function<hipError_t(hipStream_t)>& fn,
+                        hipStream_t st) {
     hipGraphExec_t exec = nullptr;
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        const hipError_t e1 = fn(cs);
-        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
-        e = e1 != hipSuccess ? e1 : e2;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipError_t e = capture_exec(kind, fn, &exec);
     if (e == hipSuccess) e = hipGraphLaunch(exec, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the exec is destroyed below
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     return e;
 }
 
@@ -1277,8 +1317,12 @@ int batch_autotune(BCtx& c, ss_schedule* best, float* cand_ms, int32_t* ncand) {
     return SS_OK;
 }
 
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int64_t>, ss_schedule> g_tuned;
+// The schedule spar_sink_batched uses when the caller passes none: the one
+// ss_autotune_batched picks on MI355X for batches of a few hundred problems
+// with sides up to 4096 (8 lanes per line, 1024 threads).  The library keeps
+// no tuning state; a caller who wants tuning runs ss_autotune_batched once
+// and passes its result.
+constexpr ss_schedule kDefaultSchedule = {8, 1024};
 
 int batch_start(BCtx& c, const ss_batch* B, const ss_options* O, void* ws, size_t ws_bytes,
                 void* stream) {
@@ -1599,31 +1643,9 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
     if (rc != SS_OK) return rc;
     Timer tm;
     tm.mark(0, c.st);
-    HIP_TRY(run_captured([&](hipStream_t s) { return batch_sample(c, s); }, c.st));
+    HIP_TRY(run_captured(GK_SAMPLE, [&](hipStream_t s) { return batch_sample(c, s); }, c.st));
     tm.mark(1, c.st);
-    ss_schedule sc;
-    if (schedule) {
-        sc = *schedule;
-    } else {
-        // size class: half octaves of the total number of rows
-        const auto key = std::make_tuple(O->precision, B->count,
-                                         (int64_t)floor(2.0 * log2((double)c.L.rows)));
-        bool have = false;
-        {
-            std::lock_guard<std::mutex> g(g_tune_mu);
-            auto it = g_tuned.find(key);
-            if (it != g_tuned.end()) {
-                sc = it->second;
-                have = true;
-            }
-        }
-        if (!have) {
-            rc = batch_autotune(c, &sc, nullptr, nullptr);
-            if (rc != SS_OK) return rc;
-            std::lock_guard<std::mutex> g(g_tune_mu);
-            g_tuned[key] = sc;
-        }
-    }
+    const ss_schedule sc = schedule ? *schedule : kDefaultSchedule;
     tm.mark(2, c.st);
     // The loop runs at most kHandoffIters iterations first.  When at most
     // kHandoffMax problems are still short of the tolerance, each continues
@@ -1635,7 +1657,8 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
     if (O->max_iter > kHandoffIters) {
         BIterArgs ia = c.ia;
         ia.max_iter = kHandoffIters;
-        HIP_TRY(run_captured([&](hipStream_t s) { return batch_iterate(c, ia, sc, s); }, c.st));
+        HIP_TRY(run_captured(GK_BATCH_LOOP, [&](hipStream_t s) { return batch_iterate(c, ia, sc, s); },
+                             c.st));
         std::vector<BStat> st0(K);
         HIP_TRY(hipMemcpyAsync(st0.data(), at<void>(ws, c.L.stat), (size_t)K * sizeof(BStat),
                                hipMemcpyDeviceToHost, c.st));
@@ -1645,15 +1668,17 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
                 strag.push_back(k);
         if ((int)strag.size() > kHandoffMax) {
             strag.clear();
-            HIP_TRY(run_captured([&](hipStream_t s) { return batch_iterate(c, c.ia, sc, s); },
-                                 c.st));
+            HIP_TRY(run_captured(GK_BATCH_LOOP,
+                                 [&](hipStream_t s) { return batch_iterate(c, c.ia, sc, s); }, c.st));
         }
     } else {
-        HIP_TRY(run_captured([&](hipStream_t s) { return batch_iterate(c, c.ia, sc, s); }, c.st));
+        HIP_TRY(run_captured(GK_BATCH_LOOP,
+                             [&](hipStream_t s) { return batch_iterate(c, c.ia, sc, s); }, c.st));
     }
     tm.mark(3, c.st);
     HIP_TRY(run_captured(
-        [&](hipStream_t s) { return launch_batch_objective(O->precision, B->count, c.oa, s); }, c.st));
+        GK_OTHER, [&](hipStream_t s) { return launch_batch_objective(O->precision, B->count, c.oa, s); },
+        c.st));
     tm.mark(4, c.st);
     std::vector<BStat> stat(K);
     double gst[ST_COUNT];
@@ -2335,15 +2360,12 @@ int ss_ibp_time_iterations(const ss_ibp_problem* P, const ss_options* O, void* w
     A.max_iter = iters;
     A.err_hist = nullptr;
     const int prec = O->precision == SS_F64 ? P_F64 : P_F32;
-    hipStream_t cs;
-    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (int k = 0; k < iters && e == hipSuccess; ++k) e = launch_ibp_iteration(prec, A, cs);
-    hipError_t e2 = hipStreamEndCapture(cs, &graph);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipError_t e = capture_exec(GK_TIMING, [&](hipStream_t cs) {
+        hipError_t er = hipSuccess;
+        for (int k = 0; k < iters && er == hipSuccess; ++k) er = launch_ibp_iteration(prec, A, cs);
+        return er;
+    }, &exec);
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
@@ -2359,9 +2381,6 @@ int ss_ibp_time_iterations(const ss_ibp_problem* P, const ss_options* O, void* w
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cs);
     if (e != hipSuccess) return fail(SS_E_HIP, "timing graph failed: %s", hipGetErrorString(e));
     IterState hs;
     HIP_TRY(hipMemcpy(&hs, A.st, sizeof hs, hipMemcpyDeviceToHost));

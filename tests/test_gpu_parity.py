@@ -2,11 +2,11 @@
 
 Bars: integer/index/bit outputs bit-exact; FP64 scalings and estimates within
 1e-10 relative; FP32 and log-FP32 estimates within 1e-4 relative of the FP64
-oracle.  The UOT keep decision depends on exponentials (host libm against the
-device library) and on a normaliser summed in a different order, so a mask
-bit could differ where U lies within about 1e-15 of p* (expected count per
-case below 1e-8).  The UOT tests still require every bit to be equal; a
-failure reports the differing positions and their distance to the boundary."""
+oracle.  The UOT keep decision takes its exponentials and logarithms from the
+specified functions both sides implement, so given the oracle's normaliser
+(z_in) the UOT mask, offsets, indices and stored values are compared bit for
+bit as well; a failure reports the differing positions and their distance to
+the boundary.  The library's own normaliser is compared separately."""
 import math
 
 import numpy as np
