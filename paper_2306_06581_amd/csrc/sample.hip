@@ -399,40 +399,6 @@ __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t
                 acc = fma(p, eb[j], acc);
             }
             acc = acc * (pp.row_bnd[i] * e_quarter);
-        } else if (pp.cost == kCostWfr) {
-            // WFR: q = exp(la + lb) cos(z)^(2 inv_tau).  cos z is its Taylor
-            // series in t = z^2 = c w^2 < (pi/2)^2 up to t^11 (truncation below
-            // 1e-19), so the pair needs no square root and no range reduction;
-            // blocked pairs (z >= pi/2) add nothing, and neither does a pair
-            // whose series rounds to <= 0 (z within about 1e-16 of pi/2).
-            constexpr double c0 = 1.0, c1 = 1.0 / 2, c2 = 1.0 / 24, c3 = 1.0 / 720,
-                             c4 = 1.0 / 40320, c5 = 1.0 / 3628800, c6 = 1.0 / 479001600,
-                             c7 = 1.0 / 87178291200.0, c8 = 1.0 / 20922789888000.0,
-                             c9 = 1.0 / 6402373705728000.0, c10 = 1.0 / 2432902008176640000.0,
-                             c11 = 1.0 / 1124000727777607680000.0;
-            const double la = pp.row_fac[i];
-            const double w2 = pp.wfr_w * pp.wfr_w;
-            const double k2 = 2.0 * pp.inv_tau;
-            for (int64_t j = j0; j < j1; ++j) {
-                const double c = sqdist<D>(D > 0 ? xi : xp, pp.y + j * pp.d, pp.d);
-                const double t = c * w2;
-                if (t < kHalfPi * kHalfPi) {
-                    const double u = -t;  // cos z = sum_k u^k / (2k)!
-                    double p = c11;
-                    p = fma(p, u, c10);
-                    p = fma(p, u, c9);
-                    p = fma(p, u, c8);
-                    p = fma(p, u, c7);
-                    p = fma(p, u, c6);
-                    p = fma(p, u, c5);
-                    p = fma(p, u, c4);
-                    p = fma(p, u, c3);
-                    p = fma(p, u, c2);
-                    p = fma(p, u, c1);
-                    p = fma(p, u, c0);
-                    if (p > 0.0) acc = acc + exp((la + pp.col_fac[j]) + k2 * log(p));
-                }
-            }
         } else {
             const double la = pp.row_fac[i];
             for (int64_t j = j0; j < j1; ++j) {
@@ -446,6 +412,131 @@ __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// WFR: q = exp(la + lb) cos(z)^(2 inv_tau), cos z from its Taylor series in
+// t = z^2 = c w^2 < (pi/2)^2 up to t^11 (truncation below 1e-19; no square
+// root, no range reduction).  Blocked pairs (z >= pi/2) add nothing, and
+// neither does a pair whose series rounds to <= 0.  Most pairs are blocked,
+// so the pairs that are not are compacted before the logarithm and
+// exponential: each wave scans its 64 rows against the tile's columns one
+// column at a time, appends the unblocked pairs (t and la + lb) to its own
+// LDS queue in lane order (a ballot and prefix count: a fixed order), and
+// whenever 64 are queued every lane evaluates one.  Sums stay in a fixed
+// order for a given launch shape.
+constexpr double kWfrC[12] = {1.0,
+                              1.0 / 2,
+                              1.0 / 24,
+                              1.0 / 720,
+                              1.0 / 40320,
+                              1.0 / 3628800,
+                              1.0 / 479001600,
+                              1.0 / 87178291200.0,
+                              1.0 / 20922789888000.0,
+                              1.0 / 6402373705728000.0,
+                              1.0 / 2432902008176640000.0,
+                              1.0 / 1124000727777607680000.0};
+
+__device__ __forceinline__ double wfr_q(double t, double s, double k2) {
+    const double u = -t;  // cos z = sum_k u^k / (2k)!
+    double p = kWfrC[11];
+#pragma unroll
+    for (int k = 10; k >= 0; --k) p = fma(p, u, kWfrC[k]);
+    // the specified functions: no special-case paths, about half the
+    // instructions of the library's (their 1-3 ulp are far inside the
+    // normaliser's accuracy)
+    return p > 0.0 ? exp_spec(s + k2 * log_spec(p)) : 0.0;
+}
+
+// Columns per LDS stage of the WFR normaliser: their coordinates and log
+// factors are read once per block, then by every wave as broadcasts.
+constexpr int kZwChunk = 256;
+
+template <int D>
+__global__ __launch_bounds__(256) void k_uot_z_wfr(ProbParams pp, int64_t n, int64_t m,
+                                                   int64_t ncol_tiles, double* partials) {
+    constexpr int DD = D > 0 ? D : 1;
+    __shared__ double sh[4];
+    __shared__ double qt[4][128], qs[4][128];
+    __shared__ double ys[kZwChunk][DD + 1];  // coordinates, then the column's log factor
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
+    const int64_t i = rt * 256 + threadIdx.x;
+    const int64_t j0 = ct * kCostTileCols;
+    const int64_t j1 = (j0 + kCostTileCols < m) ? j0 + kCostTileCols : m;
+    const bool live = i < n;
+    double xi[DD];
+    const double* xp = pp.x + (live ? i : 0) * pp.d;
+#pragma unroll
+    for (int k = 0; k < DD; ++k) xi[k] = D > 0 ? xp[k] : 0.0;
+    const double la = live ? pp.row_fac[i] : 0.0;
+    const double w2 = pp.wfr_w * pp.wfr_w;
+    const double k2 = 2.0 * pp.inv_tau;
+    double acc = 0.0;
+    int nq = 0;  // queued pairs of this wave (wave-uniform)
+    for (int64_t c0 = j0; c0 < j1; c0 += kZwChunk) {
+        const int nc = (int)(j1 - c0 < kZwChunk ? j1 - c0 : kZwChunk);
+        if constexpr (D > 0) {
+            __syncthreads();  // the previous chunk is read
+            if (threadIdx.x < nc) {
+                const double* yp = pp.y + (c0 + threadIdx.x) * D;
+#pragma unroll
+                for (int k = 0; k < D; ++k) ys[threadIdx.x][k] = yp[k];
+                ys[threadIdx.x][D] = pp.col_fac[c0 + threadIdx.x];
+            }
+            __syncthreads();
+        }
+        for (int jj = 0; jj < nc; ++jj) {
+            const int64_t j = c0 + jj;
+            double c, lb;
+            if constexpr (D > 0) {
+                // fused: the normaliser needs its sum to 1e-13, not the
+                // mask's operation order (a pair it would block differently
+                // lies at z = pi/2, where its term is 0)
+                double d0 = xi[0] - ys[jj][0];
+                c = d0 * d0;
+#pragma unroll
+                for (int k = 1; k < D; ++k) {
+                    const double u = xi[k] - ys[jj][k];
+                    c = fma(u, u, c);
+                }
+                lb = ys[jj][D];
+            } else {
+                c = sqdist<D>(xp, pp.y + j * pp.d, pp.d);
+                lb = pp.col_fac[j];
+            }
+            const double t = c * w2;
+            const bool on = live && t < kHalfPi * kHalfPi;
+            const uint64_t bal = __ballot(on);
+            if (on) {
+                const int pos = nq + __popcll(bal & ((1ull << lane) - 1));
+                qt[wv][pos] = t;
+                qs[wv][pos] = la + lb;
+            }
+            nq += __popcll(bal);
+            if (nq >= 64) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                acc = acc + wfr_q(qt[wv][lane], qs[wv][lane], k2);
+                const double t2 = qt[wv][64 + lane], s2 = qs[wv][64 + lane];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                nq -= 64;
+                if (lane < nq) {
+                    qt[wv][lane] = t2;
+                    qs[wv][lane] = s2;
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < nq) acc = acc + wfr_q(qt[wv][lane], qs[wv][lane], k2);
+    const double tot = block_sum256(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
 template <int D>
 static void run_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* eb, double g,
                       bool short_range, double* partials, int64_t nct, int64_t nrt,
@@ -454,6 +545,9 @@ static void run_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* 
     if (short_range)
         hipLaunchKernelGGL((k_uot_z<D, true>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n,
                            m, nct, eb, g, eq, partials);
+    else if (pp.cost == kCostWfr)
+        hipLaunchKernelGGL((k_uot_z_wfr<D>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n,
+                           m, nct, partials);
     else
         hipLaunchKernelGGL((k_uot_z<D, false>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n,
                            m, nct, eb, g, eq, partials);

@@ -157,6 +157,32 @@ def test_sample_ot_dense_budgets(api, frac):
     assert np.array_equal(g["val"].cpu().numpy(), sk.val)
 
 
+def test_sample_ot_columns_of_every_length(api):
+    """Columns of very different lengths in one sketch: n = 5000 rows; heavy
+    columns hold more than 4096 entries (one has half the column mass: about
+    every row), most hold a few thousand, ten light ones a few hundred, one
+    none.  The CSC must still list every column's rows in order."""
+    rng = np.random.default_rng(21)
+    n, m = 5000, 130
+    x = rng.standard_normal((n, 2))
+    y = rng.standard_normal((m, 2)) + 0.5
+    a = rng.dirichlet(np.ones(n))
+    b = rng.dirichlet(np.ones(m)) * 0.4
+    b[7] = 0.5
+    b[50] = 0.003
+    b[100:110] = 1e-5
+    b[-1] = 0.0
+    b /= b.sum()
+    p = W.Problem(x, y, a, b, eps=0.1, s=W.s_budget(n, 8.0), seed=21)
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    counts = np.diff(sk.col_ptr)
+    assert (counts > 4096).any() and ((counts > 256) & (counts <= 4096)).any()
+    assert ((counts > 1) & (counts <= 256)).any() and counts[-1] == 0
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    _check_sketch_structure(g, sk)
+    assert np.array_equal(g["val_t"].cpu().numpy(), sk.val_t)
+
+
 def test_sample_uot_dense_budget(api):
     p = W.uot_mix3(300, seed=10, eps=0.05)
     p.s = 0.5 * p.n * p.m
