@@ -1573,12 +1573,20 @@ __global__ __launch_bounds__(256) void k_b_fill_idx(BatchArgs A) {
 }
 
 // Value pass: one wave per line, two entries per lane at a time.
+constexpr int kBValLines = 4;  // lines per wave of the batched value pass
+
 template <int ROLE, int PREC, int D>
 __global__ __launch_bounds__(256) void k_b_fill_val(BatchArgs A) {
+    // kBValLines lines per wave, kWave / kBValLines lanes each: a line of
+    // these problems holds ~8 ln n entries, so a wave per line spent most of
+    // its time on the line's chain of dependent loads (owner, problem, offsets,
+    // indices, coordinates); four lines a wave run four chains at once
+    constexpr int LL = kWave / kBValLines;
     const int lane = threadIdx.x & (kWave - 1);
+    const int sub = lane % LL;
     const int64_t lines = ROLE == 0 ? A.rows : A.cols;
-    const int64_t L = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (L >= lines) return;
+    const int64_t L = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kBValLines + lane / LL;
+    if (L >= lines) return;  // no wave-wide operation follows
     const int k = A.owner[(ROLE == 0 ? 0 : A.rows) + L];
     const BProb P = A.prob[k];
     const int64_t local = L - (ROLE == 0 ? A.row_off : A.col_off)[k];
@@ -1601,8 +1609,8 @@ __global__ __launch_bounds__(256) void k_b_fill_val(BatchArgs A) {
     void* val = ROLE == 0 ? A.val : A.val_t;
     const int64_t e0 = ptr[L];
     const int64_t e1 = ptr[L + 1] < A.cap ? ptr[L + 1] : A.cap;
-    for (int64_t e = e0 + lane; e < e1; e += 2 * kWave) {
-        const int64_t e2 = e + kWave;
+    for (int64_t e = e0 + sub; e < e1; e += 2 * LL) {
+        const int64_t e2 = e + LL;
         const bool two = e2 < e1;
         const int64_t oa = idx[e];
         const int64_t ob = two ? idx[e2] : oa;
@@ -1663,10 +1671,12 @@ static void run_b_cmax(const BatchArgs& a, int64_t nt, hipStream_t st) {
 template <int PREC, int D>
 static void run_b_fill(const BatchArgs& a, hipStream_t st) {
     const dim3 gr((unsigned)((a.rows + 3) / 4)), gc((unsigned)((a.cols + 3) / 4));
+    constexpr int64_t per = 4 * kBValLines;  // lines per block of the value pass
+    const dim3 vr((unsigned)((a.rows + per - 1) / per)), vc((unsigned)((a.cols + per - 1) / per));
     hipLaunchKernelGGL((k_b_fill_idx<0>), gr, dim3(256), 0, st, a);
-    hipLaunchKernelGGL((k_b_fill_val<0, PREC, D>), gr, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_b_fill_val<0, PREC, D>), vr, dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_b_fill_idx<1>), gc, dim3(256), 0, st, a);
-    hipLaunchKernelGGL((k_b_fill_val<1, PREC, D>), gc, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_b_fill_val<1, PREC, D>), vc, dim3(256), 0, st, a);
 }
 
 template <int D>
