@@ -160,8 +160,8 @@ def batched_bench(count: int, steps: int) -> dict:
     ms = (time.perf_counter() - t0) * 1e3 / steps
     if rc < 0:
         raise SystemExit(f"batched solve failed with status {rc}")
-    iters = np.array([r.iters for r in res])
-    nnz = np.array([r.nnz for r in res], dtype=np.float64)
+    iters = res.column("iters")
+    nnz = res.column("nnz").astype(np.float64)
     n = np.array([p.n for p in probs], dtype=np.float64)
     m = np.array([p.m for p in probs], dtype=np.float64)
     # per iteration of a problem: value (4 B) + 16-bit index per entry in both
@@ -181,8 +181,8 @@ def batched_bench(count: int, steps: int) -> dict:
             "stage_ms": {"sample": res[0].t_sample_ms, "iterate": t_iter,
                          "objective": res[0].t_obj_ms},
             "loop_GBps": gbps, "loop_frac_of_8TBps": gbps / HBM_PEAK_GBPS,
-            "converged": int(sum(r.status == 0 for r in res)),
-            "max_marginal_err": float(max(r.marginal_err for r in res))}
+            "converged": int(np.sum(res.column("status") == 0)),
+            "max_marginal_err": float(res.column("marginal_err").max())}
 
 
 def warmstart_bench(ntrain: int, count: int) -> dict:

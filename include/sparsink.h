@@ -370,6 +370,21 @@ int ss_warmstart_workspace_size(const ss_batch *batch, size_t *bytes);
 int ss_warmstart_predict(const ss_mlp *mlp, const ss_batch *batch, double eps, int32_t cost,
                          double *log_u0, double *log_v0, void *ws, size_t ws_bytes, void *stream);
 
+/* Learned warm start for a batch: spar_sink_batched started from
+ * the network's prediction (ss_warmstart_predict), with the
+ * prediction on a second stream of the library (one per host thread and
+ * device, default priority) that overlaps the sampling stage; the loop waits
+ * for it.  The prediction is judged per problem against the plain start, as
+ * in spar_sink_batched, and the results equal ss_warmstart_predict followed
+ * by spar_sink_batched with its outputs as init_log_u / init_log_v.  opts
+ * must not carry init_log_u / init_log_v; d = 3; cost maxnorm or plain.
+ * ws: ss_batch_learned_workspace_size bytes (the batch's, the network's and
+ * the two start vectors).  Returns as spar_sink_batched. */
+int ss_batch_learned_workspace_size(const ss_batch *batch, const ss_options *opts, size_t *bytes);
+int spar_sink_batched_learned(const ss_batch *batch, const ss_options *opts,
+                              const ss_schedule *schedule, const ss_mlp *mlp, void *ws,
+                              size_t ws_bytes, void *stream, ss_result *outs);
+
 /* One Adam step (learning rate lr, betas 0.9 / 0.999, eps 1e-8) on the batch
  * loss against the solutions tgt_log_u (device FP64, sum(n)) and tgt_log_v
  * (sum(m)); entries that are not finite (empty lines) are left out.  *loss

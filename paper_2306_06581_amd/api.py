@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+from collections.abc import Sequence
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -304,15 +305,8 @@ def batch_workspace_size(batch: Batch, opts: N.SsOptions) -> int:
     return int(out.value)
 
 
-def spar_sink_batched(batch: Batch, *, eps, tol=1e-6, max_iter=1000, seed=0, precision="f32",
-                      cost="maxnorm", empty_policy="auto", schedule=None, init_log_u=None,
-                      init_log_v=None, return_scalings=False, stream=None,
-                      raise_on_error=True):
-    """Alg. 3 for every problem of the batch; returns (status, [Result per problem]).
-
-    schedule: (lanes_per_line, block_threads), or None for the library's default
-    (8, 1024); ss_autotune_batched picks one for a given batch.
-    With return_scalings, each Result carries its u and v (FP64 device views)."""
+def _batched(name, batch, net, eps, tol, max_iter, seed, precision, cost, empty_policy, schedule,
+             init_log_u, init_log_v, return_scalings, stream, raise_on_error):
     rows, cols = int(batch.row_off[-1]), int(batch.col_off[-1])
     u_out = torch.empty(rows, dtype=torch.float64, device="cuda") if return_scalings else None
     v_out = torch.empty(cols, dtype=torch.float64, device="cuda") if return_scalings else None
@@ -322,25 +316,95 @@ def spar_sink_batched(batch: Batch, *, eps, tol=1e-6, max_iter=1000, seed=0, pre
         raise ValueError("init_log_u / init_log_v need sum(n) / sum(m) entries")
     opts = make_options(eps, 1.0, math.inf, tol, max_iter, seed, precision, cost, "marginal",
                         empty_policy, 0, 0, ilu, ilv, u_out, v_out, None)
-    ws = workspace(batch_workspace_size(batch, opts))
+    nb = ctypes.c_size_t(0)
+    size_fn = N.lib.ss_batch_learned_workspace_size if net is not None else \
+        N.lib.ss_batch_workspace_size
+    rc = size_fn(ctypes.byref(batch.c), ctypes.byref(opts), ctypes.byref(nb))
+    if rc < 0:
+        raise N.SparSinkError(rc, size_fn.__name__)
+    ws = workspace(nb.value)
     outs = (N.SsResult * batch.count)()
     sched = N.SsSchedule(*schedule) if schedule is not None else None
-    rc = N.lib.spar_sink_batched(ctypes.byref(batch.c), ctypes.byref(opts),
-                                 ctypes.byref(sched) if sched is not None else None,
-                                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
-                                 _stream(stream), outs)
+    args = [ctypes.byref(batch.c), ctypes.byref(opts),
+            ctypes.byref(sched) if sched is not None else None]
+    if net is not None:
+        args.append(ctypes.byref(net.c))
+    rc = getattr(N.lib, name)(*args, ctypes.c_void_p(ws.data_ptr()),
+                              ctypes.c_size_t(ws.numel()), _stream(stream), outs)
     if rc < 0 and raise_on_error and rc not in (N.SS_E_NONFINITE, N.SS_E_EMPTY):
-        raise N.SparSinkError(rc, "spar_sink_batched")
-    results = []
-    for k in range(batch.count):
-        r = outs[k]
-        res = Result(status=r.status, **{f: getattr(r, f) for f, _ in N.SsResult._fields_
-                                         if f != "status"})
-        if return_scalings:
-            res.u = u_out[batch.row_off[k]:batch.row_off[k + 1]]
-            res.v = v_out[batch.col_off[k]:batch.col_off[k + 1]]
-        results.append(res)
-    return rc, results
+        raise N.SparSinkError(rc, name)
+    res = BatchResults(outs, batch.count)
+    if return_scalings:
+        res._scalings(u_out, v_out, batch.row_off, batch.col_off)
+    return rc, res
+
+
+_RESULT_NAMES = tuple(f for f, _ in N.SsResult._fields_)
+_RESULT_DTYPE = np.dtype(N.SsResult)
+
+
+class BatchResults(Sequence):
+    """The Result of every problem of a batched solve, in batch order.
+
+    Each Result (and its u / v views) is built on first access from a copy of
+    the library's ss_result array, so returning a batch of thousands costs no
+    Python work per problem; column(name) gives one field of every problem as
+    a NumPy array."""
+
+    def __init__(self, outs, count: int):
+        self._rows = np.frombuffer(outs, dtype=_RESULT_DTYPE, count=count).copy()
+        self._cache = [None] * count
+        self._uv = None
+
+    def _scalings(self, u_out, v_out, row_off, col_off):
+        self._uv = (u_out, v_out, row_off, col_off)
+
+    def __len__(self) -> int:
+        return len(self._cache)
+
+    def __getitem__(self, k):
+        if isinstance(k, slice):
+            return [self[i] for i in range(*k.indices(len(self)))]
+        r = self._cache[k]  # IndexError past the end, as a list
+        if r is None:
+            k = k % len(self)
+            r = object.__new__(Result)
+            r.__dict__.update(zip(_RESULT_NAMES, self._rows[k].tolist()))
+            r.__dict__.update(u=None, v=None, err_hist=None, extra={})
+            if self._uv is not None:
+                u, v, ro, co = self._uv
+                r.u, r.v = u[ro[k]:ro[k + 1]], v[co[k]:co[k + 1]]
+            self._cache[k] = r
+        return r
+
+    def column(self, name: str) -> np.ndarray:
+        return self._rows[name].copy()
+
+
+def spar_sink_batched(batch: Batch, *, eps, tol=1e-6, max_iter=1000, seed=0, precision="f32",
+                      cost="maxnorm", empty_policy="auto", schedule=None, init_log_u=None,
+                      init_log_v=None, return_scalings=False, stream=None,
+                      raise_on_error=True):
+    """Alg. 3 for every problem of the batch; returns (status, BatchResults),
+    one Result per problem in batch order.
+
+    schedule: (lanes_per_line, block_threads), or None for the library's default
+    (8, 1024); ss_autotune_batched picks one for a given batch.
+    With return_scalings, each Result carries its u and v (FP64 device views)."""
+    return _batched("spar_sink_batched", batch, None, eps, tol, max_iter, seed, precision, cost,
+                    empty_policy, schedule, init_log_u, init_log_v, return_scalings, stream,
+                    raise_on_error)
+
+
+def spar_sink_batched_learned(batch: Batch, net: "WarmStartNet", *, eps, tol=1e-6,
+                              max_iter=1000, seed=0, precision="f32", cost="maxnorm",
+                              empty_policy="auto", schedule=None, return_scalings=False,
+                              stream=None, raise_on_error=True):
+    """spar_sink_batched started from net's prediction, which the library
+    computes on a second stream beside the sampling stage (d = 3)."""
+    return _batched("spar_sink_batched_learned", batch, net, eps, tol, max_iter, seed, precision,
+                    cost, empty_policy, schedule, None, None, return_scalings, stream,
+                    raise_on_error)
 
 
 def ss_autotune_batched(batch: Batch, *, eps, seed=0, precision="f32", cost="maxnorm",

@@ -1625,10 +1625,13 @@ static int noalloc_scratch(void** ws) {
 constexpr int kHandoffIters = 64;
 constexpr int kHandoffMax = 2;
 
-extern "C" {
+namespace {
 
-int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule* schedule, void* ws,
-                      size_t ws_bytes, void* stream, ss_result* outs) {
+// spar_sink_batched; `before_loop` (may be null) is an event the stream
+// waits for between the sampling stage and the loop (the warm start's
+// producer on another stream).
+// Host checks of the arguments batched_run takes beside the batch.
+int check_run_args(const ss_schedule* schedule, const ss_result* outs) {
     if (!outs) return fail(SS_E_INVALID_ARG, "outs must not be NULL");
     if (schedule) {
         bool ok = false;
@@ -1638,14 +1641,22 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
         if (!ok || !okb)
             return fail(SS_E_INVALID_ARG, "schedule: lanes_per_line in {4,8,16,32}, block_threads in {256,512,1024}");
     }
+    return SS_OK;
+}
+
+int batched_run(const ss_batch* B, const ss_options* O, const ss_schedule* schedule, void* ws,
+                size_t ws_bytes, void* stream, ss_result* outs, hipEvent_t before_loop) {
+    int rc = check_run_args(schedule, outs);
+    if (rc != SS_OK) return rc;
     BCtx c;
-    int rc = batch_start(c, B, O, ws, ws_bytes, stream);
+    rc = batch_start(c, B, O, ws, ws_bytes, stream);
     if (rc != SS_OK) return rc;
     Timer tm;
     tm.mark(0, c.st);
     HIP_TRY(run_captured(GK_SAMPLE, [&](hipStream_t s) { return batch_sample(c, s); }, c.st));
     tm.mark(1, c.st);
     const ss_schedule sc = schedule ? *schedule : kDefaultSchedule;
+    if (before_loop) HIP_TRY(hipStreamWaitEvent(c.st, before_loop, 0));
     tm.mark(2, c.st);
     // The loop runs at most kHandoffIters iterations first.  When at most
     // kHandoffMax problems are still short of the tolerance, each continues
@@ -1784,13 +1795,124 @@ int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule*
     return worst;
 }
 
-}  // extern "C"
+// Per host thread and device: a second stream for work that overlaps the
+// caller's stream, and two events, created on first use and kept for the
+// thread's life (default priority).
+struct SideStream {
+    hipStream_t s;
+    hipEvent_t ev[2];
+};
 
-namespace {
+static SideStream* side_stream() {
+    thread_local SideStream ss[kGraphDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kGraphDevices) return nullptr;
+    SideStream& x = ss[dev];
+    if (!x.s) {
+        if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess) {
+            x.s = nullptr;
+            return nullptr;
+        }
+        for (auto& e : x.ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    }
+    return &x;
+}
+
+// Workspace of spar_sink_batched_learned: the batch's, the network's and the
+// two start vectors, each 256-byte aligned.
+struct LearnedLayout {
+    size_t batch, pred, lu, lv, total;
+};
+
+int learned_plan(const ss_batch* B, const ss_options* O, LearnedLayout* L) {
+    int rc = check_batch(B, O);
+    if (rc != SS_OK) return rc;
+    rc = check_ws_batch(B);
+    if (rc != SS_OK) return rc;
+    int64_t rows = 0, cols = 0;
+    for (int k = 0; k < B->count; ++k) {
+        rows += B->n[k];
+        cols += B->m[k];
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L->batch = take(bplan(B, O).total);
+    L->pred = take(wplan(B).total);
+    L->lu = take((size_t)rows * 8);
+    L->lv = take((size_t)cols * 8);
+    L->total = off;
+    return SS_OK;
+}
 
 }  // namespace
 
 extern "C" {
+
+int spar_sink_batched(const ss_batch* B, const ss_options* O, const ss_schedule* schedule, void* ws,
+                      size_t ws_bytes, void* stream, ss_result* outs) {
+    return batched_run(B, O, schedule, ws, ws_bytes, stream, outs, nullptr);
+}
+
+int ss_batch_learned_workspace_size(const ss_batch* batch, const ss_options* opts, size_t* bytes) {
+    if (!bytes) return fail(SS_E_INVALID_ARG, "bytes must not be NULL");
+    LearnedLayout L;
+    const int rc = learned_plan(batch, opts, &L);
+    if (rc != SS_OK) return rc;
+    *bytes = L.total;
+    return SS_OK;
+}
+
+int spar_sink_batched_learned(const ss_batch* B, const ss_options* O, const ss_schedule* schedule,
+                              const ss_mlp* mlp, void* ws, size_t ws_bytes, void* stream,
+                              ss_result* outs) {
+    if (!O) return fail(SS_E_INVALID_ARG, "options must not be NULL");
+    if (O->init_log_u || O->init_log_v)
+        return fail(SS_E_INVALID_ARG, "the network gives the start: init_log_u/v must be NULL");
+    LearnedLayout L;
+    int rc = learned_plan(B, O, &L);
+    if (rc != SS_OK) return rc;
+    rc = check_run_args(schedule, outs);
+    if (rc != SS_OK) return rc;
+    if (!mlp || !mlp->params || !mlp->bf16 || !mlp->w2t)
+        return fail(SS_E_INVALID_ARG, "mlp buffers must not be NULL");
+    if (O->cost != SS_COST_SQEUCLID_MAXNORM && O->cost != SS_COST_SQEUCLID)
+        return fail(SS_E_INVALID_ARG, "unknown cost %d", O->cost);
+    if (!ws) return fail(SS_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(SS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(SS_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    SideStream* side = side_stream();
+    if (!side) return fail(SS_E_HIP, "no side stream");
+    const hipStream_t st = (hipStream_t)stream;
+    // the prediction starts after the caller's earlier work on `stream` (its
+    // inputs) and runs beside the sampling stage
+    HIP_TRY(hipEventRecord(side->ev[0], st));
+    HIP_TRY(hipStreamWaitEvent(side->s, side->ev[0], 0));
+    WLayout WL;
+    std::vector<WSide> sides;  // its host copy stays alive until the solve returns
+    MlpArgs a;
+    rc = ws_args(mlp, B, O->eps, O->cost, at<void>(ws, L.pred), L.total - L.pred, side->s, &WL,
+                 &sides, &a);
+    if (rc != SS_OK) return rc;
+    a.out_u = at<double>(ws, L.lu);
+    a.out_v = at<double>(ws, L.lv);
+    HIP_TRY(launch_mlp_predict(a, side->s));
+    HIP_TRY(hipEventRecord(side->ev[1], side->s));
+    ss_options o = *O;
+    o.init_log_u = a.out_u;
+    o.init_log_v = a.out_v;
+    rc = batched_run(B, &o, schedule, at<void>(ws, L.batch), L.pred - L.batch, stream, outs,
+                     side->ev[1]);
+    // the stream waited for the prediction before its loop and was
+    // synchronised; an early error leaves the side stream to finish here
+    (void)hipStreamSynchronize(side->s);
+    return rc;
+}
 
 int ss_version(void) { return 100; }
 

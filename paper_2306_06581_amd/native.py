@@ -125,6 +125,11 @@ SIGNATURES = {
     "ss_batch_workspace_size": (c_int, [POINTER(SsBatch), POINTER(SsOptions), POINTER(c_size_t)]),
     "spar_sink_batched": (c_int, [POINTER(SsBatch), POINTER(SsOptions), POINTER(SsSchedule),
                                   c_void_p, c_size_t, c_void_p, POINTER(SsResult)]),
+    "ss_batch_learned_workspace_size": (c_int, [POINTER(SsBatch), POINTER(SsOptions),
+                                                POINTER(c_size_t)]),
+    "spar_sink_batched_learned": (c_int, [POINTER(SsBatch), POINTER(SsOptions),
+                                          POINTER(SsSchedule), POINTER(SsMlp), c_void_p,
+                                          c_size_t, c_void_p, POINTER(SsResult)]),
     "ss_autotune_batched": (c_int, [POINTER(SsBatch), POINTER(SsOptions), c_void_p, c_size_t,
                                     c_void_p, POINTER(SsSchedule), POINTER(c_float),
                                     POINTER(c_int32)]),

@@ -56,7 +56,9 @@ def train(net: A.WarmStartNet, minibatches, *, eps, lr=1e-3, epochs=1):
 def evaluate(net: A.WarmStartNet, problems, *, eps, seed, tol=1e-6, max_iter=1000,
              precision="f32", schedule=None, repeats=3):
     """Iterations and wall time to tol from the plain start and from the
-    predicted one, on the same batch; the prediction time is reported apart."""
+    predicted one, on the same batch; the prediction time is reported apart,
+    and the solve that predicts on a second stream beside its sampling
+    (spar_sink_batched_learned) is timed whole."""
     B = A.Batch.from_problems(problems)
     kw = dict(eps=eps, tol=tol, max_iter=max_iter, seed=seed, precision=precision,
               schedule=schedule)
@@ -73,6 +75,9 @@ def evaluate(net: A.WarmStartNet, problems, *, eps, seed, tol=1e-6, max_iter=100
     (lu, lv), t_pred = timed(lambda: net.predict(B, eps=eps))
     (rc0, cold), t_cold = timed(lambda: A.spar_sink_batched(B, **kw))
     (rc1, warm), t_warm = timed(lambda: A.spar_sink_batched(B, init_log_u=lu, init_log_v=lv, **kw))
+    (rc2, fused), t_fused = timed(lambda: A.spar_sink_batched_learned(B, net, **kw))
+    same = all(f.iters == w.iters and f.estimate == w.estimate and f.status == w.status
+               for f, w in zip(fused, warm))
     both = [i for i in range(len(problems)) if cold[i].status == 0 and warm[i].status == 0]
     ic = np.array([cold[i].iters for i in both], dtype=np.float64)
     iw = np.array([warm[i].iters for i in both], dtype=np.float64)
@@ -82,5 +87,6 @@ def evaluate(net: A.WarmStartNet, problems, *, eps, seed, tol=1e-6, max_iter=100
             "iters_plain_mean": float(ic.mean()), "iters_learned_mean": float(iw.mean()),
             "iters_saved_frac": float(1.0 - iw.mean() / ic.mean()),
             "batch_ms_plain": t_cold, "batch_ms_learned": t_warm, "predict_ms": t_pred,
+            "batch_ms_learned_overlapped": t_fused, "overlapped_matches_two_calls": same,
             "loop_ms_plain": cold[0].t_iter_ms, "loop_ms_learned": warm[0].t_iter_ms,
             "max_rel_estimate_change": dev}

@@ -255,6 +255,46 @@ def test_batch_workspace_and_schedule_checks():
                                    ctypes.c_void_p(4096), 1 << 40, None, res) == N.SS_E_INVALID_ARG
 
 
+@pytest.mark.parametrize("change", ["none", "init", "mlp", "d2", "small_ws", "schedule",
+                                    "cost"])
+def test_batch_learned_checks(change):
+    # every argument of the overlapped learned solve is checked on the host,
+    # before the library takes a stream or launches anything
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd.api import make_options
+    b, keep = _fake_batch(N, ns=(300, 70), ms=(200, 90), ss=(3000.0, 700.0))
+    opts = make_options(0.05, precision="f32")
+    mlp = N.SsMlp(4096, 8192, 12288, 0, 0, 0, 0)
+    sched = None
+    plain, learned = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert N.lib.ss_batch_workspace_size(ctypes.byref(b), ctypes.byref(opts),
+                                         ctypes.byref(plain)) == 0
+    assert N.lib.ss_batch_learned_workspace_size(ctypes.byref(b), ctypes.byref(opts),
+                                                 ctypes.byref(learned)) == 0
+    # the batch's workspace, the network's and both start vectors (FP64)
+    assert learned.value >= plain.value + 8 * (300 + 70 + 200 + 90)
+    ws_bytes, want = learned.value, N.SS_E_INVALID_ARG
+    if change == "none":
+        return
+    if change == "init":
+        opts.init_log_u = 4096
+    elif change == "mlp":
+        mlp.bf16 = None
+    elif change == "d2":
+        b.d = 2
+    elif change == "small_ws":
+        ws_bytes, want = learned.value - 256, N.SS_E_WORKSPACE
+    elif change == "schedule":
+        sched = N.SsSchedule(8, 128)
+    elif change == "cost":
+        opts.cost = 7
+    res = (N.SsResult * 2)()
+    assert N.lib.spar_sink_batched_learned(ctypes.byref(b), ctypes.byref(opts),
+                                           ctypes.byref(sched) if sched is not None else None,
+                                           ctypes.byref(mlp), ctypes.c_void_p(4096), ws_bytes,
+                                           None, res) == want
+
+
 def _ibp_problem(N, n=8, d=2, count=2, w=(0.5, 0.5)):
     warr = (ctypes.c_double * len(w))(*w)
     prob = N.SsIbpProblem(n, d, count, ctypes.c_void_p(16), ctypes.c_void_p(16),

@@ -236,3 +236,40 @@ def test_poor_finite_start_is_judged_worse_than_plain(api):
     for c, w in zip(cold, warm):
         assert w.warm_start == 1 and w.status == 0 and w.iters <= 1
         assert abs(w.estimate - c.estimate) <= 1e-9 * abs(c.estimate)
+
+
+def _same_solve(a, b):
+    for k, (x, y) in enumerate(zip(a, b)):
+        assert (x.status, x.iters, x.nnz, x.warm_start) == (y.status, y.iters, y.nnz,
+                                                            y.warm_start), k
+        assert x.estimate == y.estimate and x.marginal_err == y.marginal_err, k
+        assert torch.equal(x.u, y.u) and torch.equal(x.v, y.v), k
+
+
+@pytest.mark.parametrize("corrupt", [False, True])
+def test_overlapped_learned_solve_equals_two_calls(api, corrupt):
+    # spar_sink_batched_learned predicts on a second stream beside the
+    # sampling stage; the loop must read the finished prediction, so the
+    # result is the one of predict followed by spar_sink_batched, bit for bit:
+    # on the current stream, then on another one with a smaller batch
+    flat = api.WarmStartNet(seed=7).weights().copy()
+    if corrupt:
+        flat[-1] = np.nan  # every prediction NaN: each problem falls back
+    net = api.WarmStartNet(flat)
+    other = torch.cuda.Stream()
+    kw = dict(eps=0.05, seed=0, schedule=(8, 256), tol=1e-6, max_iter=1000, precision="f32",
+              return_scalings=True)
+    for count, seed, stream in ((24, 2300, None), (9, 2301, other)):
+        B = api.Batch.from_problems(W.batch_ot(count, seed=seed, n_lo=200, n_hi=1200))
+        lu, lv = net.predict(B, eps=0.05)
+        rc2, two = api.spar_sink_batched(B, init_log_u=lu, init_log_v=lv, **kw)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            rc1, one = api.spar_sink_batched_learned(B, net, stream=stream, **kw)
+        torch.cuda.synchronize()
+        assert rc1 == rc2 and rc1 >= 0
+        _same_solve(one, two)
+        if corrupt:
+            assert all(r.warm_start == 0 for r in one)
+        print(f"{count} problems: prediction kept for "
+              f"{sum(r.warm_start == 1 for r in one)}")
