@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched workload (profiling runs)")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched workload on the library's default schedule (counter runs)")
     ap.add_argument("--warmstart-train", type=int, default=100_000,
                     help="training problems for the learned warm start (0: skip)")
     ap.add_argument("--warmstart-only", action="store_true")
@@ -134,7 +136,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 2 ** 30, "copy_bytes_written": 2 ** 30, "copies": 3}))
 
 
-def batched_bench(count: int, steps: int) -> dict:
+def batched_bench(count: int, steps: int, autotune: bool = True) -> dict:
     """512 OT problems, n_k = m_k ~ U{256..4096}, d = 3, Dirichlet weights,
     eps = 0.05, s_k = 8 n_k ln n_k, FP32, tol 1e-6 with at most 1000 iterations
     (the paper's cap): one batched solve per step.  A sampled support can
@@ -148,7 +150,10 @@ def batched_bench(count: int, steps: int) -> dict:
     probs = W.batch_ot(count, seed=0)
     B = A.Batch.from_problems(probs)
     t0 = time.perf_counter()
-    sched, cand = A.ss_autotune_batched(B, eps=0.05, seed=0, precision="f32")
+    if autotune:
+        sched, cand = A.ss_autotune_batched(B, eps=0.05, seed=0, precision="f32")
+    else:
+        sched, cand = (8, 1024), {}
     t_tune = time.perf_counter() - t0
     kw = dict(eps=0.05, tol=1e-6, max_iter=1000, seed=0, precision="f32", schedule=sched)
     A.spar_sink_batched(B, **kw)  # warm-up
@@ -180,7 +185,7 @@ def batched_bench(count: int, steps: int) -> dict:
             "autotune_s": t_tune, "candidates_ms": {f"{l}x{b}": v for (l, b), v in cand.items()},
             "stage_ms": {"sample": res[0].t_sample_ms, "iterate": t_iter,
                          "objective": res[0].t_obj_ms},
-            "loop_GBps": gbps, "loop_frac_of_8TBps": gbps / HBM_PEAK_GBPS,
+            "loop_bytes": moved, "loop_GBps": gbps, "loop_frac_of_8TBps": gbps / HBM_PEAK_GBPS,
             "converged": int(np.sum(res.column("status") == 0)),
             "max_marginal_err": float(res.column("marginal_err").max())}
 
@@ -631,7 +636,7 @@ def main():
     if args.batched_only:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps({"batched": batched_bench(args.batch_count, args.steps)}))
+        print(json.dumps({"batched": batched_bench(args.batch_count, args.steps, not args.no_autotune)}))
         return
     if args.divergence_only:
         import torch
