@@ -745,7 +745,26 @@ hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrin
 //     their bit in the wave's own words of the tile.
 // An entry that the filter drops has hi >= 2^16 P, so U >= P: it is never
 // kept.  The mask is therefore the same as a pair-by-pair evaluation's.
+// WFR (which takes no shrinkage): the filter also bounds the cost factor, F <= 2^-t
+// with t = z^2 inv_tau log2(e) (uot_bound_exponent), from an FP32 squared
+// distance c32 with its rounding taken out, c >= c32 (1 - 2^-20) - 2^-20
+// (|x|^2 + |y|^2) (coordinates rounded to FP32, differences and the sum
+// rounded); with log2 hi >= e + m for hi = 2^e (1 + m) (read off the bits of
+// hi as a float), an entry is a candidate only if hi = 0 or
+// e + m + t < log2(2^16 P) (both sides bounded outward), which drops the
+// pairs whose cost factor rules them out before the exact decision (about
+// 70 in 71 of the cost-free candidates at the WFR workload's sparsity).
 // A list entry is 32 bits: row (4), slot of the wave (4), lane (6), high half.
+// An FP32 upper bound of log2 v for a double v (+ 2^-8 for the rounding of
+// the conversion and of v_log_f32); -inf for v <= 0 and NaN.
+__device__ __forceinline__ float log2_up(double v) {
+    if (!(v > 0.0)) return -INFINITY;
+    if (v == INFINITY) return INFINITY;
+    int e;
+    const double f = frexp(v, &e);  // f in [1/2, 1)
+    return (float)e + __builtin_amdgcn_logf((float)f) + 0x1p-8f;
+}
+
 constexpr int kMaskRows = 16;
 constexpr int kMaskCand = 1024;  // list entries per wave (>= 512 + one row's 512)
 
@@ -782,6 +801,26 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
         lp.cost = pp.cost == SS_COST_SQEUCLID ? SS_COST_SQEUCLID : SS_COST_SQEUCLID_MAXNORM;
     uint32_t* const list = cand[wv];
     int cnt = 0;  // wave-uniform
+    // WFR (no shrinkage: the host rejects it with this cost): lane r < 16
+    // holds row r's FP32 coordinates, its rounding term -2^-20 |x|^2 and an
+    // upper bound of log2 of its factor (the kernels of a fixed dimension;
+    // D = 0 reads pp.d at run time and keeps the cost-free filter)
+    constexpr bool kCfb = WFR && D > 0;
+    constexpr int CD = kCfb ? D : 1;
+    float xr_l[CD], nxs_l = 0.0f, lr_l = -INFINITY;
+    float alpha = 0.0f;
+    if constexpr (kCfb) {
+        float nx = 0.0f;
+#pragma unroll
+        for (int k = 0; k < CD; ++k) {
+            xr_l[k] = lane < nrows ? (float)pp.x[(row0 + lane) * D + k] : 0.0f;
+            nx = fmaf(xr_l[k], xr_l[k], nx);
+        }
+        nxs_l = -0x1p-20f * nx;
+        lr_l = log2_up(rowv);
+        // t per unit squared distance, rounded down
+        alpha = (float)(pp.wfr_w * pp.wfr_w * pp.inv_tau * kLog2e) * (1.0f - 0x1p-20f);
+    }
     const int64_t g_end = (W + 7) / 8;  // hash groups of 512 columns (8 words)
     const int64_t g_first = ct * 8 + wv * 2;
     const int ng = (int)(g_end - g_first < 2 ? (g_end - g_first > 0 ? g_end - g_first : 0) : 2);
@@ -796,16 +835,55 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
             const int64_t j = 512 * g + 64 * s + lane;
             cf[s] = j < m ? csrc[j] : -INFINITY;
         }
+        // cost-factor bound data of the lane's eight columns (WFR)
+        float yc[8][CD], nys[8], lcol[8];
+        if constexpr (kCfb) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int64_t j = 512 * g + 64 * s + lane;
+                float ny = 0.0f;
+#pragma unroll
+                for (int k = 0; k < CD; ++k) {
+                    yc[s][k] = j < m ? (float)pp.y[j * D + k] : 0.0f;
+                    ny = fmaf(yc[s][k], yc[s][k], ny);
+                }
+                nys[s] = -0x1p-20f * ny;
+                lcol[s] = log2_up(cf[s]);
+            }
+        }
         for (int r = 0; r < nrows; ++r) {
             const int64_t i = row0 + r;
             const uint32_t lo = __builtin_amdgcn_readlane((int)__double2loint(rowv), r);
             const uint32_t hi = __builtin_amdgcn_readlane((int)__double2hiint(rowv), r);
             const double rowf = __hiloint2double((int)hi, (int)lo);
             const Words4 h = philox10(q, (uint32_t)i, pp.problem_index, 0u, pp.k0, pp.k1);
+            float xr[CD], nxs = 0.0f, lr = 0.0f;
+            if constexpr (kCfb) {
+#pragma unroll
+                for (int k = 0; k < CD; ++k)
+                    xr[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xr_l[k]), r));
+                nxs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(nxs_l), r));
+                lr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lr_l), r));
+            }
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 const uint32_t hs = coarse_half(h, s);
-                const bool c = (double)hs < fma(rowf, cf[s], pcf);
+                bool c;
+                if constexpr (kCfb) {
+                    float c32 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < CD; ++k) {
+                        const float dk = xr[k] - yc[s][k];
+                        c32 = fmaf(dk, dk, c32);
+                    }
+                    const float clo = fmaf(c32, 1.0f - 0x1p-20f, nxs + nys[s]);
+                    // e + m of hs (as an unsigned float, exact below 2^24) plus t
+                    const float bits = (float)__float_as_uint((float)hs);
+                    const float v = fmaf(bits, 0x1p-23f, fmaf(alpha, clo, -127.0f));
+                    c = v < lr + lcol[s] || hs == 0u;
+                } else {
+                    c = (double)hs < fma(rowf, cf[s], pcf);
+                }
                 const uint64_t bal = __ballot(c);
                 if (bal) {
                     if (c) {

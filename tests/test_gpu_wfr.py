@@ -74,6 +74,26 @@ def test_sample_wfr(api, pattern, ratio):
     assert np.all(np.isfinite(g["val"].cpu().numpy())) and np.all(g["val"].cpu().numpy() > 0)
 
 
+@pytest.mark.parametrize("n,m,d,s_factor", [(2100, 1337, 5, 8.0), (700, 4500, 5, 40.0),
+                                             (900, 611, 3, 8.0)])
+def test_sample_wfr_filter(api, n, m, d, s_factor):
+    # The mask kernel's filter bounds the WFR cost factor in FP32 before the
+    # exact decision; the mask must still be the pair-by-pair one: bit for
+    # bit with the oracle's, over many row tiles, two column tiles and ragged
+    # edges, and at a budget where a third of the pairs are kept.
+    p = W.wfr_synthetic(max(n, m), d=d, seed=23, pattern="C1", nnz_ratio=0.5,
+                        s_factor=s_factor)
+    p = W.Problem(p.x[:n], p.y[:m], p.a[:n] * (5.0 / p.a[:n].sum()),
+                  p.b[:m] * (3.0 / p.b[:m].sum()), eps=p.eps, s=p.s, lam=p.lam, seed=p.seed,
+                  name=p.name, meta=p.meta)
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    assert sk.nnz > 1000
+    ge = api.ss_sample(_prob(api, p), **_kw(p), z_in=sk.prob.z, precision="f64")
+    assert np.array_equal(ge["mask"].cpu().numpy().view(np.uint64), sk.mask)
+    for k in ("row_ptr", "col_idx", "col_ptr", "row_idx", "val", "val_t"):
+        assert np.array_equal(ge[k].cpu().numpy(), getattr(sk, k)), k
+
+
 @pytest.mark.parametrize("lam,eps", [(5.0, 0.1), (0.02, 0.05), (0.1, 0.1)])
 def test_wfr_normaliser_exponents(api, lam, eps):
     # the device evaluates cos(z)^(2/(2 lam + eps)) from a series in z^2; the
