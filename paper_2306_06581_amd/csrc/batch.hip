@@ -356,53 +356,75 @@ hipError_t launch_batch_iterate(int precision, int lanes, int block, int grid, c
 // ------------------------------------------------------------------ estimate
 // One block per problem, 16 lanes per row: sum T~ C, sum T~ (log T~ - 1) and
 // sum T~ (log u + log v - 1) over the kept entries (Alg. 3; 0 log 0 = 0).
+// With log T~ = log u + log v + log K~ the second is the third plus
+// sum T~ log K~, so an entry takes one logarithm (the specified one); log v
+// is formed once per column.
 constexpr int kBObjLanes = 16;
+constexpr int kBObjUnroll = 4;  // entries a lane loads before using any
 
 // Block (k, b) of kBObjSplit per problem sums rows b, b + kBObjSplit, ... of
 // problem k (in groups of blockDim / kBObjLanes rows) into its partials.  The
-// problem's v is staged in LDS (the entries gather it at random columns).
+// problem's v and log v are staged in LDS (the entries gather them at random
+// columns).
 template <int PREC, int D>
 __global__ __launch_bounds__(256) void k_b_objective(BObjArgs A) {
     typedef typename BTypes<PREC>::V V;
     __shared__ double sh[16];
-    __shared__ double vs[SS_BATCH_MAX_SIDE];
+    __shared__ V vs[SS_BATCH_MAX_SIDE];
+    __shared__ double lvs[SS_BATCH_MAX_SIDE];
     if (A.row_ptr[A.rows] > A.cap || A.col_ptr[A.cols] > A.cap) return;
     const int k = blockIdx.x / kBObjSplit, blk = blockIdx.x % kBObjSplit;
     const BProb P = A.prob[k];
-    for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x) vs[j] = (double)((const V*)A.v)[P.yo + j];
+    for (int64_t j = threadIdx.x; j < P.m; j += blockDim.x) {
+        const V v = ((const V*)A.v)[P.yo + j];
+        vs[j] = v;
+        lvs[j] = log_spec((double)v);
+    }
     __syncthreads();
     const int sub = threadIdx.x % kBObjLanes;
     const double inv_cmax = A.stat[k].inv_cmax;
-    const V* u = (const V*)A.u + P.xo;
-    const V* val = (const V*)A.val;
-    const double* x = A.x + P.xo * A.d;
-    const double* y = A.y + P.yo * A.d;
+    const V* __restrict__ u = (const V*)A.u + P.xo;
+    const V* __restrict__ val = (const V*)A.val;
+    const uint16_t* __restrict__ cidx = A.col_idx;
+    const double* __restrict__ x = A.x + P.xo * A.d;
+    const double* __restrict__ y = A.y + P.yo * A.d;
     constexpr int RPB = 256 / kBObjLanes;  // rows in flight per block
-    double s_tc = 0.0, s_ent = 0.0, s_sp = 0.0;
+    double s_tc = 0.0, s_lk = 0.0, s_sp = 0.0;
     for (int64_t r = (int64_t)blk * RPB + threadIdx.x / kBObjLanes; r < P.n;
          r += (int64_t)kBObjSplit * RPB) {
         const int64_t k0 = A.row_ptr[P.xo + r], k1 = A.row_ptr[P.xo + r + 1];
         const double ur = (double)u[r];
-        const double lu = log(ur);
-        for (int64_t e = k0 + sub; e < k1; e += kBObjLanes) {
-            const int64_t o = A.col_idx[e];
-            const double vo = vs[o];
-            const double t = ur * (double)val[e] * vo;
-            if (t > 0.0) {
-                const double c = sqdist<D>(x + r * A.d, y + o * A.d, A.d) * inv_cmax;
-                s_tc += t * c;
-                s_ent += t * (log(t) - 1.0);
-                s_sp += t * ((lu + log(vo)) - 1.0);
+        const double lu = log_spec(ur);
+        for (int64_t e0 = k0 + sub; e0 < k1; e0 += kBObjUnroll * kBObjLanes) {
+            int o[kBObjUnroll];
+            V kv[kBObjUnroll];
+#pragma unroll
+            for (int q = 0; q < kBObjUnroll; ++q) {
+                const int64_t e = e0 + q * kBObjLanes;
+                const bool in = e < k1;
+                o[q] = in ? (int)cidx[e] : 0;
+                kv[q] = in ? val[e] : (V)0;
+            }
+#pragma unroll
+            for (int q = 0; q < kBObjUnroll; ++q) {
+                const double vo = (double)vs[o[q]];
+                const double t = ur * (double)kv[q] * vo;
+                if (t > 0.0) {
+                    const double c = sqdist<D>(x + r * A.d, y + o[q] * A.d, A.d) * inv_cmax;
+                    s_tc += t * c;
+                    s_lk += t * log_spec((double)kv[q]);
+                    s_sp += t * ((lu + lvs[o[q]]) - 1.0);
+                }
             }
         }
     }
     s_tc = block_sum(s_tc, sh);
-    s_ent = block_sum(s_ent, sh);
+    s_lk = block_sum(s_lk, sh);
     s_sp = block_sum(s_sp, sh);
     if (threadIdx.x == 0) {
         double* pt = A.part + ((int64_t)k * kBObjSplit + blk) * 3;
         pt[0] = s_tc;
-        pt[1] = s_ent;
+        pt[1] = s_sp + s_lk;
         pt[2] = s_sp;
     }
 }
