@@ -1623,30 +1623,65 @@ __global__ __launch_bounds__(256) void k_b_owner(BatchArgs A) {
         A.owner[A.rows + l] = k;
 }
 
-// Batched fill in two passes, one wave per line (a batch line has at most
-// 64 mask words: SS_BATCH_MAX_SIDE = 4096).  Index pass: one word per lane,
-// the prefix-popcount, local indices in ascending order.
+// Batched fill in two passes (a batch line has at most 64 mask words:
+// SS_BATCH_MAX_SIDE = 4096).  Index pass: the prefix-popcount over a line's
+// words gives its local indices in ascending order; kBIdxLines lines per
+// wave, 16 lanes a line and four words a lane, so a wave runs four lines'
+// chains of dependent loads (owner, problem, words, offset) at once.
+constexpr int kBIdxLines = 4;
+
 template <int ROLE>
 __global__ __launch_bounds__(256) void k_b_fill_idx(BatchArgs A) {
+    constexpr int LL = kWave / kBIdxLines;  // lanes a line
+    constexpr int WPL = kWave / LL;         // words a lane
+    static_assert(LL * WPL == 64 && SS_BATCH_MAX_SIDE <= 64 * 64, "a line's words fit its lanes");
     const int lane = threadIdx.x & (kWave - 1);
+    const int sub = lane % LL;
     const int64_t lines = ROLE == 0 ? A.rows : A.cols;
-    const int64_t L = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (L >= lines) return;  // the whole wave
-    const int k = A.owner[(ROLE == 0 ? 0 : A.rows) + L];
-    const BProb P = A.prob[k];
-    const int64_t local = L - (ROLE == 0 ? A.row_off : A.col_off)[k];
-    const int64_t words = ROLE == 0 ? P.W : P.Wn;
-    const uint64_t* bits = ROLE == 0 ? A.mask + P.mo + local * P.W : A.maskT + P.mto + local * P.Wn;
-    uint64_t word = lane < words ? bits[lane] : 0ull;
-    const int c = __popcll(word);
-    const int incl = wave_inclusive_scan(c);
-    int64_t pos = (ROLE == 0 ? A.row_ptr : A.col_ptr)[L] + (incl - c);
+    const int64_t L = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kBIdxLines + lane / LL;
+    // lanes of a line past the end take part in the scan with no words
+    const bool live = L < lines;
+    uint64_t w[WPL];
+    int64_t base = 0;
+    if (live) {
+        const int k = A.owner[(ROLE == 0 ? 0 : A.rows) + L];
+        const BProb P = A.prob[k];
+        const int64_t local = L - (ROLE == 0 ? A.row_off : A.col_off)[k];
+        const int64_t words = ROLE == 0 ? P.W : P.Wn;
+        const uint64_t* bits =
+            ROLE == 0 ? A.mask + P.mo + local * P.W : A.maskT + P.mto + local * P.Wn;
+        base = (ROLE == 0 ? A.row_ptr : A.col_ptr)[L];
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) {
+            const int wi = sub * WPL + q;
+            w[q] = wi < words ? bits[wi] : 0ull;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) w[q] = 0ull;
+    }
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) c += __popcll(w[q]);
+    // inclusive scan over the line's lanes (every lane of the wave takes part)
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < LL; d <<= 1) {
+        const int t = __shfl_up(incl, d, LL);
+        if (sub >= d) incl += t;
+    }
+    int64_t pos = base + (incl - c);
     uint16_t* idx = ROLE == 0 ? A.col_idx : A.row_idx;
-    while (word) {
-        const int b = __ffsll((unsigned long long)word) - 1;
-        word &= word - 1;
-        if (pos < A.cap) idx[pos] = (uint16_t)(64 * lane + b);
-        ++pos;
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) {
+        uint64_t word = w[q];
+        const int col0 = 64 * (sub * WPL + q);
+        while (word) {
+            const int b = __ffsll((unsigned long long)word) - 1;
+            word &= word - 1;
+            if (pos < A.cap) idx[pos] = (uint16_t)(col0 + b);
+            ++pos;
+        }
     }
 }
 
@@ -1748,7 +1783,8 @@ static void run_b_cmax(const BatchArgs& a, int64_t nt, hipStream_t st) {
 
 template <int PREC, int D>
 static void run_b_fill(const BatchArgs& a, hipStream_t st) {
-    const dim3 gr((unsigned)((a.rows + 3) / 4)), gc((unsigned)((a.cols + 3) / 4));
+    constexpr int64_t pi = 4 * kBIdxLines;  // lines per block of the index pass
+    const dim3 gr((unsigned)((a.rows + pi - 1) / pi)), gc((unsigned)((a.cols + pi - 1) / pi));
     constexpr int64_t per = 4 * kBValLines;  // lines per block of the value pass
     const dim3 vr((unsigned)((a.rows + per - 1) / per)), vc((unsigned)((a.cols + per - 1) / per));
     hipLaunchKernelGGL((k_b_fill_idx<0>), gr, dim3(256), 0, st, a);
