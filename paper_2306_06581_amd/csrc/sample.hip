@@ -1548,11 +1548,44 @@ __global__ __launch_bounds__(1024) void k_b_cmax(BatchArgs A) {
     __syncthreads();
     const int ns = nsurv;
     double mx = L;
-    for (int q = 0; q < ns; ++q) {
-        const int64_t i = surv[q];
-        for (int64_t j = tid; j < P.m; j += 1024) {
-            const double c = sqdist<D>(x + i * d, y + j * d, d);
-            mx = c > mx ? c : mx;
+    if constexpr (D > 0) {
+        // each thread keeps its (at most four) columns in registers; the
+        // survivors' coordinates go through LDS (v is free now) in chunks and
+        // are read as broadcasts, so the scan has no global load in its loop
+        constexpr int kCols = kBatchMaxSide / 1024;
+        double yr[kCols][D];
+#pragma unroll
+        for (int t = 0; t < kCols; ++t) {
+            const int64_t j = tid + 1024 * t;
+#pragma unroll
+            for (int c = 0; c < D; ++c) yr[t][c] = j < P.m ? y[j * D + c] : 0.0;
+        }
+        constexpr int cap = kBatchMaxSide / D;  // survivors per chunk
+        for (int q0 = 0; q0 < ns; q0 += cap) {
+            const int nq = ns - q0 < cap ? ns - q0 : cap;
+            __syncthreads();  // v's previous contents are read
+            for (int e = tid; e < nq * D; e += 1024) v[e] = x[(int64_t)surv[q0 + e / D] * D + e % D];
+            __syncthreads();
+            for (int q = 0; q < nq; ++q) {
+                double xi[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) xi[c] = v[q * D + c];
+#pragma unroll
+                for (int t = 0; t < kCols; ++t) {
+                    if (tid + 1024 * t < P.m) {
+                        const double c = sqdist<D>(xi, yr[t], D);
+                        mx = c > mx ? c : mx;
+                    }
+                }
+            }
+        }
+    } else {
+        for (int q = 0; q < ns; ++q) {
+            const int64_t i = surv[q];
+            for (int64_t j = tid; j < P.m; j += 1024) {
+                const double c = sqdist<D>(x + i * d, y + j * d, d);
+                mx = c > mx ? c : mx;
+            }
         }
     }
     mx = block_max1024(mx, sh);
