@@ -1125,7 +1125,8 @@ void build_batch_tables(const ss_batch* B, BHost* H) {
         H->ro[k + 1] = H->ro[k] + P.n;
         H->co[k + 1] = H->co[k] + P.m;
         H->tc[k + 1] = H->tc[k] + ((P.n + 255) / 256) * ((P.m + 2047) / 2048);
-        H->tm[k + 1] = H->tm[k] + ((P.n + 15) / 16) * ((P.W + 63) / 64);
+        const int64_t rows_per_tile = 16 * batch_mask_split(P.W);
+        H->tm[k + 1] = H->tm[k] + ((P.n + rows_per_tile - 1) / rows_per_tile) * ((P.W + 63) / 64);
         H->tt[k + 1] = H->tt[k] + ((P.Wn + 7) / 8) * ((P.W + 15) / 16);
     }
     // longest first: entries grow with s, iterations roughly with size

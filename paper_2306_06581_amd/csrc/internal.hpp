@@ -383,6 +383,11 @@ hipError_t launch_dense_objective(const DenseObjArgs& a, hipStream_t st);
 // ---- batches (sample.hip: sampling stages; batch.hip: loop, objective)
 constexpr int kBatchMaxSide = 4096;
 
+// 16-row blocks of one batched mask tile: a tile's four waves each cover 16
+// words of a row, so a problem whose rows have at most 16 (32) words gives
+// the spare waves further row blocks, 4 (2) per tile.
+__host__ __device__ constexpr int batch_mask_split(int64_t W) { return W <= 16 ? 4 : W <= 32 ? 2 : 1; }
+
 // Per problem, written by the host.
 struct BProb {
     int64_t n, m;      // points of x and y

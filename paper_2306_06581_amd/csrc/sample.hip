@@ -768,18 +768,24 @@ __device__ __forceinline__ float log2_up(double v) {
 constexpr int kMaskRows = 16;
 constexpr int kMaskCand = 1024;  // list entries per wave (>= 512 + one row's 512)
 
-// One tile: rows row0 .. row0 + 15 of one problem, mask words ct * 64 ..
-// ct * 64 + 63; adds the popcounts to row_cnt.  All 256 threads call it.
-// `cand` holds kMaskCand entries per wave.  WFR = false: the cost is not the
-// WFR cost (its cosine and logarithm are left out of the kernel).
+// One tile: rows rt * 16 split .. + 16 split - 1 of one problem, mask words
+// ct * 64 .. ct * 64 + 63; adds the popcounts to row_cnt.  All 256 threads
+// call it.  With split = 1 every wave takes the tile's 16 rows and 16 of its
+// words; with split = 2 or 4 (rows of at most 32 or 16 words) 4 / split waves
+// cover a row's words and the waves take split blocks of 16 rows.  `cand`
+// holds kMaskCand entries per wave.  WFR = false: the cost is not the WFR
+// cost (its cosine and logarithm are left out of the kernel).
 template <bool UOT, int D, bool WFR>
 __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64_t m, int64_t W,
-                                          int64_t rt, int64_t ct, uint64_t* __restrict__ mask,
+                                          int64_t rt, int64_t ct, int split,
+                                          uint64_t* __restrict__ mask,
                                           int32_t* __restrict__ row_cnt, double kappa,
                                           uint64_t (*tile)[64], uint32_t (*cand)[kMaskCand]) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
-    const int64_t row0 = rt * kMaskRows;
-    const int nrows = (int)(n - row0 < kMaskRows ? n - row0 : kMaskRows);
+    const int wpr = 4 / split;  // waves across a row's words
+    const int cp = wv % wpr;    // this wave's 16-word part of the row
+    const int64_t row0 = rt * kMaskRows * split + (wv / wpr) * kMaskRows;
+    const int nrows = (int)(n - row0 < kMaskRows ? (n - row0 > 0 ? n - row0 : 0) : kMaskRows);
     // the wave's 16 words of each row start empty
 #pragma unroll
     for (int e = lane; e < kMaskRows * 16; e += kWave) tile[e >> 4][wv * 16 + (e & 15)] = 0;
@@ -822,7 +828,7 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
         alpha = (float)(pp.wfr_w * pp.wfr_w * pp.inv_tau * kLog2e) * (1.0f - 0x1p-20f);
     }
     const int64_t g_end = (W + 7) / 8;  // hash groups of 512 columns (8 words)
-    const int64_t g_first = ct * 8 + wv * 2;
+    const int64_t g_first = ct * 8 + cp * 2;
     const int ng = (int)(g_end - g_first < 2 ? (g_end - g_first > 0 ? g_end - g_first : 0) : 2);
     for (int gg = 0; gg < ng; ++gg) {
         const int64_t g = g_first + gg;
@@ -953,17 +959,36 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
         }
     }
     __syncthreads();
+    if (split == 1) {
+        // a row's 64 words from the four waves' parts, one row per instruction
 #pragma unroll
-    for (int rr = 0; rr < kMaskRows / 4; ++rr) {
-        const int r = wv + 4 * rr;
-        const int64_t i = row0 + r;
-        if (i >= n) continue;
-        const int64_t widx = ct * 64 + lane;
-        const uint64_t w = tile[r][lane];
-        if (widx < W) mask[i * W + widx] = w;
-        int c = (widx < W) ? __popcll(w) : 0;
-        c = group_sum<kWave>(c);
-        if (lane == 0 && c) atomicAdd(&row_cnt[i], c);
+        for (int rr = 0; rr < kMaskRows / 4; ++rr) {
+            const int r = wv + 4 * rr;
+            const int64_t i = row0 + r;
+            if (i >= n) continue;
+            const int64_t widx = ct * 64 + lane;
+            const uint64_t w = tile[r][lane];
+            if (widx < W) mask[i * W + widx] = w;
+            int c = (widx < W) ? __popcll(w) : 0;
+            c = group_sum<kWave>(c);
+            if (lane == 0 && c) atomicAdd(&row_cnt[i], c);
+        }
+    } else {
+        // each wave writes its own 16 rows x 16 words, four rows per
+        // instruction, and adds its part of each row's count (integer adds:
+        // the order does not matter)
+#pragma unroll
+        for (int rr = 0; rr < kMaskRows / 4; ++rr) {
+            const int r = 4 * rr + lane / 16;
+            const int64_t i = row0 + r;
+            const int64_t widx = ct * 64 + cp * 16 + (lane & 15);
+            const bool ok = i < n && widx < W;
+            const uint64_t w = tile[r][wv * 16 + (lane & 15)];
+            if (ok) mask[i * W + widx] = w;
+            int c = ok ? __popcll(w) : 0;
+            c = group_sum<16>(c);
+            if ((lane & 15) == 0 && c) atomicAdd(&row_cnt[i], c);
+        }
     }
 }
 
@@ -980,7 +1005,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     __shared__ uint32_t cand[4][kMaskCand];
     const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
     const double kappa = UOT ? pp.shrink_w * (pp.s / stats[ST_Z]) : 0.0;
-    mask_tile<UOT, D, false>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile, cand);
+    mask_tile<UOT, D, false>(pp, n, m, W, rt, ct, 1, mask, row_cnt, kappa, tile, cand);
 }
 
 template <int D>
@@ -992,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_mask_wfr(ProbParams pp, int64_t n, int6
     __shared__ uint32_t cand[4][kMaskCand];
     const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
     const double kappa = pp.shrink_w * (pp.s / stats[ST_Z]);
-    mask_tile<true, D, true>(pp, n, m, W, rt, ct, mask, row_cnt, kappa, tile, cand);
+    mask_tile<true, D, true>(pp, n, m, W, rt, ct, 1, mask, row_cnt, kappa, tile, cand);
 }
 
 template <bool UOT, int D, bool WFR>
@@ -1633,8 +1658,8 @@ __global__ __launch_bounds__(256) void k_b_mask(BatchArgs A) {
     pp.problem_index = P.pidx;
     pp.k0 = A.k0;
     pp.k1 = A.k1;
-    mask_tile<false, 2, false>(pp, P.n, P.m, P.W, t / nct, t % nct, A.mask + P.mo, A.row_cnt + P.xo, 0.0,
-                        tile, cand);
+    mask_tile<false, 2, false>(pp, P.n, P.m, P.W, t / nct, t % nct, batch_mask_split(P.W),
+                               A.mask + P.mo, A.row_cnt + P.xo, 0.0, tile, cand);
 }
 
 __global__ __launch_bounds__(256) void k_b_transpose(BatchArgs A) {
