@@ -534,6 +534,8 @@ int stage_start(Ctx& c) {
     if (c.uot)
         HIP_TRY(launch_center_radii(P->x, P->y, P->n, P->m, P->d, at<void>(c.ws, c.L.tmp),
                                     at<double>(c.ws, c.L.zcenter), stats, c.st));
+    if (c.uot && c.O->cost == SS_COST_WFR)
+        HIP_TRY(launch_same_support(P->x, P->y, P->n, P->m, P->d, stats, c.st));
     HIP_TRY(hipMemcpyAsync(c.stats, stats, sizeof(c.stats), hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     if (c.stats[ST_BAD_INPUT] != 0.0)
@@ -618,7 +620,8 @@ int stage_sample(Ctx& c) {
             HIP_TRY(launch_uot_zexp(za, stats, st));
         } else {
             HIP_TRY(launch_uot_z(pp, n, m, pp.col_bnd, c.stats[ST_CMAX],
-                                 at<double>(ws, c.L.partials), tree, stats, st));
+                                 c.stats[ST_SAME_SUPPORT] != 0.0, at<double>(ws, c.L.partials),
+                                 tree, stats, st));
         }
         if (c.z_in > 0.0) HIP_TRY(launch_fill_f64(stats + ST_Z, 1, c.z_in, st));
         HIP_TRY(launch_uot_bounds(pp.col_fac, m, O->s, pp.shrink_w, stats, (double*)pp.col_bnd,

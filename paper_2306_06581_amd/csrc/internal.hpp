@@ -46,6 +46,7 @@ enum StatSlot {
     ST_EMPTY_COLS,
     ST_RX2,         // max_i |x_i - c|^2 about the cost-scan centre c
     ST_RY2,         // max_j |y_j - c|^2
+    ST_SAME_SUPPORT,  // WFR normaliser: 1 when n = m and y is x bit for bit, else 0
     ST_COUNT = 32
 };
 
@@ -170,8 +171,14 @@ hipError_t launch_uot_prep(const double* a, const double* b, int64_t n, int64_t 
                            hipStream_t st);
 // Z (eq. (pij-uot) normaliser) into stats[ST_Z]; eb_j = exp(col_fac_j); cmax
 // is the cost maximum (chooses the short-range exponential when it applies).
+// same_support: stats[ST_SAME_SUPPORT] as read by the host (WFR: only the
+// pairs j >= i are evaluated).
 hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* eb, double cmax,
-                        double* partials, double* scratch, double* stats, hipStream_t st);
+                        bool same_support, double* partials, double* scratch, double* stats,
+                        hipStream_t st);
+// stats[ST_SAME_SUPPORT] = 1 if n = m and y is x bit for bit, else 0.
+hipError_t launch_same_support(const double* x, const double* y, int64_t n, int64_t m, int d,
+                               double* stats, hipStream_t st);
 hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrink_w,
                              const double* stats, double* fb, hipStream_t st);
 hipError_t launch_mask(const ProbParams& pp, int64_t n, int64_t m, uint64_t* mask,

@@ -412,16 +412,24 @@ __global__ __launch_bounds__(256) void k_uot_z(ProbParams pp, int64_t n, int64_t
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// WFR: q = exp(la + lb) cos(z)^(2 inv_tau), cos z from its Taylor series in
+// WFR: q = ea eb cos(z)^(2 inv_tau) (ea = exp(la), eb = exp(lb)), cos z from its Taylor series in
 // t = z^2 = c w^2 < (pi/2)^2 up to t^11 (truncation below 1e-19; no square
 // root, no range reduction).  Blocked pairs (z >= pi/2) add nothing, and
 // neither does a pair whose series rounds to <= 0.  Most pairs are blocked,
 // so the pairs that are not are compacted before the logarithm and
 // exponential: each wave scans its 64 rows against the tile's columns one
-// column at a time, appends the unblocked pairs (t and la + lb) to its own
-// LDS queue in lane order (a ballot and prefix count: a fixed order), and
-// whenever 64 are queued every lane evaluates one.  Sums stay in a fixed
+// column at a time, appends the unblocked pairs (t and the weight ea eb) to
+// its own LDS queue in lane order (a ballot and prefix count: a fixed order),
+// and whenever 64 are queued every lane evaluates one.  Sums stay in a fixed
 // order for a given launch shape.
+//
+// Same support (SYM: n = m and y equal to x bit for bit, checked on the
+// device before the host reads the cost scale): c_ij = c_ji, so Z =
+// sum_i ea_i eb_i + sum_{i<j} (ea_i eb_j + ea_j eb_i) cos(z_ij)^(2 inv_tau).
+// The grid holds only the tiles with a pair j >= i (column tile major, its row
+// tiles 0 .. ceil(j1 / 256) - 1 in order, so consecutive blocks, which go to
+// different XCDs, share a column tile), and only pairs j >= i are evaluated:
+// half the scan and half the logarithms and exponentials.
 constexpr double kWfrC[12] = {1.0,
                               1.0 / 2,
                               1.0 / 24,
@@ -435,30 +443,64 @@ constexpr double kWfrC[12] = {1.0,
                               1.0 / 2432902008176640000.0,
                               1.0 / 1124000727777607680000.0};
 
-__device__ __forceinline__ double wfr_q(double t, double s, double k2) {
+__device__ __forceinline__ double wfr_q(double t, double w, double k2) {
     const double u = -t;  // cos z = sum_k u^k / (2k)!
     double p = kWfrC[11];
 #pragma unroll
     for (int k = 10; k >= 0; --k) p = fma(p, u, kWfrC[k]);
     // the specified functions: no special-case paths, about half the
     // instructions of the library's (their 1-3 ulp are far inside the
-    // normaliser's accuracy)
-    return p > 0.0 ? exp_spec(s + k2 * log_spec(p)) : 0.0;
+    // normaliser's accuracy); w is the pair's weight ea eb
+    return p > 0.0 ? w * exp_spec(k2 * log_spec(p)) : 0.0;
+}
+
+// stats[ST_SAME_SUPPORT] = 0 if any coordinate of y differs from x's (bit
+// for bit); launch_same_support sets it to 1 first.  Every writer stores the
+// same value, so the outcome does not depend on their order.
+__global__ void k_same_support(const double* __restrict__ x, const double* __restrict__ y,
+                               int64_t len, double* stats) {
+    bool diff = false;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (int64_t)gridDim.x * blockDim.x)
+        diff = diff || __double_as_longlong(x[e]) != __double_as_longlong(y[e]);
+    if (__syncthreads_or(diff) && threadIdx.x == 0) stats[ST_SAME_SUPPORT] = 0.0;
 }
 
 // Columns per LDS stage of the WFR normaliser: their coordinates and log
 // factors are read once per block, then by every wave as broadcasts.
 constexpr int kZwChunk = 256;
 
-template <int D>
+// Row tiles of column tile ct in the same-support grid.
+__host__ __device__ inline int64_t zw_sym_rows(int64_t ct, int64_t nrt) {
+    const int64_t r = (ct + 1) * (kCostTileCols / 256);
+    return r < nrt ? r : nrt;
+}
+
+template <int D, bool SYM>
 __global__ __launch_bounds__(256) void k_uot_z_wfr(ProbParams pp, int64_t n, int64_t m,
-                                                   int64_t ncol_tiles, double* partials) {
+                                                   int64_t ncol_tiles, const double* __restrict__ ea,
+                                                   const double* __restrict__ eb,
+                                                   double* partials) {
     constexpr int DD = D > 0 ? D : 1;
     __shared__ double sh[4];
     __shared__ double qt[4][128], qs[4][128];
-    __shared__ double ys[kZwChunk][DD + 1];  // coordinates, then the column's log factor
+    __shared__ double ys[kZwChunk][DD + 2];  // coordinates, then the column's eb and ea
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t rt = blockIdx.x / ncol_tiles, ct = blockIdx.x % ncol_tiles;
+    constexpr bool sym = SYM;
+    int64_t rt, ct;
+    if constexpr (SYM) {
+        const int64_t nrt = (n + 255) / 256;
+        int64_t b = blockIdx.x;
+        ct = 0;
+        while (b >= zw_sym_rows(ct, nrt)) {
+            b -= zw_sym_rows(ct, nrt);
+            ++ct;
+        }
+        rt = b;
+    } else {
+        rt = blockIdx.x / ncol_tiles;
+        ct = blockIdx.x % ncol_tiles;
+    }
     const int64_t i = rt * 256 + threadIdx.x;
     const int64_t j0 = ct * kCostTileCols;
     const int64_t j1 = (j0 + kCostTileCols < m) ? j0 + kCostTileCols : m;
@@ -467,7 +509,8 @@ __global__ __launch_bounds__(256) void k_uot_z_wfr(ProbParams pp, int64_t n, int
     const double* xp = pp.x + (live ? i : 0) * pp.d;
 #pragma unroll
     for (int k = 0; k < DD; ++k) xi[k] = D > 0 ? xp[k] : 0.0;
-    const double la = live ? pp.row_fac[i] : 0.0;
+    const double eai = live ? ea[i] : 0.0;
+    const double ebi = live && sym ? eb[i] : 0.0;
     const double w2 = pp.wfr_w * pp.wfr_w;
     const double k2 = 2.0 * pp.inv_tau;
     double acc = 0.0;
@@ -480,13 +523,14 @@ __global__ __launch_bounds__(256) void k_uot_z_wfr(ProbParams pp, int64_t n, int
                 const double* yp = pp.y + (c0 + threadIdx.x) * D;
 #pragma unroll
                 for (int k = 0; k < D; ++k) ys[threadIdx.x][k] = yp[k];
-                ys[threadIdx.x][D] = pp.col_fac[c0 + threadIdx.x];
+                ys[threadIdx.x][D] = eb[c0 + threadIdx.x];
+                ys[threadIdx.x][D + 1] = ea[c0 + threadIdx.x];
             }
             __syncthreads();
         }
         for (int jj = 0; jj < nc; ++jj) {
             const int64_t j = c0 + jj;
-            double c, lb;
+            double c, ebj, eaj;
             if constexpr (D > 0) {
                 // fused: the normaliser needs its sum to 1e-13, not the
                 // mask's operation order (a pair it would block differently
@@ -498,18 +542,20 @@ __global__ __launch_bounds__(256) void k_uot_z_wfr(ProbParams pp, int64_t n, int
                     const double u = xi[k] - ys[jj][k];
                     c = fma(u, u, c);
                 }
-                lb = ys[jj][D];
+                ebj = ys[jj][D];
+                eaj = ys[jj][D + 1];
             } else {
                 c = sqdist<D>(xp, pp.y + j * pp.d, pp.d);
-                lb = pp.col_fac[j];
+                ebj = eb[j];
+                eaj = ea[j];
             }
             const double t = c * w2;
-            const bool on = live && t < kHalfPi * kHalfPi;
+            const bool on = live && t < kHalfPi * kHalfPi && (!sym || j >= i);
             const uint64_t bal = __ballot(on);
             if (on) {
                 const int pos = nq + __popcll(bal & ((1ull << lane) - 1));
                 qt[wv][pos] = t;
-                qs[wv][pos] = la + lb;
+                qs[wv][pos] = !sym || j == i ? eai * ebj : eai * ebj + eaj * ebi;
             }
             nq += __popcll(bal);
             if (nq >= 64) {
@@ -539,31 +585,48 @@ __global__ __launch_bounds__(256) void k_uot_z_wfr(ProbParams pp, int64_t n, int
 
 template <int D>
 static void run_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* eb, double g,
-                      bool short_range, double* partials, int64_t nct, int64_t nrt,
-                      hipStream_t st) {
+                      bool short_range, bool same, double* partials, int64_t nct, int64_t nrt,
+                      int64_t nsym, hipStream_t st) {
     const double eq = exp(-0.25);
     if (short_range)
         hipLaunchKernelGGL((k_uot_z<D, true>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n,
                            m, nct, eb, g, eq, partials);
+    else if (pp.cost == kCostWfr && same)
+        hipLaunchKernelGGL((k_uot_z_wfr<D, true>), dim3((unsigned)nsym), dim3(256), 0, st, pp, n, m,
+                           nct, pp.row_bnd, eb, partials);
     else if (pp.cost == kCostWfr)
-        hipLaunchKernelGGL((k_uot_z_wfr<D>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n,
-                           m, nct, partials);
+        hipLaunchKernelGGL((k_uot_z_wfr<D, false>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st,
+                           pp, n, m, nct, pp.row_bnd, eb, partials);
     else
         hipLaunchKernelGGL((k_uot_z<D, false>), dim3((unsigned)(nct * nrt)), dim3(256), 0, st, pp, n,
                            m, nct, eb, g, eq, partials);
 }
 
+hipError_t launch_same_support(const double* x, const double* y, int64_t n, int64_t m, int d,
+                               double* stats, hipStream_t st) {
+    hipError_t e = launch_fill_f64(stats + ST_SAME_SUPPORT, 1, n == m ? 1.0 : 0.0, st);
+    if (e != hipSuccess) return e;
+    if (n == m && x != y)
+        hipLaunchKernelGGL(k_same_support, dim3(256), dim3(256), 0, st, x, y, n * d, stats);
+    return hipGetLastError();
+}
+
 hipError_t launch_uot_z(const ProbParams& pp, int64_t n, int64_t m, const double* eb, double cmax,
-                        double* partials, double* scratch, double* stats, hipStream_t st) {
+                        bool same_support, double* partials, double* scratch, double* stats,
+                        hipStream_t st) {
     const int64_t nct = (m + kCostTileCols - 1) / kCostTileCols;
     const int64_t nrt = (n + 255) / 256;
     const double g = pp.inv_cmax * pp.inv_tau;
     // the short-range exponential needs the squared Euclidean cost
     const bool short_range = pp.cost != kCostWfr && g * cmax <= 0.5;
-    SS_DISPATCH_D(pp.d, run_uot_z, pp, n, m, eb, g, short_range, partials, nct, nrt, st);
+    const bool same = pp.cost == kCostWfr && same_support && n == m;
+    int64_t nsym = 0;
+    for (int64_t ct = 0; ct < nct; ++ct) nsym += zw_sym_rows(ct, nrt);
+    SS_DISPATCH_D(pp.d, run_uot_z, pp, n, m, eb, g, short_range, same, partials, nct, nrt, nsym,
+                  st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_tree_sum(partials, nct * nrt, scratch, stats + ST_Z, st);
+    return launch_tree_sum(partials, same ? nsym : nct * nrt, scratch, stats + ST_Z, st);
 }
 
 // ------------------------------------------------------------------ Z by expansion

@@ -88,10 +88,29 @@ def test_sample_wfr_filter(api, n, m, d, s_factor):
                   name=p.name, meta=p.meta)
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
     assert sk.nnz > 1000
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    assert g["z_norm"] == pytest.approx(sk.prob.z, rel=1e-13)
     ge = api.ss_sample(_prob(api, p), **_kw(p), z_in=sk.prob.z, precision="f64")
     assert np.array_equal(ge["mask"].cpu().numpy().view(np.uint64), sk.mask)
     for k in ("row_ptr", "col_idx", "col_ptr", "row_idx", "val", "val_t"):
         assert np.array_equal(ge[k].cpu().numpy(), getattr(sk, k)), k
+
+
+@pytest.mark.parametrize("perturb", [False, True])
+def test_wfr_normaliser_same_support(api, perturb):
+    # With y equal to x bit for bit the normaliser sums each unordered pair
+    # once with both weights; one coordinate of y moved by one ulp takes the
+    # general path.  Both agree with the oracle's plain sum over all pairs.
+    p = W.wfr_synthetic(1500, d=5, seed=29, pattern="C3", nnz_ratio=0.6)
+    y = p.y.copy()
+    if perturb:
+        y[777, 3] = np.nextafter(y[777, 3], 2.0)
+    p = W.Problem(p.x, y, p.a, p.b, eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, name=p.name,
+                  meta=p.meta)
+    pr = O.uot_probabilities(p.a, p.b, p.x, p.y, p.s, p.lam, p.eps, 1.0, cost="wfr",
+                             eta=p.meta["eta"])
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    assert g["z_norm"] == pytest.approx(pr.z, rel=1e-13)
 
 
 @pytest.mark.parametrize("lam,eps", [(5.0, 0.1), (0.02, 0.05), (0.1, 0.1)])
