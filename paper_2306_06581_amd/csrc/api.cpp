@@ -2171,7 +2171,7 @@ IbpLayout ibp_plan(const ss_ibp_problem* P, const ss_options* O) {
     const int64_t n = P->n, K = P->count;
     const int64_t W = (n + 63) / 64;
     L.cap = entry_capacity(O->s, n, n);
-    L.nb_rows = ibp_row_blocks(n);
+    L.nb_rows = ibp_row_blocks(n, (int)K);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -2434,6 +2434,7 @@ int spar_ibp(const ss_ibp_problem* P, const ss_options* O, double* q_out, void* 
     }
     tm.mark(1, c.st);
     const int64_t n = P->n, K = P->count;
+    HIP_TRY(ibp_lds_init());
     IbpArgs A = ibp_args(c);
     HIP_TRY(launch_ibp_init(A.u, K * n, A.q[0], n, c.st));
     const int prec = O->precision == SS_F64 ? P_F64 : P_F32;
@@ -2481,6 +2482,7 @@ int ss_ibp_time_iterations(const ss_ibp_problem* P, const ss_options* O, void* w
         if (rc != SS_OK) return rc;
     }
     if (nnz) *nnz = c.nnz;
+    HIP_TRY(ibp_lds_init());
     IbpArgs A = ibp_args(c);
     A.tol = 0.0;
     A.max_iter = iters;

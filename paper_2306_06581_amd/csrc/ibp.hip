@@ -95,27 +95,64 @@ hipError_t launch_ibp_init(double* u, int64_t nu, double* q0, int64_t n, hipStre
 }
 
 // Dot product of one CSR/CSC line (entries [lo, hi) + base) with the
-// gathered vector x: the 16 lanes of a group stride the entries, four
-// independent loads per lane in flight, four partial sums per lane added in a
-// fixed order, then the xor tree over the lanes; every lane returns the total.
+// gathered vector x.  The line's entries are read as aligned quads (16-byte
+// loads of four indices and of four FP32 values, two 16-byte loads of FP64
+// values): the 16 lanes of a group take quads l, l + 16, ..., two at a time,
+// and lanes 0..2 take the at most three entries before the first aligned
+// quad and after the last one.  Per lane the products are added in a fixed
+// order, then the xor tree over the lanes; every lane returns the total.
+// (One 4-byte index and value per load, four loads in flight per lane, held
+// a step at n = 16384 to 57 us: too few bytes in flight per compute unit.)
+template <typename V>
+__device__ __forceinline__ void quad_load(const V* p, double* out);
+template <>
+__device__ __forceinline__ void quad_load<float>(const float* p, double* out) {
+    const float4 q = *(const float4*)p;
+    out[0] = q.x;
+    out[1] = q.y;
+    out[2] = q.z;
+    out[3] = q.w;
+}
+template <>
+__device__ __forceinline__ void quad_load<double>(const double* p, double* out) {
+    const double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
+    out[0] = a.x;
+    out[1] = a.y;
+    out[2] = b.x;
+    out[3] = b.y;
+}
+
 template <typename V>
 __device__ __forceinline__ double line_dot(const V* __restrict__ val, const int32_t* __restrict__ idx,
                                            int64_t base, int64_t lo, int64_t hi,
                                            const double* __restrict__ x, int lane16) {
-    const V* __restrict__ pv = val + base;
-    const int32_t* __restrict__ pi = idx + base;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int64_t e = lo + lane16;
-    for (; e + 48 < hi; e += 64) {
-        const int32_t i0 = pi[e], i1 = pi[e + 16], i2 = pi[e + 32], i3 = pi[e + 48];
-        const V v0 = pv[e], v1 = pv[e + 16], v2 = pv[e + 32], v3 = pv[e + 48];
-        a0 += (double)v0 * x[i0];
-        a1 += (double)v1 * x[i1];
-        a2 += (double)v2 * x[i2];
-        a3 += (double)v3 * x[i3];
+    // absolute entry indices; the arrays start 256-byte aligned, so an entry
+    // index divisible by 4 starts an aligned quad
+    const int64_t E0 = base + lo, E1 = base + hi;
+    int64_t A = (E0 + 3) & ~(int64_t)3;
+    if (A > E1) A = E1;
+    int64_t B = E1 & ~(int64_t)3;
+    if (B < A) B = A;
+    double a0 = 0.0, a1 = 0.0, ht = 0.0;
+    if (E0 + lane16 < A) ht += (double)val[E0 + lane16] * x[idx[E0 + lane16]];
+    if (B + lane16 < E1) ht += (double)val[B + lane16] * x[idx[B + lane16]];
+    const int64_t nq = (B - A) / 4;
+    for (int64_t q = lane16; q < nq; q += 32) {
+        const int64_t e = A + 4 * q;
+        const bool two = q + 16 < nq;
+        const int4 ia = *(const int4*)(idx + e);
+        const int4 ib = two ? *(const int4*)(idx + e + 64) : make_int4(0, 0, 0, 0);
+        double va[4], vb[4];
+        quad_load<V>(val + e, va);
+        if (two) {
+            quad_load<V>(val + e + 64, vb);
+        } else {
+            vb[0] = vb[1] = vb[2] = vb[3] = 0.0;
+        }
+        a0 += ((va[0] * x[ia.x] + va[1] * x[ia.y]) + (va[2] * x[ia.z] + va[3] * x[ia.w]));
+        a1 += ((vb[0] * x[ib.x] + vb[1] * x[ib.y]) + (vb[2] * x[ib.z] + vb[3] * x[ib.w]));
     }
-    for (; e < hi; e += 16) a0 += (double)pv[e] * x[pi[e]];
-    return group_sum<16>((a0 + a1) + (a2 + a3));
+    return group_sum<16>((a0 + a1) + ht);
 }
 
 // Block 0 of a column launch closes the previous step: err(t-1) from the row
@@ -234,9 +271,190 @@ __global__ __launch_bounds__(256) void k_ibp_rows(IbpArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0) S->cnt_u = t;
 }
 
-int ibp_row_blocks(int64_t n) { return (int)grid_lines(n, kMaxLoopBlocks); }
+// ------------------------------------------------------------------ LDS-staged step
+// Where a measure's vector (n FP64 values) fits in LDS, a block stages the
+// vector its lines gather, so the random reads come from LDS instead of each
+// pulling a cache line from L2: a column block takes a contiguous range of one
+// measure's columns and stages u_k; a row block takes a contiguous range of
+// rows and stages v_k for each measure in turn, keeping the rows' products
+// g_k in LDS until q and u are formed.  Every line's sum, and every row's
+// combination, runs in the same order as above, so the iterates are the same
+// bit for bit; only the residual's block partials are grouped differently.
+constexpr int kIbpLdsThreads = 1024;
+constexpr int kIbpLdsLines = kIbpLdsThreads / 16;  // lines a round
+constexpr int64_t kIbpLdsBlocks = 256;              // about one block per compute unit
+constexpr size_t kIbpLdsMax = 159 * 1024;  // dynamic LDS; the rest holds the static part
+
+static int64_t ibp_row_grid(int64_t n) {
+    const int64_t r = (n + kIbpLdsLines - 1) / kIbpLdsLines;
+    return r < kIbpLdsBlocks ? r : kIbpLdsBlocks;
+}
+static int64_t ibp_rows_per_block(int64_t n) {
+    const int64_t g = ibp_row_grid(n);
+    return (n + g - 1) / g;
+}
+static size_t ibp_row_lds(int64_t n, int count) {
+    return ((size_t)n + (size_t)count * (size_t)ibp_rows_per_block(n)) * 8;
+}
+static bool ibp_lds_fits(int64_t n, int count) { return ibp_row_lds(n, count) <= kIbpLdsMax; }
+static int64_t ibp_col_blocks_per_measure(int64_t n, int count) {
+    int64_t b = (kIbpLdsBlocks + count - 1) / count;
+    return b < n ? b : n;
+}
+
+// Copies src[0, n) into the LDS vector xs: each thread issues its (up to)
+// kIbpStage loads before storing any, so a 16384-entry vector takes one
+// round of load latency instead of one per element.
+constexpr int kIbpStage = 16;
+
+__device__ __forceinline__ void ibp_stage(double* xs, const double* __restrict__ src, int64_t n) {
+    for (int64_t e0 = threadIdx.x; e0 < n; e0 += (int64_t)blockDim.x * kIbpStage) {
+        double t[kIbpStage];
+#pragma unroll
+        for (int q = 0; q < kIbpStage; ++q) {
+            const int64_t e = e0 + (int64_t)q * blockDim.x;
+            t[q] = e < n ? src[e] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kIbpStage; ++q) {
+            const int64_t e = e0 + (int64_t)q * blockDim.x;
+            if (e < n) xs[e] = t[q];
+        }
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kIbpLdsThreads) void k_ibp_cols_lds(IbpArgs A, int64_t bpm) {
+    extern __shared__ double xs[];  // u_k
+    __shared__ double sh[16];
+    __shared__ int ctl[2];
+    if (threadIdx.x == 0) {
+        ctl[0] = A.st->stop_iter != 0 || A.st->nonfinite != 0;
+        ctl[1] = A.st->cnt_u + 1;
+    }
+    __syncthreads();
+    if (ctl[0]) return;
+    const int t = ctl[1];
+    if (blockIdx.x == 0) ibp_close(A, t, sh);
+    if (t > A.max_iter) return;
+    const int64_t n = A.n;
+    const int64_t k = blockIdx.x / bpm, jb = blockIdx.x % bpm;
+    const int64_t per = (n + bpm - 1) / bpm;
+    const int64_t j0 = jb * per, j1 = j0 + per < n ? j0 + per : n;
+    ibp_stage(xs, A.u + k * n, n);
+    __syncthreads();
+    const V* __restrict__ val = (const V*)A.val_t;
+    double* __restrict__ vout = A.v[t & 1];
+    const int grp = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+    const int64_t* cp = A.col_ptr + k * (n + 1);
+    for (int64_t j = j0 + grp; j < j1; j += kIbpLdsLines) {
+        const double den = line_dot<V>(val, A.row_idx, k * A.cap, cp[j], cp[j + 1], xs, l16);
+        if (l16 == 0) vout[k * n + j] = den > 0.0 ? A.b[k * n + j] / den : 0.0;
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kIbpLdsThreads) void k_ibp_rows_lds(IbpArgs A, int64_t rpb) {
+    extern __shared__ double dyn[];  // v_k, then g_k of the block's rows (count x rpb)
+    __shared__ double sh[16];
+    __shared__ int ctl[2];
+    IterState* S = A.st;
+    if (threadIdx.x == 0) {
+        ctl[0] = S->stop_iter != 0 || S->nonfinite != 0;
+        ctl[1] = S->cnt_v;
+    }
+    __syncthreads();
+    if (ctl[0]) return;
+    const int t = ctl[1];
+    if (t > A.max_iter) return;
+    const int64_t n = A.n;
+    const int count = A.count;
+    double* xs = dyn;
+    double* gk = dyn + n;
+    const V* __restrict__ val = (const V*)A.val;
+    const double* __restrict__ v = A.v[t & 1];
+    const double* __restrict__ qold = A.q[(t - 1) & 1];
+    double* __restrict__ qnew = A.q[t & 1];
+    const int grp = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+    const int64_t i0 = (int64_t)blockIdx.x * rpb, i1 = i0 + rpb < n ? i0 + rpb : n;
+    for (int k = 0; k < count; ++k) {
+        __syncthreads();  // the previous measure's vector is read
+        ibp_stage(xs, v + (int64_t)k * n, n);
+        __syncthreads();
+        const int64_t* rp = A.row_ptr + (int64_t)k * (n + 1);
+        for (int64_t i = i0 + grp; i < i1; i += kIbpLdsLines) {
+            const double g = line_dot<V>(val, A.col_idx, (int64_t)k * A.cap, rp[i], rp[i + 1], xs,
+                                         l16);
+            if (l16 == 0) gk[(int64_t)k * rpb + (i - i0)] = g;
+        }
+    }
+    __syncthreads();
+    double part = 0.0;
+    bool bad = false;
+    for (int64_t i = i0 + grp; i < i1; i += kIbpLdsLines) {
+        const int64_t r = i - i0;
+        double lq = 0.0;
+        bool zero = false;
+        for (int k = 0; k < count; ++k) {
+            const double g = gk[(int64_t)k * rpb + r];
+            const double wk = A.w[k];
+            if (wk > 0.0) {
+                if (g > 0.0)
+                    lq += wk * log(g);
+                else
+                    zero = true;
+            }
+        }
+        const double qi = zero ? 0.0 : exp(lq);
+        bad = bad || !isfinite(qi);
+        for (int k = l16; k < count; k += 16) {
+            const double g = gk[(int64_t)k * rpb + r];
+            A.u[(int64_t)k * n + i] = g > 0.0 ? qi / g : 0.0;
+        }
+        if (l16 == 0) {
+            qnew[i] = qi;
+            part += fabs(qi - qold[i]);
+        }
+    }
+    if (bad) S->nonfinite = 1;
+    part = block_sum(part, sh);
+    if (threadIdx.x == 0) A.partials[blockIdx.x] = part;
+    if (blockIdx.x == 0 && threadIdx.x == 0) S->cnt_u = t;
+}
+
+hipError_t ibp_lds_init() {
+    static hipError_t status = [] {
+        const void* fns[] = {(const void*)&k_ibp_cols_lds<double>, (const void*)&k_ibp_cols_lds<float>,
+                             (const void*)&k_ibp_rows_lds<double>, (const void*)&k_ibp_rows_lds<float>};
+        for (const void* f : fns) {
+            const hipError_t e =
+                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kIbpLdsMax);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }();
+    return status;
+}
+
+int ibp_row_blocks(int64_t n, int count) {
+    return ibp_lds_fits(n, count) ? (int)ibp_row_grid(n) : (int)grid_lines(n, kMaxLoopBlocks);
+}
 
 hipError_t launch_ibp_iteration(int precision, const IbpArgs& A, hipStream_t st) {
+    if (ibp_lds_fits(A.n, A.count)) {
+        const int64_t bpm = ibp_col_blocks_per_measure(A.n, A.count);
+        const int64_t rpb = ibp_rows_per_block(A.n);
+        const dim3 gc((unsigned)(bpm * A.count)), gr((unsigned)A.nb_rows);
+        const size_t lc = (size_t)A.n * 8, lr = ibp_row_lds(A.n, A.count);
+        if (precision == P_F64) {
+            hipLaunchKernelGGL(k_ibp_cols_lds<double>, gc, dim3(kIbpLdsThreads), lc, st, A, bpm);
+            hipLaunchKernelGGL(k_ibp_rows_lds<double>, gr, dim3(kIbpLdsThreads), lr, st, A, rpb);
+        } else {
+            hipLaunchKernelGGL(k_ibp_cols_lds<float>, gc, dim3(kIbpLdsThreads), lc, st, A, bpm);
+            hipLaunchKernelGGL(k_ibp_rows_lds<float>, gr, dim3(kIbpLdsThreads), lr, st, A, rpb);
+        }
+        return hipGetLastError();
+    }
     const unsigned gc = grid_lines((int64_t)A.count * A.n, 8 * kMaxLoopBlocks);
     const unsigned gr = (unsigned)A.nb_rows;
     if (precision == P_F64) {

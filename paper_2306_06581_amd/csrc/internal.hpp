@@ -117,7 +117,12 @@ hipError_t launch_ibp_prep(const double* b, int64_t n, double s, double shrink_w
 hipError_t launch_ibp_empty(const int32_t* cnt, int64_t n, unsigned long long* out,
                             hipStream_t st);
 hipError_t launch_ibp_init(double* u, int64_t nu, double* q0, int64_t n, hipStream_t st);
-int ibp_row_blocks(int64_t n);
+// Grid of the row launch (the number of residual partials) for n points and
+// count measures.
+int ibp_row_blocks(int64_t n, int count);
+// Raises the dynamic LDS limit of the LDS-staged step kernels (once, before
+// any launch or capture).
+hipError_t ibp_lds_init();
 hipError_t launch_ibp_iteration(int precision, const IbpArgs& A, hipStream_t st);
 
 // ---- sample.hip
