@@ -101,8 +101,6 @@ hipError_t launch_ibp_init(double* u, int64_t nu, double* q0, int64_t n, hipStre
 // and lanes 0..2 take the at most three entries before the first aligned
 // quad and after the last one.  Per lane the products are added in a fixed
 // order, then the xor tree over the lanes; every lane returns the total.
-// (One 4-byte index and value per load, four loads in flight per lane, held
-// a step at n = 16384 to 57 us: too few bytes in flight per compute unit.)
 template <typename V>
 __device__ __forceinline__ void quad_load(const V* p, double* out);
 template <>
