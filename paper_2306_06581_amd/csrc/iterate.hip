@@ -387,6 +387,7 @@ __global__ __launch_bounds__(256) void k_pack(const int64_t* __restrict__ ptr,
     if (k >= p.info->K) return;
     const V* __restrict__ val = (const V*)val_;
     V* __restrict__ pval = (V*)p.pval;
+    uint16_t* __restrict__ poff = p.poff;
     const int64_t r0 = p.rstart[k];
     const int nl = (int)(p.rstart[k + 1] - r0);
     const int ns = p.ns;
@@ -434,27 +435,43 @@ __global__ __launch_bounds__(256) void k_pack(const int64_t* __restrict__ ptr,
         p.lmeta[g0 + L] = (s << 8) | bq;
         const int q = L / BS, l = L - q * BS;
         const int w = total - q * BS < BS ? total - q * BS : BS;
+        // the lane's two segments' entry ranges, then every load of its J
+        // quads before any store (the stores cannot alias the loads)
+        int64_t e0[J], ee[J];
+#pragma unroll
         for (int j = 0; j < J; ++j) {
             const int c = j < bq ? a : b;
             const int seg = cseg[c];
             const int64_t line = r0 + (seg - (seg / nl) * nl);
             const int32_t* sp = p.split + line * (ns + 1);
-            const int64_t eb = ptr[line] + sp[s];
-            const int64_t ee = ptr[line] + sp[s + 1];
-            const int64_t e0 = eb + (int64_t)(Q0 + j - cqs[c]) * 4;
-            const int64_t pa = packed_at(g0, q, BS, E, w, j, l);
+            const int64_t base = ptr[line];
+            ee[j] = base + sp[s + 1];
+            e0[j] = base + sp[s] + (int64_t)(Q0 + j - cqs[c]) * 4;
+        }
+        V x[E];
+        uint16_t o[E];
+#pragma unroll
+        for (int j = 0; j < J; ++j)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int64_t e = e0 + u;
-                const bool ok = e < ee;
-                V x = (V)0;  // empty slot: neutral value, offset 0
+                const int64_t e = e0[j] + u;
+                const bool ok = e < ee[j];
+                // empty slot: neutral value, offset 0
                 if constexpr (PREC == P_LOG)
-                    x = ok ? (V)((double)val[e] * kLog2e) : (V)-INFINITY;
+                    x[4 * j + u] = ok ? (V)((double)val[e] * kLog2e) : (V)-INFINITY;
                 else
-                    x = ok ? val[e] : (V)0;
-                pval[pa + u] = x;
-                p.poff[pa + u] = (uint16_t)(ok ? (idx[e] - s * SL) * (int64_t)sizeof(G) : 0);
+                    x[4 * j + u] = ok ? val[e] : (V)0;
+                o[4 * j + u] = (uint16_t)(ok ? (idx[e] - s * SL) * (int64_t)sizeof(G) : 0);
             }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int64_t pa = packed_at(g0, q, BS, E, w, j, l);  // a quad: 4-aligned
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pval[pa + u] = x[4 * j + u];
+            uint2 ow;
+            ow.x = (uint32_t)o[4 * j] | ((uint32_t)o[4 * j + 1] << 16);
+            ow.y = (uint32_t)o[4 * j + 2] | ((uint32_t)o[4 * j + 3] << 16);
+            *(uint2*)(poff + pa) = ow;
         }
     }
 }
