@@ -124,6 +124,70 @@ __device__ __forceinline__ double cost_spec(double c, int kind, double scale, do
     return z >= kHalfPi ? INFINITY : -2.0 * log_spec(cos_spec(z));
 }
 
+// Logarithm and exponential by small tables, for sums that need about 1e-15
+// relative, not bit-exactness (the WFR normaliser); the
+// tables cost about half the instructions of the table-free specified
+// functions.  Per block, in LDS:
+//  * log c, c = 2^e m, m in [1, 2): with j the top 7 bits of m's fraction,
+//    c_j = 1 + (j + 1/2)/128, ti[j] = 1/c_j rounded and tl[j] = -log ti[j],
+//    log c = e ln 2 + tl[j] + log(1 + r), r = m ti[j] - 1 (one fused
+//    operation), |r| < 2^-8, log(1 + r) to r^7 (remainder below 1e-20);
+//  * e^x = 2^(N/64) e^r, N = rint(64 x / ln 2), r = x - N ln2/64 (the split
+//    ln 2 of the specified exponential), |r| <= ln2/128, e^r - 1 to r^6
+//    (remainder below 1e-19), 2^(N/64) = 2^(N >> 6) te[N & 63],
+//    te[j] = 2^(j/64).
+// The tables come from the specified functions (1-3 ulp), so a term is
+// within a few 1e-16 relative (a multiple of the logarithm multiplies its error).
+struct TabLog {
+    double te[64], ti[128], tl[128];
+};
+
+__device__ __forceinline__ void tab_log_init(TabLog& T) {
+    for (int j = threadIdx.x; j < 64 + 128; j += blockDim.x) {
+        if (j < 64) {
+            T.te[j] = exp_spec((double)j * (spec::kLn2Hi / 64.0) + (double)j * (spec::kLn2Lo / 64.0));
+        } else {
+            const int q = j - 64;
+            const double inv = 1.0 / (1.0 + ((double)q + 0.5) / 128.0);
+            T.ti[q] = inv;
+            T.tl[q] = -log_spec(inv);
+        }
+    }
+}
+
+// log c for a normal c > 0.
+__device__ __forceinline__ double tab_log(double c, const TabLog& T) {
+    const long long b = __double_as_longlong(c);
+    const int e = (int)((b >> 52) & 0x7FF) - 1023;
+    const int j = (int)((b >> 45) & 127);
+    const double m = __longlong_as_double((b & 0x000FFFFFFFFFFFFFLL) | 0x3FF0000000000000LL);
+    const double r = fma(m, T.ti[j], -1.0);
+    double p = 1.0 / 7;
+    p = fma(p, r, -1.0 / 6);
+    p = fma(p, r, 1.0 / 5);
+    p = fma(p, r, -0.25);
+    p = fma(p, r, 1.0 / 3);
+    p = fma(p, r, -0.5);
+    p = fma(p, r, 1.0);
+    const double ed = (double)e;
+    return ed * spec::kLn2Hi + (T.tl[j] + (ed * spec::kLn2Lo + r * p));
+}
+
+// e^x for -740 <= x <= 0.
+__device__ __forceinline__ double tab_exp(double x, const TabLog& T) {
+    const double N = rint(x * (64.0 * spec::kLog2e));
+    const double r = (x - N * (spec::kLn2Hi / 64.0)) - N * (spec::kLn2Lo / 64.0);
+    double p = 1.0 / 720;
+    p = fma(p, r, 1.0 / 120);
+    p = fma(p, r, 1.0 / 24);
+    p = fma(p, r, 1.0 / 6);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    const int n = (int)N;
+    const double t = T.te[n & 63];
+    return ldexp(fma(t, r * p, t), n >> 6);  // n >> 6 = floor(n / 64)
+}
+
 // ---------------------------------------------------------------------------
 // Wave and block reductions.  xor-butterflies give every lane the same value
 // (IEEE addition is commutative), so the results are deterministic.

@@ -443,70 +443,9 @@ constexpr double kWfrC[12] = {1.0,
                               1.0 / 2432902008176640000.0,
                               1.0 / 1124000727777607680000.0};
 
-// The normaliser's logarithm and exponential by small tables (Z needs its
-// sum to 1e-13, not bit-exactness; the tables cost about half the
-// instructions of the table-free specified functions).  Per block, in LDS:
-//  * log c, c = 2^e m, m in [1, 2): with j the top 7 bits of m's fraction,
-//    c_j = 1 + (j + 1/2)/128, ti[j] = 1/c_j rounded and tl[j] = -log ti[j],
-//    log c = e ln 2 + tl[j] + log(1 + r), r = m ti[j] - 1 (one fused
-//    operation), |r| < 2^-8, log(1 + r) to r^7 (remainder below 1e-20);
-//  * e^x = 2^(N/64) e^r, N = rint(64 x / ln 2), r = x - N ln2/64 (the split
-//    ln 2 of the specified exponential), |r| <= ln2/128, e^r - 1 to r^6
-//    (remainder below 1e-19), 2^(N/64) = 2^(N >> 6) te[N & 63],
-//    te[j] = 2^(j/64).
-// The tables come from the specified functions (1-3 ulp), so a term is
-// within a few 1e-16 relative; k2 = 2/tau multiplies the logarithm's error.
-struct WfrTables {
-    double te[64], ti[128], tl[128];
-};
-
-__device__ __forceinline__ void wfr_tables_init(WfrTables& T) {
-    for (int j = threadIdx.x; j < 64 + 128; j += blockDim.x) {
-        if (j < 64) {
-            T.te[j] = exp_spec((double)j * (spec::kLn2Hi / 64.0) + (double)j * (spec::kLn2Lo / 64.0));
-        } else {
-            const int q = j - 64;
-            const double inv = 1.0 / (1.0 + ((double)q + 0.5) / 128.0);
-            T.ti[q] = inv;
-            T.tl[q] = -log_spec(inv);
-        }
-    }
-}
-
-// log c for a normal c > 0.
-__device__ __forceinline__ double wfr_log(double c, const WfrTables& T) {
-    const long long b = __double_as_longlong(c);
-    const int e = (int)((b >> 52) & 0x7FF) - 1023;
-    const int j = (int)((b >> 45) & 127);
-    const double m = __longlong_as_double((b & 0x000FFFFFFFFFFFFFLL) | 0x3FF0000000000000LL);
-    const double r = fma(m, T.ti[j], -1.0);
-    double p = 1.0 / 7;
-    p = fma(p, r, -1.0 / 6);
-    p = fma(p, r, 1.0 / 5);
-    p = fma(p, r, -0.25);
-    p = fma(p, r, 1.0 / 3);
-    p = fma(p, r, -0.5);
-    p = fma(p, r, 1.0);
-    const double ed = (double)e;
-    return ed * spec::kLn2Hi + (T.tl[j] + (ed * spec::kLn2Lo + r * p));
-}
-
-// e^x for -740 <= x <= 0.
-__device__ __forceinline__ double wfr_exp(double x, const WfrTables& T) {
-    const double N = rint(x * (64.0 * spec::kLog2e));
-    const double r = (x - N * (spec::kLn2Hi / 64.0)) - N * (spec::kLn2Lo / 64.0);
-    double p = 1.0 / 720;
-    p = fma(p, r, 1.0 / 120);
-    p = fma(p, r, 1.0 / 24);
-    p = fma(p, r, 1.0 / 6);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    const int n = (int)N;
-    const double t = T.te[n & 63];
-    return ldexp(fma(t, r * p, t), n >> 6);  // n >> 6 = floor(n / 64)
-}
-
-__device__ __forceinline__ double wfr_q(double t, double w, double k2, const WfrTables& T) {
+// The normaliser's logarithm and exponential come from the small tables of
+// common.hpp (TabLog; Z needs its sum to 1e-13, not bit-exactness).
+__device__ __forceinline__ double wfr_q(double t, double w, double k2, const TabLog& T) {
     const double u = -t;  // cos z = sum_k u^k / (2k)!
     double p = kWfrC[11];
 #pragma unroll
@@ -514,8 +453,8 @@ __device__ __forceinline__ double wfr_q(double t, double w, double k2, const Wfr
     // w is the pair's weight ea eb; cos z below 2^-1000 gives a term far
     // below the sum's rounding
     if (!(p > 0x1p-1000)) return 0.0;
-    const double x = k2 * wfr_log(p, T);
-    return x < -740.0 ? 0.0 : w * wfr_exp(x, T);
+    const double x = k2 * tab_log(p, T);
+    return x < -740.0 ? 0.0 : w * tab_exp(x, T);
 }
 
 // stats[ST_SAME_SUPPORT] = 0 if any coordinate of y differs from x's (bit
@@ -549,8 +488,8 @@ __global__ __launch_bounds__(256) void k_uot_z_wfr(ProbParams pp, int64_t n, int
     __shared__ double sh[4];
     __shared__ double qt[4][128], qs[4][128];
     __shared__ double ys[kZwChunk][DD + 2];  // coordinates, then the column's eb and ea
-    __shared__ WfrTables tabs;
-    wfr_tables_init(tabs);
+    __shared__ TabLog tabs;
+    tab_log_init(tabs);
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     constexpr bool sym = SYM;
