@@ -879,7 +879,9 @@ int spar_sink_impl(const ss_problem* P, const ss_options* O, void* ws, size_t ws
     };
     if (time_iters > 0) {
         for (int k = 0; k < 2; ++k) {
-            ua[k].tol = va[k].tol = 0.0;
+            // a negative tolerance never stops the loop: an error that
+            // reaches exactly 0 would otherwise end every later launch at entry
+            ua[k].tol = va[k].tol = -1.0;
             ua[k].max_iter = va[k].max_iter = time_iters;
             ua[k].err_hist = va[k].err_hist = nullptr;
         }
@@ -1284,7 +1286,7 @@ const int kBlockCand[3] = {256, 512, 1024};
 
 int batch_autotune(BCtx& c, ss_schedule* best, float* cand_ms, int32_t* ncand) {
     BIterArgs ia = c.ia;
-    ia.tol = 0.0;
+    ia.tol = -1.0;  // never stops early: every candidate runs its 16 iterations
     ia.max_iter = 16;
     ia.u_out = ia.v_out = nullptr;
     hipEvent_t e0, e1;
@@ -2484,7 +2486,7 @@ int ss_ibp_time_iterations(const ss_ibp_problem* P, const ss_options* O, void* w
     if (nnz) *nnz = c.nnz;
     HIP_TRY(ibp_lds_init());
     IbpArgs A = ibp_args(c);
-    A.tol = 0.0;
+    A.tol = -1.0;  // never stops early (an exactly zero change would end the later launches)
     A.max_iter = iters;
     A.err_hist = nullptr;
     const int prec = O->precision == SS_F64 ? P_F64 : P_F32;
