@@ -374,3 +374,44 @@ def test_divergence_arguments_rejected(case):
     assert N.lib.ss_divergence_workspace_size(ctypes.byref(prob), ctypes.byref(o2),
                                               ctypes.byref(out)) == 0
     assert out.value > 0
+
+
+def test_batch_results_sequence():
+    # the batched call returns its results as a lazy sequence over one copy
+    # of the ss_result array: every Result equals a field-by-field read, in
+    # batch order, with list-like indexing, slicing and iteration
+    import numpy as np
+    import torch
+    from paper_2306_06581_amd import native as N
+    from paper_2306_06581_amd.api import BatchResults, Result
+    count = 37
+    outs = (N.SsResult * count)()
+    for k in range(count):
+        outs[k].estimate = 0.25 * k - 3.0
+        outs[k].iters = 3 * k
+        outs[k].status = -3 if k % 5 == 0 else 0
+        outs[k].nnz = 2 ** 40 + k
+        outs[k].t_iter_ms = 0.5 + k
+        outs[k].warm_start = k % 3 - 1
+    res = BatchResults(outs, count)
+    outs[0].iters = 999  # the sequence holds its own copy
+    assert len(res) == count
+    for k in range(count):
+        r = res[k]
+        assert isinstance(r, Result) and r is res[k]
+        assert (r.estimate, r.iters, r.status, r.nnz, r.warm_start) == \
+            (0.25 * k - 3.0, 3 * k, -3 if k % 5 == 0 else 0, 2 ** 40 + k, k % 3 - 1)
+        assert r.t_iter_ms == np.float32(0.5 + k)
+        assert r.u is None and r.v is None and r.extra == {}
+    assert res[-1] is res[count - 1] and [r.iters for r in res[2:5]] == [6, 9, 12]
+    assert [r.iters for r in res] == list(range(0, 3 * count, 3))
+    assert (res.column("iters") == np.arange(0, 3 * count, 3)).all()
+    with pytest.raises(IndexError):
+        res[count]
+    # per-problem views of the concatenated scalings
+    u = torch.arange(10.0, dtype=torch.float64)
+    off = np.array([0, 4, 4, 10] + [10] * (count - 3))
+    sc = BatchResults(outs, count)
+    sc._scalings(u, u, off, off)
+    assert sc[0].u.tolist() == [0.0, 1.0, 2.0, 3.0] and sc[1].u.numel() == 0
+    assert sc[2].v.tolist() == [4.0, 5.0, 6.0, 7.0, 8.0, 9.0]
