@@ -824,6 +824,22 @@ hipError_t launch_uot_bounds(const double* lb, int64_t m, double s, double shrin
 // pairs whose cost factor rules them out before the exact decision (about
 // 70 in 71 of the cost-free candidates at the WFR workload's sparsity).
 // A list entry is 32 bits: row (4), slot of the wave (4), lane (6), high half.
+// The FP32 bit pattern of 2^23 + hi, hi the coarse half of `slot`: the half's
+// two bytes and the bytes 0x00, 0x4B of the constant in one byte permute
+// (selectors 0-3 take the word's bytes, 4-7 the constant's).
+__device__ __forceinline__ uint32_t half_f23(const Words4& w, int slot) {
+    const int t = slot >> 1;
+    const uint32_t x = t == 0 ? w.w[0] : t == 1 ? w.w[1] : t == 2 ? w.w[2] : w.w[3];
+    return __builtin_amdgcn_perm(0x4B000000u, x, (slot & 1) ? 0x07040302u : 0x07040100u);
+}
+// An FP32 upper bound of a factor v >= 0 in [2^-126, inf] (v = 0 and the
+// FP32 denormals included); -inf and NaN stay as they are.
+__device__ __forceinline__ float fac_up(double v) {
+    if (!(v > 0x1p-126)) return v >= 0.0 ? 0x1p-126f : (float)v;
+    float f = (float)v;  // nearest; above FLT_MAX by more than half an ulp: inf
+    if ((double)f < v) f = __int_as_float(__float_as_int(f) + 1);  // FLT_MAX -> inf
+    return f;
+}
 // An FP32 upper bound of log2 v for a double v (+ 2^-8 for the rounding of
 // the conversion and of v_log_f32); -inf for v <= 0 and NaN.
 __device__ __forceinline__ float log2_up(double v) {
@@ -863,12 +879,19 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
     // the uniform part of shrinkage (0 without it); for the UOT bound with
     // the bound's margin
     const double pc = UOT ? pp.shrink_c * (1.0 + 0x1p-30) : pp.shrink_c;
-    // filter scale 2^16 (1 + 2^-40); the constant 2^-900 keeps every entry
-    // with hi = 0 a candidate where the scaled product underflows
+    // filter scale 2^16 (1 + 2^-40)
     constexpr double kScale = 0x1p16 * (1.0 + 0x1p-40);
-    const double pcf = pc * kScale + 0x1p-900;
     // lane r < 16 holds row r's factor, scaled
     const double rowv = lane < nrows ? rsrc[row0 + lane] * kScale : 0.0;
+    // The filter in FP32: hi is a candidate when 2^23 + hi < fma(r, c, b)
+    // with r, c the scaled row and column factors rounded up into
+    // [2^-126, inf] and b = 2^23 + 2^16 pc + 1 rounded up.  A kept entry has
+    // hi < 2^16 P; the exact sum r c + b is at least 2^23 + 2^16 P + 1, and
+    // its rounding (ulp 1 below 2^24) loses at most 1/2, so every kept entry
+    // is a candidate, hi = 0 always, and no product is NaN (only the columns
+    // past m carry -inf, and are never candidates).
+    const float bias32 = fac_up(0x1p23 + pc * kScale + 1.0);
+    const float row32 = fac_up(rowv);
     // the cost as a value the compiler sees: without WFR one of the two
     // squared Euclidean kinds, so the WFR branches fold away
     ProbParams lp = pp;
@@ -910,6 +933,9 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
             const int64_t j = 512 * g + 64 * s + lane;
             cf[s] = j < m ? csrc[j] : -INFINITY;
         }
+        float cf32[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) cf32[s] = fac_up(cf[s]);
         // cost-factor bound data of the lane's eight columns (WFR)
         float yc[8][CD], nys[8], lcol[8];
         if constexpr (kCfb) {
@@ -928,9 +954,8 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
         }
         for (int r = 0; r < nrows; ++r) {
             const int64_t i = row0 + r;
-            const uint32_t lo = __builtin_amdgcn_readlane((int)__double2loint(rowv), r);
-            const uint32_t hi = __builtin_amdgcn_readlane((int)__double2hiint(rowv), r);
-            const double rowf = __hiloint2double((int)hi, (int)lo);
+            const float rowf =
+                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(row32), r));
             const Words4 h = philox10(q, (uint32_t)i, pp.problem_index, 0u, pp.k0, pp.k1);
             float xr[CD], nxs = 0.0f, lr = 0.0f;
             if constexpr (kCfb) {
@@ -942,9 +967,10 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
             }
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                const uint32_t hs = coarse_half(h, s);
+                uint32_t hs;
                 bool c;
                 if constexpr (kCfb) {
+                    hs = coarse_half(h, s);
                     float c32 = 0.0f;
 #pragma unroll
                     for (int k = 0; k < CD; ++k) {
@@ -957,7 +983,9 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
                     const float v = fmaf(bits, 0x1p-23f, fmaf(alpha, clo, -127.0f));
                     c = v < lr + lcol[s] || hs == 0u;
                 } else {
-                    c = (double)hs < fma(rowf, cf[s], pcf);
+                    const uint32_t hb = half_f23(h, s);
+                    c = __uint_as_float(hb) < fmaf(rowf, cf32[s], bias32);
+                    hs = hb & 0xFFFFu;
                 }
                 const uint64_t bal = __ballot(c);
                 if (bal) {

@@ -84,6 +84,41 @@ def test_sample_ot_bit_exact(api, name, make):
     assert np.array_equal(g["val_t"].cpu().numpy(), sk.val_t)
 
 
+def test_sample_ot_weights_over_300_decades(api):
+    """Four in five weights of each marginal are 10^-U(0,300): about 400 row
+    and column factors lie below the FP32 range, where the hash filter's FP32
+    bounds are clamped up to 2^-126.  The filter only ever admits a superset
+    of the kept entries, so the mask and CSR/CSC still match bit for bit."""
+    p = W.ot_gauss2d(700, seed=6, m=650)
+    rng = np.random.default_rng(6)
+    a = 10.0 ** -rng.uniform(0, 300, p.n)
+    a[::5] = rng.uniform(0.5, 1.0, a[::5].shape)
+    b = 10.0 ** -rng.uniform(0, 300, p.m)
+    b[::5] = rng.uniform(0.5, 1.0, b[::5].shape)
+    p.a, p.b = a / a.sum(), b / b.sum()
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    assert (sk.prob.alpha * 65536 < 2.0 ** -126).sum() > 100
+    assert (sk.prob.rb < 2.0 ** -126).sum() > 100
+    g = api.ss_sample(_prob(api, p), **_kw(p), precision="f64")
+    _check_sketch_structure(g, sk)
+    assert np.array_equal(g["val"].cpu().numpy(), sk.val)
+
+
+def test_sample_uot_weights_over_300_decades(api):
+    """The UOT bound factors of weights 10^-U(0,300) (one in five of order
+    one) fall below the FP32 range too; given the oracle's normaliser the
+    mask, CSR/CSC and values stay bit-exact."""
+    p = W.uot_mix3(500, seed=8, eps=0.05, lam=1.0)
+    rng = np.random.default_rng(8)
+    p.a = p.a * 10.0 ** -rng.uniform(0, 300, p.n)
+    p.b = p.b * 10.0 ** -rng.uniform(0, 300, p.m)
+    p.a[::5] = 1.0 / p.n
+    p.b[::5] = 1.0 / p.m
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    assert sk.nnz > 1000
+    _uot_bit_exact(api, p, sk, precision="f64")
+
+
 def test_sample_precisions_share_the_mask(api):
     p = W.ot_gauss2d(512, seed=5)
     sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
