@@ -900,9 +900,16 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
     uint32_t* const list = cand[wv];
     int cnt = 0;  // wave-uniform
     // WFR (no shrinkage: the host rejects it with this cost): lane r < 16
-    // holds row r's FP32 coordinates, its rounding term -2^-20 |x|^2 and an
-    // upper bound of log2 of its factor (the kernels of a fixed dimension;
-    // D = 0 reads pp.d at run time and keeps the cost-free filter)
+    // holds row r's FP32 coordinates, its squared norm less 2^-16 of it and
+    // an upper bound of log2 of its factor (the kernels of a fixed
+    // dimension; D = 0 reads pp.d at run time and keeps the cost-free
+    // filter).  A pair's squared distance is bounded below by
+    // |x|^2 (1 - 2^-16) + |y|^2 (1 - 2^-16) - 2 x.y in FP32: with u = 2^-24
+    // and S = |x|^2 + |y|^2, rounding the coordinates to FP32 moves c by at
+    // most 4 u S, the fused sums of at most 10 terms by 20 u S and the last
+    // roundings by 4 u S, far inside the 2^-16 S taken off.  A norm of 2^100
+    // or more (or NaN) takes -inf, so its pairs are always candidates and
+    // nothing overflows.
     constexpr bool kCfb = WFR && D > 0;
     constexpr int CD = kCfb ? D : 1;
     float xr_l[CD], nxs_l = 0.0f, lr_l = -INFINITY;
@@ -914,7 +921,7 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
             xr_l[k] = lane < nrows ? (float)pp.x[(row0 + lane) * D + k] : 0.0f;
             nx = fmaf(xr_l[k], xr_l[k], nx);
         }
-        nxs_l = -0x1p-20f * nx;
+        nxs_l = nx < 0x1p100f ? nx * (1.0f - 0x1p-16f) : -INFINITY;
         lr_l = log2_up(rowv);
         // t per unit squared distance, rounded down
         alpha = (float)(pp.wfr_w * pp.wfr_w * pp.inv_tau * kLog2e) * (1.0f - 0x1p-20f);
@@ -948,7 +955,7 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
                     yc[s][k] = j < m ? (float)pp.y[j * D + k] : 0.0f;
                     ny = fmaf(yc[s][k], yc[s][k], ny);
                 }
-                nys[s] = -0x1p-20f * ny;
+                nys[s] = ny < 0x1p100f ? ny * (1.0f - 0x1p-16f) : -INFINITY;
                 lcol[s] = log2_up(cf[s]);
             }
         }
@@ -971,17 +978,15 @@ __device__ __forceinline__ void mask_tile(const ProbParams& pp, int64_t n, int64
                 bool c;
                 if constexpr (kCfb) {
                     hs = coarse_half(h, s);
-                    float c32 = 0.0f;
+                    float dot = xr[0] * yc[s][0];
 #pragma unroll
-                    for (int k = 0; k < CD; ++k) {
-                        const float dk = xr[k] - yc[s][k];
-                        c32 = fmaf(dk, dk, c32);
-                    }
-                    const float clo = fmaf(c32, 1.0f - 0x1p-20f, nxs + nys[s]);
+                    for (int k = 1; k < CD; ++k) dot = fmaf(xr[k], yc[s][k], dot);
+                    const float clo = fmaf(-2.0f, dot, nxs + nys[s]);
                     // e + m of hs (as an unsigned float, exact below 2^24) plus t
                     const float bits = (float)__float_as_uint((float)hs);
                     const float v = fmaf(bits, 0x1p-23f, fmaf(alpha, clo, -127.0f));
-                    c = v < lr + lcol[s] || hs == 0u;
+                    // NaN (an infinite norm) is a candidate too
+                    c = !(v >= lr + lcol[s]) || hs == 0u;
                 } else {
                     const uint32_t hb = half_f23(h, s);
                     c = __uint_as_float(hb) < fmaf(rowf, cf32[s], bias32);
