@@ -96,6 +96,25 @@ def test_sample_wfr_filter(api, n, m, d, s_factor):
         assert np.array_equal(ge[k].cpu().numpy(), getattr(sk, k)), k
 
 
+def test_sample_wfr_filter_far_points(api):
+    # One point in 25 of each side moved out by 1e25: its FP32 squared norm
+    # overflows, so the filter makes every pair of it a candidate and leaves
+    # the exact decision to block it (d >= pi eta); the mask, CSR, CSC and
+    # values stay bit-exact with the oracle's.
+    p = W.wfr_synthetic(800, d=5, seed=31, pattern="C1", nnz_ratio=0.5)
+    x, y = p.x.copy(), p.y.copy()
+    x[::25] *= 1e25
+    y[3::25] *= 1e25
+    p = W.Problem(x, y, p.a, p.b, eps=p.eps, s=p.s, lam=p.lam, seed=p.seed, name=p.name,
+                  meta=p.meta)
+    sk = O.build_sketch(p.x, p.y, p.a, p.b, _oopt(p))
+    assert sk.nnz > 1000
+    ge = api.ss_sample(_prob(api, p), **_kw(p), z_in=sk.prob.z, precision="f64")
+    assert np.array_equal(ge["mask"].cpu().numpy().view(np.uint64), sk.mask)
+    for k in ("row_ptr", "col_idx", "col_ptr", "row_idx", "val", "val_t"):
+        assert np.array_equal(ge[k].cpu().numpy(), getattr(sk, k)), k
+
+
 @pytest.mark.parametrize("perturb", [False, True])
 def test_wfr_normaliser_same_support(api, perturb):
     # With y equal to x bit for bit the normaliser sums each unordered pair
